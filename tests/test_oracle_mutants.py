@@ -1,0 +1,64 @@
+"""Planted mistakes in a copy of the oracle must fail at least one pin.
+
+Each mutant is a plausible slip (a swapped tap, a dropped term, a wrong
+sign, focal length or comparison) applied textually to oracle/bn_oracle.c,
+compiled to a temporary library and run through every check in pins.py.
+This shows the pins constrain each part of the oracle, not just some.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import pins
+
+MUTANTS = {
+    "eq10_fx_for_fy": [("n[0] = -alpha / (4.0 * fy)", "n[0] = -alpha / (4.0 * fx)")],
+    "eq12_drop_alpha2_term": [("+ alpha * alpha / (4.0 * fx * fy) * (d2 + d4) * (d3 + d5);", "+ 0.0;")],
+    "eq12_sign_u1": [("n[2] = -u1 * n[0] - v1 * n[1]", "n[2] = u1 * n[0] - v1 * n[1]")],
+    "u1_with_fy": [("double u1 = ((double)x - cx) / fx;", "double u1 = ((double)x - cx) / fy;")],
+    "taps_3_5_swapped": [("(y + alpha) * stride + x]", "(y + ALPHA_MINUS) * stride + x]"),
+                         ("(y - alpha) * stride + x]", "(y + alpha) * stride + x]"),
+                         ("(y + ALPHA_MINUS) * stride + x]", "(y - alpha) * stride + x]")],
+    "eq7_wrong_pair": [("cross3(s15, s12, c)", "cross3(s12, s15, c)")],
+    "not_camera_facing": [("out[0] = -n[0] / len;", "out[0] = n[0] / len;"),
+                          ("out[1] = -n[1] / len;", "out[1] = n[1] / len;"),
+                          ("out[2] = -n[2] / len;", "out[2] = n[2] / len;")],
+    "border_off_by_one": [("(x - alpha >= 0)", "(x - alpha >= -1)")],
+    "d1_not_checked": [("tap_ok_f32(d1) && ", "")],
+    "mask_not_strict": [("(q > h) ?", "(q >= h) ?")],
+    "rel_tau_not_squared": [("float tt = tau * tau;", "float tt = tau;")],
+    "abs_threshold_not_squared": [("    k = k * k;\n", "")],
+    "xc_uses_cy": [("float xc = (float)x - cx;", "float xc = (float)x - cy;")],
+    "my_uses_fx": [("float my = fy * b;", "float my = fx * b;")],
+    "no_degenerate_rule": [("if (!isfinite(q) || q < FLT_MIN)", "if (!isfinite(q))")],
+    "boundary_keeps_normal": [("if (code == ORC_VALID) {", "if (code != ORC_INVALID) {")],
+    "q_missing_mz": [("float q = (mx2 + my2) + mz2;", "float q = (mx2 + my2);")],
+}
+
+
+def _apply(src, edits):
+    for old, new in edits:
+        assert old in src, f"mutation anchor not found: {old!r}"
+        src = src.replace(old, new)
+    return src
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    src = open(oracle.SRC).read()
+    mutated = _apply(src, MUTANTS[name])
+    assert mutated != src
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(mutated)
+    subprocess.check_call(["gcc", *oracle.GCC_FLAGS, str(c), "-o", str(so), "-lm"])
+    o = oracle.Oracle(str(so))
+    failed = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin(o)
+        except (AssertionError, ValueError, FloatingPointError):
+            failed.append(pin.__name__)
+    assert failed, f"mutant {name} passed every pin"
