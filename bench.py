@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Throughput of the boundary-aware normal estimator on one MI355X.
+
+Default workload: plain single-frame launches on 1920x1080 binary32 depth
+(fx=fy=1050, principal point at the centre, alpha=2, REL mask tau=4).  To
+measure HBM rather than the 256 MB last-level cache, every step processes the
+next frame of a ring of distinct device buffers (>= 1 GiB of traffic per
+pass).  One step = one launch of the whole per-pixel path (stencil gather,
+validity, normal, boundary mask, normalisation, stores, per-frame counts)
+over one frame.  The launches of one pass over the ring are captured in a
+HIP graph and replayed, so that Python's per-call overhead does not starve
+the GPU.
+
+`--workload batch` runs the 256-frame mixed batch (64x 320x240, 96x 640x480,
+64x 1280x720, 32x 1920x1080) as one step.
+
+Prints one JSON line.  Also reports the FP64 CPU oracle, timed on the host
+cores on a bounded sample of the same frames.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_PIXEL = 17          # 4 B depth in, 12 B normal + 1 B code out
+HBM_PEAK_GBS = 8000.0         # MI355X HBM3E, AMD published peak
+KERNEL_SOURCES = ["bn_device.h", "bn_kernels.hip", "bn_batch.hip", "bn_capi.hip"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        p = os.path.join(ROOT, "paper_2209_08241_amd", "csrc", name)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, launch_pixels: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p))
+    except Exception:
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(frames, alpha, mode, tau, budget_s):
+    """The oracle as it stands, single thread, on frames until budget_s."""
+    import oracle
+    t0 = time.perf_counter()
+    px = 0
+    n = 0
+    while True:
+        s = frames[n % len(frames)]
+        oracle.normals_f32(s.depth, s.fx, s.fy, s.cx, s.cy, alpha, mode, tau)
+        px += s.depth.size
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": px / el / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} frames ({', '.join(sorted(set(f'{f.depth.shape[1]}x{f.depth.shape[0]}' for f in frames)))}), "
+                      f"{el:.1f} s, single thread, FP64 normals + binary32 mask"}
+
+
+def run_plain(args, torch, bn, scenes):
+    H, W = 1080, 1920
+    ring = args.ring
+    ndistinct = min(args.distinct, ring)
+    log(f"generating {ndistinct} distinct 1920x1080 scenes (seeds 2..{1 + ndistinct})")
+    scs = [scenes.frame_1920x1080(seed=2 + i) for i in range(ndistinct)]
+    dev = torch.device("cuda:0")
+    depth = [torch.from_numpy(scs[i % ndistinct].depth).to(dev) for i in range(ring)]
+    normals = [torch.empty((H, W, 3), dtype=torch.float32, device=dev) for _ in range(ring)]
+    masks = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(ring)]
+    stats = torch.zeros((ring, 4), dtype=torch.int32, device=dev)
+    s0 = scs[0]
+    kw = dict(alpha=args.alpha, mode=args.mode, tau=args.tau, variant=args.variant)
+
+    def one(i, stream=None):
+        j = i % ring
+        bn.estimate_normals(depth[j], s0.fx, s0.fy, s0.cx, s0.cy, normals=normals[j],
+                            mask=masks[j], stats=stats[j], stream=stream, **kw)
+
+    # correctness of the benchmarked configuration against the oracle (frame 0)
+    one(0)
+    torch.cuda.synchronize()
+    import oracle
+    ref = oracle.normals_f32(s0.depth, s0.fx, s0.fy, s0.cx, s0.cy, args.alpha, args.mode, args.tau)
+    import numpy as np
+    ok_mask = bool(np.array_equal(masks[0].cpu().numpy(), ref["mask"]))
+    err = float(np.abs(normals[0].cpu().numpy().astype(np.float64) - ref["normals"]).max())
+    log(f"parity frame 0: mask equal={ok_mask}, max normal error={err:.2e}")
+    if not ok_mask or err > 1e-5:
+        raise SystemExit("benchmark configuration disagrees with the oracle")
+
+    stream = torch.cuda.Stream()
+    graph = None
+    if not args.eager:
+        # one pass over the ring, captured once, replayed per pass
+        with torch.cuda.stream(stream):
+            for i in range(ring):
+                one(i, stream)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            for i in range(ring):
+                one(i, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+
+    steps = max(args.steps // ring, 1) * ring if graph is not None else args.steps
+    warm = max(args.warmup // ring, 1) * ring if graph is not None else args.warmup
+
+    def run(nsteps):
+        if graph is not None:
+            for _ in range(nsteps // ring):
+                graph.replay()
+        else:
+            with torch.cuda.stream(stream):
+                for i in range(nsteps):
+                    one(i, stream)
+
+    with torch.cuda.stream(stream):
+        run(warm)
+    torch.cuda.synchronize()
+    stats.zero_()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        run(steps)
+        end.record(stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(end)
+    ms_step = ms_total / steps
+    px = H * W
+    st = stats.cpu().numpy()
+    passes = steps // ring
+    want = [passes * int(c) for c in ref["counts"]]
+    if st[0, :3].tolist() != want:
+        raise SystemExit(f"per-frame counts wrong after timing: {st[0, :3].tolist()} != {want}")
+    achieved = BYTES_PER_PIXEL * px / (ms_step * 1e-3) / 1e9
+    traffic = load_traffic("plain1080", px)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"timing the oracle for {args.cpu_seconds} s")
+        cpu = cpu_baseline(scs, args.alpha, args.mode, args.tau, args.cpu_seconds)
+    return {
+        "metric": "normals Mpix/s (plain single-frame launches)",
+        "value": px / (ms_step * 1e-3) / 1e6,
+        "unit": "Mpix/s",
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": ms_step,
+        "config": {"workload": "plain 1920x1080, one launch per frame, ring of "
+                               f"{ring} frame buffers ({ndistinct} distinct scenes)",
+                   "frame": "1920x1080", "fx": 1050.0, "alpha": args.alpha,
+                   "mask": args.mode, "tau": args.tau,
+                   "launch": "hip graph replay" if graph is not None else "eager",
+                   "variant": args.variant or "auto"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3200)
+    ap.add_argument("--warmup", type=int, default=320)
+    ap.add_argument("--workload", default="plain1080", choices=["plain1080"])
+    ap.add_argument("--ring", type=int, default=32)
+    ap.add_argument("--distinct", type=int, default=8)
+    ap.add_argument("--alpha", type=int, default=2)
+    ap.add_argument("--mode", default="rel")
+    ap.add_argument("--tau", type=float, default=4.0)
+    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--eager", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2209_08241_amd as bn
+    from synth import scenes
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    bn.lib()
+    out = run_plain(args, torch, bn, scenes)
+    line = {
+        "metric": out["metric"],
+        "value": out["value"],
+        "unit": out["unit"],
+        "n_gpus": 1,
+        "steps": out["steps"],
+        "warmup": out["warmup"],
+        "ms_per_step": out["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": out["config"],
+        "roofline": out["roofline"],
+        "cpu_baseline": out["cpu_baseline"],
+    }
+    for k in ("batched",):
+        if k in out:
+            line[k] = out[k]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * bnormals.h -- C ABI of the MI355X (gfx950) boundary-aware surface-normal
+ * library.
+ *
+ * Method: Moradi, Memarmoghadam, Laurendeau, "Fast, Accurate and Object
+ * Boundary-Aware Surface Normal Estimation from Depth Maps".
+ *   - Per pixel, the average of the normals of the four perpendicular
+ *     tangent pairs around the pixel (Section 3.1, Eq. 7), evaluated in the
+ *     paper's reformulated single-cross-product form 0.25 s24 x s35
+ *     (Eqs. 8-12).  Stencil at pixel distance alpha: tap 2 = (x+alpha, y),
+ *     3 = (x, y+alpha), 4 = (x-alpha, y), 5 = (x, y-alpha), x the column,
+ *     y the row; u = (x - cx)/fx, v = (y - cy)/fy; depth is z-depth.
+ *   - Boundary test (Section 3.2, Eq. 13): the length r = |n| grows with
+ *     the tangent lengths, so pixels whose r exceeds a threshold are
+ *     masked out of the normal map.
+ *
+ * Output per pixel: a code (BN_VALID, BN_BOUNDARY, BN_INVALID) and a normal
+ * that is the camera-facing unit vector -n/|n| when the code is BN_VALID and
+ * (0, 0, 0) otherwise.
+ *
+ * Codes:
+ *   BN_INVALID  the stencil leaves the image; or one of the five taps is not
+ *               a finite depth > 0 (holes are 0); or the binary32 squared
+ *               length below is not a finite number >= FLT_MIN.
+ *   BN_BOUNDARY otherwise, when the threshold test fires;
+ *   BN_VALID    otherwise.
+ *
+ * The threshold test is decided in IEEE binary32, with this exact order of
+ * operations (no fused multiply-add), on m = -(4 fx fy / alpha) n:
+ *     P=d2-d4  S=d2+d4  Q=d3-d5  T=d3+d5   a=T*P  b=S*Q  c=S*T
+ *     mx=fx*a  my=fy*b  xc=(float)x-cx  yc=(float)y-cy
+ *     t3=(xc*a)+(yc*b)  w=(float)alpha*c  mz=t3+w
+ *     q=((mx*mx)+(my*my))+(mz*mz)
+ *   BN_MASK_REL : fires iff q > (tau*tau)*(w*w)    i.e. r/(n.(u,v,1)) > tau
+ *   BN_MASK_ABS : fires iff q > K,  K = (float)((4 fx fy tau / alpha)^2)
+ *                 evaluated in double as ((((4*fx)*fy)*tau)/alpha)^2;
+ *                 i.e. r = |n| > tau, tau in squared depth units
+ *   BN_MASK_NONE: never fires.
+ * so the mask is reproducible bit for bit by any IEEE binary32 evaluation
+ * of the same sequence.  The normal itself is (mx, my, -mz)/sqrt(q) in
+ * binary32 (within 1e-5 per component of the FP64 value for intrinsics of
+ * ordinary cameras, |x - cx|/fx and |y - cy|/fy up to about 2).
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer (HBM of the current HIP
+ *     device) unless its name ends in _host.  The caller owns all buffers;
+ *     the plain entry point allocates nothing.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on that stream; results are visible after the
+ *     caller synchronises it.
+ *   - Argument errors return synchronously, before any launch, and nothing
+ *     is written.  A launch failure returns BN_ERR_DEVICE.  Faults inside a
+ *     kernel surface at the caller's next synchronisation.
+ *   - No C++ exception crosses this interface.  Calls on distinct streams
+ *     may run from several threads at once.
+ */
+#ifndef BNORMALS_H
+#define BNORMALS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BN_VERSION 1
+
+/* status codes */
+#define BN_OK 0
+#define BN_ERR_INVALID_ARG 1
+#define BN_ERR_UNSUPPORTED 2
+#define BN_ERR_DEVICE 3
+#define BN_ERR_OOM 4
+
+/* boundary-test modes */
+#define BN_MASK_REL 0
+#define BN_MASK_ABS 1
+#define BN_MASK_NONE 2
+
+/* per-pixel codes written to the mask */
+#define BN_VALID 0
+#define BN_BOUNDARY 1
+#define BN_INVALID 2
+
+/* limits */
+#define BN_MAX_ALPHA 8
+#define BN_MAX_WIDTH 65536
+#define BN_MAX_PIXELS (1LL << 28)
+
+typedef struct bn_params {
+    int32_t alpha;     /* stencil pixel distance, 1..BN_MAX_ALPHA (Section 3.1) */
+    int32_t mask_mode; /* BN_MASK_REL, BN_MASK_ABS or BN_MASK_NONE (Section 3.2) */
+    float tau;         /* threshold, finite and > 0 (ignored by BN_MASK_NONE) */
+    uint32_t variant;  /* 0 = library's choice; else a kernel variant id
+                          (bn_variant_count / bn_variant_name), for tests and
+                          tuning: every variant writes identical output */
+} bn_params;
+
+/* Per-frame pixel counts by code.  The entry points ADD to these counters
+ * with device atomics; the caller zeroes them before the first call. */
+typedef struct bn_frame_stats {
+    uint32_t n_valid;
+    uint32_t n_boundary;
+    uint32_t n_invalid;
+    uint32_t reserved;
+} bn_frame_stats;
+
+/* One frame of a batch.  depth: [height][depth_stride] binary32, row-major,
+ * depth_stride >= width (elements).  normals: [height][width][3] binary32,
+ * dense.  mask: [height][width] uint8, dense.  stats: nullable. */
+typedef struct bn_frame {
+    const float *depth;
+    int32_t height;
+    int32_t width;
+    int64_t depth_stride;
+    float fx, fy, cx, cy;
+    float *normals;
+    uint8_t *mask;
+    bn_frame_stats *stats;
+} bn_frame;
+
+/*
+ * One frame: normals, mask and (if stats != NULL) counts.
+ *   depth     [height][depth_stride] binary32 depth (z, > 0; 0 = hole)
+ *   fx, fy    focal lengths in pixels (finite, > 0); cx, cy principal point
+ *   params    alpha, mode, tau, variant (host pointer, read during the call)
+ *   normals   [height][width][3] binary32 out
+ *   mask      [height][width] uint8 out (BN_VALID / BN_BOUNDARY / BN_INVALID)
+ *   stats     one bn_frame_stats, counts added atomically (nullable)
+ * height or width 0: nothing to do, BN_OK.  Limits: width <= BN_MAX_WIDTH,
+ * height*width <= BN_MAX_PIXELS.  Returns BN_OK, BN_ERR_INVALID_ARG,
+ * BN_ERR_UNSUPPORTED (alpha > BN_MAX_ALPHA, or a forced variant whose
+ * layout requirement the buffers do not meet) or BN_ERR_DEVICE.
+ */
+int bn_estimate_normals(const float *depth, int32_t height, int32_t width,
+                        int64_t depth_stride, float fx, float fy, float cx, float cy,
+                        const bn_params *params, float *normals, uint8_t *mask,
+                        bn_frame_stats *stats, void *stream);
+
+/* Number of kernel variants of the plain entry point, and a name for each
+ * id 1..count (NULL for an unknown id). */
+int bn_variant_count(void);
+const char *bn_variant_name(int variant);
+/* 1 if `variant` can run this frame layout, 0 if not. */
+int bn_variant_supported(int variant, const float *depth, int32_t height, int32_t width,
+                         int64_t depth_stride, const float *normals, const uint8_t *mask);
+
+const char *bn_status_string(int status);
+int bn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BNORMALS_H */

@@ -51,6 +51,12 @@ def load(path: str = LIB):
                                   ctypes.c_float, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_float, dp, up, qp, dp, dp, dp]
     L.bno_normals_f32.restype = ctypes.c_int
+    L.bno_normals_f32_rows.argtypes = [fp, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_float, ctypes.c_int, ctypes.c_int,
+                                       dp, up, qp, dp, dp, dp]
+    L.bno_normals_f32_rows.restype = ctypes.c_int
     L.bno_normals_f64.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -119,6 +125,28 @@ class Oracle:
         return _run(self.L.bno_normals_f32, depth, np.float32, ctypes.c_float,
                     fx, fy, cx, cy, alpha, mode, tau, want_r, want_rho, eq7)
 
+    def normals_f32_rows(self, depth, fx, fy, cx, cy, alpha, mode, tau, row_begin, row_end):
+        """Rows [row_begin, row_end) of normals_f32 on the full frame."""
+        depth = np.asarray(depth)
+        if depth.ndim != 2 or depth.dtype != np.float32:
+            raise TypeError("depth must be a 2-D float32 array")
+        if depth.strides[1] != 4 or depth.strides[0] % 4:
+            depth = np.ascontiguousarray(depth)
+        H, W = depth.shape
+        stride = depth.strides[0] // 4 if H > 0 else W
+        n = row_end - row_begin
+        normals = np.zeros((n, W, 3), dtype=np.float64)
+        mask = np.zeros((n, W), dtype=np.uint8)
+        counts = np.zeros(3, dtype=np.uint64)
+        none = ctypes.cast(None, ctypes.POINTER(ctypes.c_double))
+        rc = self.L.bno_normals_f32_rows(
+            _ptr(depth, ctypes.c_float), H, W, stride, fx, fy, cx, cy, int(alpha),
+            _mode(mode), tau, int(row_begin), int(row_end), _ptr(normals, ctypes.c_double),
+            _ptr(mask, ctypes.c_uint8), _ptr(counts, ctypes.c_uint64), none, none, none)
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        return {"normals": normals, "mask": mask, "counts": counts}
+
     def normals_f64(self, depth, fx, fy, cx, cy, alpha=2, mode="rel", tau=4.0, *,
                     want_r=False, want_rho=False, eq7=False):
         """FP64 depth -> FP64 normals; boundary decided in FP64 on r or rho."""
@@ -146,6 +174,10 @@ def normals_f32(*args, **kw):
 
 def normals_f64(*args, **kw):
     return default().normals_f64(*args, **kw)
+
+
+def normals_f32_rows(*args, **kw):
+    return default().normals_f32_rows(*args, **kw)
 
 
 def abs_threshold_f32(*args, **kw):

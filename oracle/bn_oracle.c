@@ -262,24 +262,29 @@ static void pixel_normal(double d1, double d2, double d3, double d4, double d5,
  *   rho_out    [H][W] out: FP64 r / (n . ray), NaN if INVALID (nullable)
  *   eq7_gap    out: largest relative gap definition vs closed form over the
  *              non-INVALID pixels (nullable; when null the definition is skipped)
+ *   row_begin, row_end: only rows [row_begin, row_end) of the frame are
+ *              evaluated (in full-frame coordinates); the outputs hold those
+ *              rows only.
  * Returns 0, or 1 on an argument error (nothing written).
  */
-int bno_normals_f32(const float *depth, int H, int W, int64_t stride,
-                    float fx, float fy, float cx, float cy,
-                    int alpha, int mode, float tau,
-                    double *normals, uint8_t *mask, uint64_t *counts,
-                    double *r_out, double *rho_out, double *eq7_gap)
+int bno_normals_f32_rows(const float *depth, int H, int W, int64_t stride,
+                         float fx, float fy, float cx, float cy,
+                         int alpha, int mode, float tau, int row_begin, int row_end,
+                         double *normals, uint8_t *mask, uint64_t *counts,
+                         double *r_out, double *rho_out, double *eq7_gap)
 {
     if (check_common(H, W, stride, fx, fy, alpha, mode, tau) != ORC_OK)
+        return ORC_EARG;
+    if (row_begin < 0 || row_end > H || row_begin > row_end)
         return ORC_EARG;
     if ((H > 0 && W > 0) && (!depth || !normals || !mask))
         return ORC_EARG;
     float kabs = (mode == ORC_ABS) ? abs_threshold_f32(fx, fy, tau, alpha) : 0.0f;
     uint64_t cnt[3] = {0, 0, 0};
     double gap = 0.0;
-    for (int y = 0; y < H; ++y) {
+    for (int y = row_begin; y < row_end; ++y) {
         for (int x = 0; x < W; ++x) {
-            int64_t i = (int64_t)y * W + x;
+            int64_t i = (int64_t)(y - row_begin) * W + x;
             int code = ORC_INVALID;
             double nrm[3] = {0.0, 0.0, 0.0};
             double r = NAN, rho = NAN;
@@ -324,6 +329,17 @@ int bno_normals_f32(const float *depth, int H, int W, int64_t stride,
     }
     if (eq7_gap) *eq7_gap = gap;
     return ORC_OK;
+}
+
+/* The whole frame: bno_normals_f32_rows over rows [0, H). */
+int bno_normals_f32(const float *depth, int H, int W, int64_t stride,
+                    float fx, float fy, float cx, float cy,
+                    int alpha, int mode, float tau,
+                    double *normals, uint8_t *mask, uint64_t *counts,
+                    double *r_out, double *rho_out, double *eq7_gap)
+{
+    return bno_normals_f32_rows(depth, H, W, stride, fx, fy, cx, cy, alpha, mode, tau,
+                                0, H, normals, mask, counts, r_out, rho_out, eq7_gap);
 }
 
 /*

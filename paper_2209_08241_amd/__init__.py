@@ -1,0 +1,178 @@
+"""Python binding of libbnormals.so, the gfx950 HIP implementation of the
+boundary-aware surface normal estimator (include/bnormals.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  PyTorch provides device memory and the current
+stream.  There is no CPU fallback: if the library is not built, or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libbnormals.so")
+
+BN_OK, BN_ERR_INVALID_ARG, BN_ERR_UNSUPPORTED, BN_ERR_DEVICE, BN_ERR_OOM = 0, 1, 2, 3, 4
+MASK_REL, MASK_ABS, MASK_NONE = 0, 1, 2
+VALID, BOUNDARY, INVALID = 0, 1, 2
+MODES = {"rel": MASK_REL, "abs": MASK_ABS, "none": MASK_NONE}
+MAX_ALPHA = 8
+
+
+class BnError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = _status_string(status)
+        super().__init__(f"{what}: {msg} (status {status})" if what else f"{msg} (status {status})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_int32), ("mask_mode", ctypes.c_int32),
+                ("tau", ctypes.c_float), ("variant", ctypes.c_uint32)]
+
+
+class FrameStats(ctypes.Structure):
+    _fields_ = [("n_valid", ctypes.c_uint32), ("n_boundary", ctypes.c_uint32),
+                ("n_invalid", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("height", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("depth_stride", ctypes.c_int64),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("normals", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is not built; run `python -m paper_2209_08241_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+        L.bn_estimate_normals.argtypes = [vp, i32, i32, i64, f32, f32, f32, f32,
+                                          ctypes.POINTER(Params), vp, vp, vp, vp]
+        L.bn_estimate_normals.restype = ctypes.c_int
+        L.bn_variant_count.argtypes = []
+        L.bn_variant_count.restype = ctypes.c_int
+        L.bn_variant_name.argtypes = [ctypes.c_int]
+        L.bn_variant_name.restype = ctypes.c_char_p
+        L.bn_variant_supported.argtypes = [ctypes.c_int, vp, i32, i32, i64, vp, vp]
+        L.bn_variant_supported.restype = ctypes.c_int
+        L.bn_status_string.argtypes = [ctypes.c_int]
+        L.bn_status_string.restype = ctypes.c_char_p
+        L.bn_version.argtypes = []
+        L.bn_version.restype = ctypes.c_int
+        _bind_batch(L)
+        _lib = L
+    return _lib
+
+
+def _bind_batch(L) -> None:
+    if not hasattr(L, "bn_batch_plan_create"):
+        return
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    L.bn_batch_plan_create.argtypes = [ctypes.POINTER(Frame), i32, ctypes.POINTER(Params),
+                                       ctypes.POINTER(vp)]
+    L.bn_batch_plan_create.restype = ctypes.c_int
+    L.bn_batch_plan_update.argtypes = [vp, ctypes.POINTER(Frame), i32]
+    L.bn_batch_plan_update.restype = ctypes.c_int
+    L.bn_batch_run.argtypes = [vp, vp]
+    L.bn_batch_run.restype = ctypes.c_int
+    L.bn_batch_plan_destroy.argtypes = [vp]
+    L.bn_batch_plan_destroy.restype = None
+
+
+def _status_string(status: int) -> str:
+    try:
+        return lib().bn_status_string(int(status)).decode()
+    except Exception:
+        return "unknown status"
+
+
+def variants() -> Sequence[Tuple[int, str]]:
+    """(id, name) of every kernel variant of the plain entry point."""
+    L = lib()
+    return [(i, L.bn_variant_name(i).decode()) for i in range(1, L.bn_variant_count() + 1)]
+
+
+def make_params(alpha: int = 2, mode="rel", tau: float = 4.0, variant: int = 0) -> Params:
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    return Params(int(alpha), m, float(tau), int(variant))
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check_depth(depth):
+    import torch
+    if not isinstance(depth, torch.Tensor) or not depth.is_cuda:
+        raise TypeError("depth must be a CUDA (HIP) torch tensor")
+    if depth.dtype != torch.float32 or depth.dim() != 2:
+        raise TypeError("depth must be a 2-D float32 tensor")
+    if depth.shape[1] > 1 and depth.stride(1) != 1:
+        raise ValueError("depth rows must be contiguous (stride(1) == 1)")
+
+
+def estimate_normals(depth, fx: float, fy: float, cx: float, cy: float, alpha: int = 2,
+                     mode="rel", tau: float = 4.0, *, variant: int = 0,
+                     normals=None, mask=None, stats=None, want_stats: bool = True,
+                     stream=None):
+    """Normals [H,W,3] float32, codes [H,W] uint8 and counts for one frame.
+
+    `stats` (int32 tensor of 4: valid, boundary, invalid, reserved) is
+    accumulated into when given; otherwise a zeroed one is allocated when
+    want_stats.  Returns (normals, mask, stats_or_None).
+    """
+    import torch
+    _check_depth(depth)
+    H, W = depth.shape
+    dev = depth.device
+    if normals is None:
+        normals = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    if mask is None:
+        mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    if stats is None and want_stats:
+        stats = torch.zeros(4, dtype=torch.int32, device=dev)
+    if not (normals.is_contiguous() and normals.shape == (H, W, 3)
+            and normals.dtype == torch.float32):
+        raise ValueError("normals must be a contiguous float32 [H, W, 3] tensor")
+    if not (mask.is_contiguous() and mask.shape == (H, W) and mask.dtype == torch.uint8):
+        raise ValueError("mask must be a contiguous uint8 [H, W] tensor")
+    if stats is not None and (stats.numel() != 4 or stats.dtype != torch.int32
+                              or not stats.is_contiguous()):
+        raise ValueError("stats must be a contiguous int32 tensor of 4 elements")
+    p = make_params(alpha, mode, tau, variant)
+    stride = depth.stride(0) if H > 0 else W
+    rc = lib().bn_estimate_normals(
+        ctypes.c_void_p(depth.data_ptr()), H, W, stride, fx, fy, cx, cy, ctypes.byref(p),
+        ctypes.c_void_p(normals.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
+        ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
+        ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_estimate_normals")
+    return normals, mask, stats
+
+
+def raw_estimate_normals(depth_ptr: int, H: int, W: int, stride: int, fx, fy, cx, cy,
+                         params: Params, normals_ptr: int, mask_ptr: int, stats_ptr: int,
+                         stream: int = 0) -> int:
+    """Direct C-ABI call with raw device addresses; returns the status code."""
+    return lib().bn_estimate_normals(ctypes.c_void_p(depth_ptr), H, W, stride, fx, fy, cx, cy,
+                                     ctypes.byref(params), ctypes.c_void_p(normals_ptr),
+                                     ctypes.c_void_p(mask_ptr), ctypes.c_void_p(stats_ptr),
+                                     ctypes.c_void_p(stream))

@@ -1,0 +1,152 @@
+// Host side of the C ABI declared in include/bnormals.h: argument
+// validation (before any launch), per-frame constants, variant choice and
+// launch on the caller's stream.
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+
+#include "bn_internal.h"
+#include "bnormals.h"
+
+#pragma clang fp contract(off)
+
+using namespace bn;
+
+namespace {
+
+bool finite(float v) { return std::isfinite(v); }
+
+int check_params(const bn_params *p) {
+    if (!p) return BN_ERR_INVALID_ARG;
+    if (p->alpha < 1) return BN_ERR_INVALID_ARG;
+    if (p->alpha > BN_MAX_ALPHA) return BN_ERR_UNSUPPORTED;
+    if (p->mask_mode != BN_MASK_REL && p->mask_mode != BN_MASK_ABS &&
+        p->mask_mode != BN_MASK_NONE)
+        return BN_ERR_INVALID_ARG;
+    if (p->mask_mode != BN_MASK_NONE && !(finite(p->tau) && p->tau > 0.0f))
+        return BN_ERR_INVALID_ARG;
+    if (p->variant > (uint32_t)VAR_COUNT) return BN_ERR_INVALID_ARG;
+    return BN_OK;
+}
+
+int check_frame(const float *depth, int32_t H, int32_t W, int64_t stride, float fx, float fy,
+                float cx, float cy, const float *normals, const uint8_t *mask) {
+    if (H < 0 || W < 0) return BN_ERR_INVALID_ARG;
+    if (W > BN_MAX_WIDTH) return BN_ERR_UNSUPPORTED;
+    if ((int64_t)H * (int64_t)W > BN_MAX_PIXELS) return BN_ERR_UNSUPPORTED;
+    if (!(finite(fx) && fx > 0.0f) || !(finite(fy) && fy > 0.0f)) return BN_ERR_INVALID_ARG;
+    if (!finite(cx) || !finite(cy)) return BN_ERR_INVALID_ARG;
+    if (H == 0 || W == 0) return BN_OK;
+    if (stride < W) return BN_ERR_INVALID_ARG;
+    if (stride > (int64_t)1 << 40) return BN_ERR_UNSUPPORTED;
+    if (!depth || !normals || !mask) return BN_ERR_INVALID_ARG;
+    return BN_OK;
+}
+
+bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool vec4_layout_ok(const float *depth, int32_t W, int64_t stride, const float *normals,
+                    const uint8_t *mask) {
+    return (W % 4 == 0) && (stride % 4 == 0) && aligned(depth, 16) && aligned(normals, 16) &&
+           aligned(mask, 4);
+}
+
+bool variant_ok(int v, const float *depth, int32_t W, int64_t stride, const float *normals,
+                const uint8_t *mask) {
+    const VariantInfo *vi = variant_info(v);
+    if (!vi) return false;
+    if (vi->px_per_item == 4) return vec4_layout_ok(depth, W, stride, normals, mask);
+    return true;
+}
+
+// r = |n| > tau on the scale of q = |m|^2: |m| = (4 fx fy / alpha) r.
+float abs_threshold(float fx, float fy, float tau, int alpha) {
+    double k = 4.0 * (double)fx;
+    k = k * (double)fy;
+    k = k * (double)tau;
+    k = k / (double)alpha;
+    k = k * k;
+    return (float)k;
+}
+
+int pick_variant(const float *depth, int32_t W, int64_t stride, const float *normals,
+                 const uint8_t *mask) {
+    if (vec4_layout_ok(depth, W, stride, normals, mask)) return VAR_VEC4;
+    return VAR_SCALAR;
+}
+
+void fill_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t stride, float fx,
+               float fy, float cx, float cy, const bn_params *p, float *normals, uint8_t *mask,
+               bn_frame_stats *stats, int px_per_item) {
+    f.depth = depth;
+    f.normals = normals;
+    f.mask = mask;
+    f.stats = stats;
+    f.stride = stride;
+    f.H = H;
+    f.W = W;
+    f.fx = fx;
+    f.fy = fy;
+    f.cx = cx;
+    f.cy = cy;
+    f.af = (float)p->alpha;
+    f.rel = p->mask_mode == BN_MASK_REL ? 1 : 0;
+    f.tt = p->tau * p->tau;
+    f.hconst = p->mask_mode == BN_MASK_ABS ? abs_threshold(fx, fy, p->tau, p->alpha) : INFINITY;
+    f.gpr = (uint32_t)(W / px_per_item);
+    f.nitems = f.gpr * (uint32_t)H;
+    f.inv_gpr = 1.0 / (double)f.gpr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bn_estimate_normals(const float *depth, int32_t height, int32_t width, int64_t depth_stride,
+                        float fx, float fy, float cx, float cy, const bn_params *params,
+                        float *normals, uint8_t *mask, bn_frame_stats *stats, void *stream) {
+    int rc = check_params(params);
+    if (rc != BN_OK) return rc;
+    rc = check_frame(depth, height, width, depth_stride, fx, fy, cx, cy, normals, mask);
+    if (rc != BN_OK) return rc;
+    if (height == 0 || width == 0) return BN_OK;
+    int v = (int)params->variant;
+    if (v == VAR_AUTO) {
+        v = pick_variant(depth, width, depth_stride, normals, mask);
+    } else if (!variant_ok(v, depth, width, depth_stride, normals, mask)) {
+        return BN_ERR_UNSUPPORTED;
+    }
+    FrameArgs f;
+    fill_args(f, depth, height, width, depth_stride, fx, fy, cx, cy, params, normals, mask, stats,
+              variant_info(v)->px_per_item);
+    hipError_t e = launch_plain(v, f, (hipStream_t)stream);
+    return e == hipSuccess ? BN_OK : BN_ERR_DEVICE;
+}
+
+int bn_variant_count(void) { return VAR_COUNT; }
+
+const char *bn_variant_name(int variant) {
+    const VariantInfo *vi = variant_info(variant);
+    return vi ? vi->name : nullptr;
+}
+
+int bn_variant_supported(int variant, const float *depth, int32_t height, int32_t width,
+                         int64_t depth_stride, const float *normals, const uint8_t *mask) {
+    (void)height;
+    return variant_ok(variant, depth, width, depth_stride, normals, mask) ? 1 : 0;
+}
+
+const char *bn_status_string(int status) {
+    switch (status) {
+        case BN_OK: return "ok";
+        case BN_ERR_INVALID_ARG: return "invalid argument";
+        case BN_ERR_UNSUPPORTED: return "unsupported argument";
+        case BN_ERR_DEVICE: return "device error";
+        case BN_ERR_OOM: return "out of device memory";
+    }
+    return "unknown status";
+}
+
+int bn_version(void) { return BN_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,32 @@
+// Internal interface between the host side of the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bn_device.h"
+
+namespace bn {
+
+enum Variant {
+    VAR_AUTO = 0,
+    VAR_SCALAR = 1,   // one pixel per thread, any layout
+    VAR_VEC4 = 2,     // 4 pixels per thread, 16-byte vector loads/stores
+    VAR_VEC4_G2 = 3,  // 2 groups of 4 pixels per thread
+    VAR_VEC4_G4 = 4,  // 4 groups of 4 pixels per thread
+    VAR_COUNT = 4
+};
+
+struct VariantInfo {
+    int id;
+    const char *name;
+    int px_per_item;        // pixels per work item (1 or 4)
+    int groups_per_thread;  // work items per thread
+};
+
+const VariantInfo *variant_info(int v);
+
+// Launch one frame with the given variant.  FrameArgs.gpr / nitems /
+// inv_gpr must match the variant's pixels per work item.
+hipError_t launch_plain(int variant, const FrameArgs &f, hipStream_t stream);
+
+}  // namespace bn
