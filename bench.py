@@ -91,7 +91,7 @@ def run_plain(args, torch, bn, scenes):
     depth = [torch.from_numpy(scs[i % ndistinct].depth).to(dev) for i in range(ring)]
     normals = [torch.empty((H, W, 3), dtype=torch.float32, device=dev) for _ in range(ring)]
     masks = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(ring)]
-    stats = torch.zeros((ring, 4), dtype=torch.int32, device=dev)
+    stats = bn.new_stats(ring, device=dev)
     s0 = scs[0]
     kw = dict(alpha=args.alpha, mode=args.mode, tau=args.tau, variant=args.variant)
 

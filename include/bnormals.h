@@ -96,14 +96,24 @@ typedef struct bn_params {
                           tuning: every variant writes identical output */
 } bn_params;
 
-/* Per-frame pixel counts by code.  The entry points ADD to these counters
- * with device atomics; the caller zeroes them before the first call. */
+/* Per-frame pixel counts by code, plus the device workspace the library uses
+ * to reduce them inside the launch that produces them.
+ *
+ * The counts are ADDED to n_valid / n_boundary / n_invalid.  Before the
+ * first use the caller zeroes the whole structure (e.g. hipMemset of
+ * sizeof(bn_frame_stats) bytes); every call leaves `work` zero again, so a
+ * structure can be reused indefinitely, re-zeroing only the counts when a
+ * fresh total is wanted.  Two calls that overlap in time must not share one
+ * structure.  Place it at a 128-byte aligned address (the workspace is one
+ * 128-byte cache line per reduction slot). */
+#define BN_STATS_SLOTS 32
 typedef struct bn_frame_stats {
     uint32_t n_valid;
     uint32_t n_boundary;
     uint32_t n_invalid;
     uint32_t reserved;
-} bn_frame_stats;
+    uint64_t work[14 + 16 * BN_STATS_SLOTS]; /* library-internal, keep zero */
+} bn_frame_stats;                             /* 4224 bytes */
 
 /* One frame of a batch.  depth: [height][depth_stride] binary32, row-major,
  * depth_stride >= width (elements).  normals: [height][width][3] binary32,
@@ -126,7 +136,8 @@ typedef struct bn_frame {
  *   params    alpha, mode, tau, variant (host pointer, read during the call)
  *   normals   [height][width][3] binary32 out
  *   mask      [height][width] uint8 out (BN_VALID / BN_BOUNDARY / BN_INVALID)
- *   stats     one bn_frame_stats, counts added atomically (nullable)
+ *   stats     one bn_frame_stats (zeroed before first use), counts added
+ *             (nullable)
  * height or width 0: nothing to do, BN_OK.  Limits: width <= BN_MAX_WIDTH,
  * height*width <= BN_MAX_PIXELS.  Returns BN_OK, BN_ERR_INVALID_ARG,
  * BN_ERR_UNSUPPORTED (alpha > BN_MAX_ALPHA, or a forced variant whose

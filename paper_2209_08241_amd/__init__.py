@@ -34,9 +34,23 @@ class Params(ctypes.Structure):
                 ("tau", ctypes.c_float), ("variant", ctypes.c_uint32)]
 
 
+STATS_SLOTS = 32
+STATS_BYTES = 16 + 8 * (14 + 16 * STATS_SLOTS)   # sizeof(bn_frame_stats) = 4224
+STATS_WORDS = STATS_BYTES // 4
+
+
 class FrameStats(ctypes.Structure):
     _fields_ = [("n_valid", ctypes.c_uint32), ("n_boundary", ctypes.c_uint32),
-                ("n_invalid", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("n_invalid", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("work", ctypes.c_uint64 * (14 + 16 * STATS_SLOTS))]
+
+
+def new_stats(n: Optional[int] = None, device="cuda"):
+    """Zeroed bn_frame_stats storage: int32 [STATS_WORDS] (or [n, STATS_WORDS]).
+    Words 0..2 are the VALID / BOUNDARY / INVALID counts."""
+    import torch
+    shape = (STATS_WORDS,) if n is None else (n, STATS_WORDS)
+    return torch.zeros(shape, dtype=torch.int32, device=device)
 
 
 class Frame(ctypes.Structure):
@@ -134,7 +148,8 @@ def estimate_normals(depth, fx: float, fy: float, cx: float, cy: float, alpha: i
                      stream=None):
     """Normals [H,W,3] float32, codes [H,W] uint8 and counts for one frame.
 
-    `stats` (int32 tensor of 4: valid, boundary, invalid, reserved) is
+    `stats` (an int32 tensor of STATS_WORDS holding a zero-initialised
+    bn_frame_stats; words 0..2 are the VALID / BOUNDARY / INVALID counts) is
     accumulated into when given; otherwise a zeroed one is allocated when
     want_stats.  Returns (normals, mask, stats_or_None).
     """
@@ -147,15 +162,16 @@ def estimate_normals(depth, fx: float, fy: float, cx: float, cy: float, alpha: i
     if mask is None:
         mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
     if stats is None and want_stats:
-        stats = torch.zeros(4, dtype=torch.int32, device=dev)
+        stats = new_stats(device=dev)
     if not (normals.is_contiguous() and normals.shape == (H, W, 3)
             and normals.dtype == torch.float32):
         raise ValueError("normals must be a contiguous float32 [H, W, 3] tensor")
     if not (mask.is_contiguous() and mask.shape == (H, W) and mask.dtype == torch.uint8):
         raise ValueError("mask must be a contiguous uint8 [H, W] tensor")
-    if stats is not None and (stats.numel() != 4 or stats.dtype != torch.int32
-                              or not stats.is_contiguous()):
-        raise ValueError("stats must be a contiguous int32 tensor of 4 elements")
+    if stats is not None and (stats.numel() != STATS_WORDS or stats.dtype != torch.int32
+                              or not stats.is_contiguous() or stats.data_ptr() % 128):
+        raise ValueError(f"stats must be a contiguous, 128-byte aligned int32 tensor of "
+                         f"{STATS_WORDS} elements (bn_frame_stats)")
     p = make_params(alpha, mode, tau, variant)
     stride = depth.stride(0) if H > 0 else W
     rc = lib().bn_estimate_normals(

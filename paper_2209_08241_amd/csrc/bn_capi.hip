@@ -95,6 +95,7 @@ void fill_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t s
     f.hconst = p->mask_mode == BN_MASK_ABS ? abs_threshold(fx, fy, p->tau, p->alpha) : INFINITY;
     f.gpr = (uint32_t)(W / px_per_item);
     f.nitems = f.gpr * (uint32_t)H;
+    f.npix = (uint32_t)H * (uint32_t)W;
     f.inv_gpr = 1.0 / (double)f.gpr;
 }
 

@@ -1,7 +1,8 @@
 // Device-side pieces shared by every kernel of the library: the per-pixel
 // evaluation (stencil validity, the reformulated normal of Eqs. 10-12 in the
 // scaled form m = -(4 fx fy / alpha) n, the binary32 boundary decision of
-// Section 3.2) and the frame arguments.
+// Section 3.2), wavefront lane shifts, and the in-launch reduction of the
+// per-frame counts.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,22 +18,25 @@ namespace bn {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+constexpr int kBlock = 256;  // 4 wave64 per workgroup
+
 // Everything a kernel needs to process one frame.
 struct FrameArgs {
     const float *depth;
     float *normals;
     uint8_t *mask;
     bn_frame_stats *stats;
-    int64_t stride;      // depth row stride, elements
+    int64_t stride;   // depth row stride, elements
     int32_t H, W;
     float fx, fy, cx, cy;
-    float af;            // (float)alpha
-    float tt;            // tau*tau (REL)
-    float hconst;        // K (ABS) or +inf (NONE)
-    int32_t rel;         // 1 for REL
-    uint32_t gpr;        // work items per row (W/4 for vector kernels, W for scalar)
-    uint32_t nitems;     // gpr * H
-    double inv_gpr;      // 1.0 / gpr
+    float af;         // (float)alpha
+    float tt;         // tau*tau (REL)
+    float hconst;     // K (ABS) or +inf (NONE)
+    int32_t rel;      // 1 for REL
+    uint32_t gpr;     // work items per row (W/4 for vector kernels, W for scalar)
+    uint32_t nitems;  // gpr * H
+    uint32_t npix;    // H * W
+    double inv_gpr;   // 1.0 / gpr
 };
 
 // A finite depth > 0: bit patterns 0x00000001 .. 0x7f7fffff.  Integer test,
@@ -96,6 +100,116 @@ __device__ __forceinline__ PixelOut eval_pixel(bool inside, float d1, float d2, 
     o.ny = valid ? my * inv : 0.0f;
     o.nz = valid ? -(mz * inv) : 0.0f;
     return o;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront lane shifts (DPP wave_shr:1 / wave_shl:1).  Lane i receives the
+// value of lane i-1 (from_left) or i+1 (from_right); the lane without a
+// source receives 0.  Every lane of the wave must execute these.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ f4 from_left(f4 v) {
+    return f4{from_left(v.x), from_left(v.y), from_left(v.z), from_left(v.w)};
+}
+__device__ __forceinline__ f4 from_right(f4 v) {
+    return f4{from_right(v.x), from_right(v.y), from_right(v.z), from_right(v.w)};
+}
+
+__device__ __forceinline__ uint32_t wave_count(bool pred) {
+    return (uint32_t)__popcll(__ballot(pred));
+}
+
+// ---------------------------------------------------------------------------
+// Per-frame counts, reduced inside the launch.
+//
+// A frame's pixels are split into `nparts` parts (workgroups or tiles).  Each
+// part contributes its VALID and BOUNDARY counts with ONE relaxed 64-bit
+// atomic add on the word of slot (part % BN_STATS_SLOTS), each slot on its
+// own 128-byte line of the caller's bn_frame_stats so that the adds of
+// different slots proceed in parallel.  The word packs the counts and an
+// arrival ticket, so the value the atomic returns holds every earlier
+// contribution: the last arrival of a slot (ticket = parts in the slot - 1)
+// knows the slot total without any fence or reload.  It clears the slot and
+// forwards the total the same way to the level-2 word; the last of those
+// adds the frame totals to the counters (INVALID = pixels - VALID - BOUNDARY)
+// and clears the level-2 word.  The workspace is therefore zero again after
+// every launch.
+//
+// Level 1 word: VALID [0,24) | BOUNDARY [24,48) | ticket [48,64)
+//   (a slot holds fewer than 2^24 pixels and 2^16 parts for frames of at
+//    most 2^28 pixels and parts of at most 2^12 pixels).
+// Level 2 word: VALID [0,29) | BOUNDARY [29,58) | ticket [58,64)
+//   (at most 2^28 pixels, at most BN_STATS_SLOTS = 32 arrivals).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long *stats_word(bn_frame_stats *st, uint32_t slot) {
+    // slot 0..31: level 1 (lines 1..32); BN_STATS_SLOTS: level 2 (header line)
+    return reinterpret_cast<unsigned long long *>(
+        slot < BN_STATS_SLOTS ? &st->work[14 + 16 * slot] : &st->work[0]);
+}
+
+__device__ __forceinline__ void reduce_counts(bn_frame_stats *st, uint32_t part, uint32_t nparts,
+                                              uint32_t nvalid, uint32_t nboundary,
+                                              uint32_t npix) {
+    const uint32_t s = part % BN_STATS_SLOTS;
+    const uint32_t ns = nparts / BN_STATS_SLOTS + (s < nparts % BN_STATS_SLOTS ? 1u : 0u);
+    unsigned long long *w1 = stats_word(st, s);
+    const unsigned long long mine1 =
+        (unsigned long long)nvalid | ((unsigned long long)nboundary << 24) | (1ull << 48);
+    const unsigned long long old1 = atomicAdd(w1, mine1);
+    if ((uint32_t)(old1 >> 48) != ns - 1u) return;
+    const unsigned long long tot1 = old1 + mine1;
+    atomicExch(w1, 0ull);
+    const uint32_t vs = (uint32_t)(tot1 & 0xffffffull);
+    const uint32_t bs = (uint32_t)((tot1 >> 24) & 0xffffffull);
+    const uint32_t nactive = nparts < (uint32_t)BN_STATS_SLOTS ? nparts : (uint32_t)BN_STATS_SLOTS;
+    unsigned long long *w2 = stats_word(st, BN_STATS_SLOTS);
+    const unsigned long long mine2 =
+        (unsigned long long)vs | ((unsigned long long)bs << 29) | (1ull << 58);
+    const unsigned long long old2 = atomicAdd(w2, mine2);
+    if ((uint32_t)(old2 >> 58) != nactive - 1u) return;
+    const unsigned long long tot2 = old2 + mine2;
+    atomicExch(w2, 0ull);
+    const uint32_t vt = (uint32_t)(tot2 & ((1ull << 29) - 1));
+    const uint32_t bt = (uint32_t)((tot2 >> 29) & ((1ull << 29) - 1));
+    atomicAdd(&st->n_valid, vt);
+    atomicAdd(&st->n_boundary, bt);
+    atomicAdd(&st->n_invalid, npix - vt - bt);
+}
+
+// Block-wide sum of wave-uniform counts; thread 0 then calls reduce_counts.
+__device__ __forceinline__ void block_counts(bn_frame_stats *st, uint32_t part, uint32_t nparts,
+                                             uint32_t cv, uint32_t cb, uint32_t npix) {
+    __shared__ uint32_t s_cnt[kBlock / 64][2];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_cnt[wave][0] = cv;
+        s_cnt[wave][1] = cb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t v = 0, b = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            v += s_cnt[w][0];
+            b += s_cnt[w][1];
+        }
+        reduce_counts(st, part, nparts, v, b, npix);
+    }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b%8).
+// Give each XCD a contiguous run of tiles so that the rows a tile shares with
+// its neighbours (the stencil halo) are fetched into that XCD's L2 once.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
+    const uint32_t per = nblocks >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7u) * per + (b >> 3);
 }
 
 }  // namespace bn

@@ -3,10 +3,17 @@
 // The estimator is a memory-bound 5-point stencil: 4 bytes of depth in,
 // 12 bytes of normal and 1 byte of code out per pixel, about 40 binary32
 // operations in between.  The kernels therefore aim at full-width coalesced
-// HBM traffic: 16-byte vector loads and stores, horizontal taps served from
-// the same cache lines, vertical taps from the L2 of the XCD that reads the
-// neighbouring rows, and per-frame counts reduced in registers (wavefront
-// ballots) before one atomic per counter per workgroup.
+// HBM traffic:
+//   * a workgroup owns a run of consecutive pixels; the normals it computes
+//     go through LDS so that every global store instruction of a wavefront
+//     writes one contiguous KiB (interleaved 12-byte records stored straight
+//     from registers would scatter each instruction over 3 KiB);
+//   * depth is read with 16-byte loads; the horizontal taps come from the
+//     neighbouring lanes through DPP wave shifts, the vertical taps from the
+//     rows alpha above and below, which the workgroups of the same XCD read
+//     as their own rows (L2 hits);
+//   * per-frame counts are reduced in registers (wavefront ballots), in LDS,
+//     then across the grid with one packed atomic per workgroup.
 #include "bn_device.h"
 #include "bn_internal.h"
 
@@ -14,50 +21,18 @@
 
 namespace bn {
 
-constexpr int kBlock = 256;   // 4 wave64 per workgroup
-
-// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b%8).
-// Give each XCD a contiguous run of tiles so that the rows a tile shares with
-// its neighbours (the stencil halo) are fetched into that XCD's L2 once.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
-    const uint32_t per = nblocks >> 3;
-    if (b >= (per << 3)) return b;
-    return (b & 7u) * per + (b >> 3);
-}
-
-// Block-wide sum of the three code counts, then one atomic per non-zero
-// counter.  cv/cb/ci are wave-uniform per-wave counts.
-__device__ __forceinline__ void flush_counts(bn_frame_stats *stats, uint32_t cv, uint32_t cb,
-                                             uint32_t ci) {
-    __shared__ uint32_t s_cnt[kBlock / 64][3];
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        s_cnt[wave][0] = cv;
-        s_cnt[wave][1] = cb;
-        s_cnt[wave][2] = ci;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        uint32_t s = 0;
-#pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += s_cnt[w][threadIdx.x];
-        if (s) atomicAdd(&stats->n_valid + threadIdx.x, s);
-    }
-}
-
-__device__ __forceinline__ uint32_t wave_count(bool pred) {
-    return (uint32_t)__popcll(__ballot(pred));
-}
-
 // ---------------------------------------------------------------------------
 // Scalar kernel: one pixel per thread, any row stride and alignment.
 // ---------------------------------------------------------------------------
 template <int A>
 __global__ __launch_bounds__(kBlock) void k_scalar(FrameArgs f) {
-    const uint32_t i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    __shared__ float s_out[3 * kBlock];
+    const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t base = blk * kBlock;
+    const uint32_t i = base + threadIdx.x;
     const bool live = i < f.nitems;
     uint32_t code = BN_INVALID;
+    float nx = 0.f, ny = 0.f, nz = 0.f;
     if (live) {
         const uint32_t y = row_of(i, f.inv_gpr);
         const uint32_t x = i - y * f.gpr;
@@ -74,55 +49,94 @@ __global__ __launch_bounds__(kBlock) void k_scalar(FrameArgs f) {
         const float xc = (float)x - f.cx;
         const float yc = (float)y - f.cy;
         const PixelOut o = eval_pixel(inside, d1, d2, d3, d4, d5, xc, yc, f);
-        float *n = f.normals + 3 * (int64_t)i;
-        n[0] = o.nx;
-        n[1] = o.ny;
-        n[2] = o.nz;
-        f.mask[i] = (uint8_t)o.code;
+        nx = o.nx;
+        ny = o.ny;
+        nz = o.nz;
         code = o.code;
+        f.mask[i] = (uint8_t)code;
+    }
+    s_out[3 * threadIdx.x + 0] = nx;
+    s_out[3 * threadIdx.x + 1] = ny;
+    s_out[3 * threadIdx.x + 2] = nz;
+    __syncthreads();
+    const uint32_t n = min((uint32_t)kBlock, f.nitems - base) * 3u;
+    float *out = f.normals + 3 * (int64_t)base;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t j = k * kBlock + threadIdx.x;
+        if (j < n) out[j] = s_out[j];
     }
     if (f.stats) {
         const uint32_t cv = wave_count(live & (code == BN_VALID));
         const uint32_t cb = wave_count(live & (code == BN_BOUNDARY));
-        const uint32_t ci = wave_count(live & (code == BN_INVALID));
-        flush_counts(f.stats, cv, cb, ci);
+        block_counts(f.stats, blk, gridDim.x, cv, cb, f.npix);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Vector kernel: four consecutive pixels of a row per thread.
-// Requires width % 4 == 0, stride % 4 == 0, 16-byte aligned depth and
-// normals and 4-byte aligned mask.  A wave covers 256 pixels of a row
-// segment (or of consecutive rows): its three 16-byte normal stores and one
-// 4-byte code store write 3 KiB + 256 B of contiguous memory.
+// Vector kernel: four consecutive pixels of a row per thread, 256 groups
+// (1024 pixels) per tile, G tiles per workgroup.  Requires width % 4 == 0,
+// stride % 4 == 0, 16-byte aligned depth and normals, 4-byte aligned mask.
 // ---------------------------------------------------------------------------
 template <int A>
-struct Group4 {
-    static constexpr int R = (A + 3) / 4;   // float4s needed on each side
+struct Win {
+    static constexpr int R = (A + 3) / 4;  // float4s needed on each side
     static constexpr int N = 4 * (2 * R + 1);
 };
 
+// Evaluate the group of thread threadIdx.x in `tile`: its 12 normal floats
+// go to s_out[3t .. 3t+2], its four codes to the mask (one 32-bit store) and
+// are returned packed one per byte.
 template <int A>
-__device__ __forceinline__ void process_group4(const FrameArgs &f, uint32_t y, uint32_t x0,
-                                               uint32_t &codes_out) {
-    constexpr int R = Group4<A>::R;
-    const float *rp = f.depth + (int64_t)y * f.stride;
-    float row[Group4<A>::N];
-#pragma unroll
-    for (int k = -R; k <= R; ++k) {
-        const int xs = (int)x0 + 4 * k;
-        f4 v = {0.f, 0.f, 0.f, 0.f};
-        if (k == 0 || (xs >= 0 && xs < f.W)) v = *reinterpret_cast<const f4 *>(rp + xs);
-        row[4 * (k + R) + 0] = v.x;
-        row[4 * (k + R) + 1] = v.y;
-        row[4 * (k + R) + 2] = v.z;
-        row[4 * (k + R) + 3] = v.w;
+__device__ __forceinline__ uint32_t vec4_group(const FrameArgs &f, uint32_t tile, f4 *s_out,
+                                               bool &live) {
+    constexpr int R = Win<A>::R;
+    const uint32_t t = threadIdx.x;
+    const uint32_t lane = t & 63u;
+    const uint32_t i = tile * kBlock + t;
+    live = i < f.nitems;
+    uint32_t y = 0, x0 = 0;
+    if (live) {
+        y = row_of(i, f.inv_gpr);
+        x0 = (i - y * f.gpr) * 4u;
     }
-    const bool rows_in = (y >= (uint32_t)A) & (y + A < (uint32_t)f.H);
-    f4 up = {0.f, 0.f, 0.f, 0.f}, dn = {0.f, 0.f, 0.f, 0.f};
+    const float *rp = f.depth + (int64_t)y * f.stride;
+    const bool rows_in = live & (y >= (uint32_t)A) & (y + A < (uint32_t)f.H);
+    f4 c = {0.f, 0.f, 0.f, 0.f}, up = {0.f, 0.f, 0.f, 0.f}, dn = {0.f, 0.f, 0.f, 0.f};
+    if (live) c = *reinterpret_cast<const f4 *>(rp + x0);
     if (rows_in) {
         up = *reinterpret_cast<const f4 *>(rp - (int64_t)A * f.stride + x0);
         dn = *reinterpret_cast<const f4 *>(rp + (int64_t)A * f.stride + x0);
+    }
+    // row window x0-4R .. x0+4+4R-1; neighbours from adjacent lanes, the
+    // first / last lane of the wave loads its missing float4 itself.  Values
+    // taken across a row end only feed border pixels, which are INVALID.
+    float row[Win<A>::N];
+    row[4 * R + 0] = c.x;
+    row[4 * R + 1] = c.y;
+    row[4 * R + 2] = c.z;
+    row[4 * R + 3] = c.w;
+    f4 lk = c, rk = c;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+        lk = from_left(lk);
+        rk = from_right(rk);
+        if (lane == 0) {
+            const int xs = (int)x0 - 4 * k;
+            lk = (live && xs >= 0) ? *reinterpret_cast<const f4 *>(rp + xs) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+        if (lane == 63) {
+            const int xs = (int)x0 + 4 * k;
+            rk = (live && xs < f.W) ? *reinterpret_cast<const f4 *>(rp + xs) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+        row[4 * (R - k) + 0] = lk.x;
+        row[4 * (R - k) + 1] = lk.y;
+        row[4 * (R - k) + 2] = lk.z;
+        row[4 * (R - k) + 3] = lk.w;
+        row[4 * (R + k) + 0] = rk.x;
+        row[4 * (R + k) + 1] = rk.y;
+        row[4 * (R + k) + 2] = rk.z;
+        row[4 * (R + k) + 3] = rk.w;
     }
     const float upv[4] = {up.x, up.y, up.z, up.w};
     const float dnv[4] = {dn.x, dn.y, dn.z, dn.w};
@@ -134,53 +148,60 @@ __device__ __forceinline__ void process_group4(const FrameArgs &f, uint32_t y, u
         const uint32_t x = x0 + j;
         const bool inside = rows_in & (x >= (uint32_t)A) & (x + A < (uint32_t)f.W);
         const float xc = (float)x - f.cx;
-        const int c = 4 * R + j;
-        const PixelOut o = eval_pixel(inside, row[c], row[c + A], dnv[j], row[c - A], upv[j],
+        const int cI = 4 * R + j;
+        const PixelOut o = eval_pixel(inside, row[cI], row[cI + A], dnv[j], row[cI - A], upv[j],
                                       xc, yc, f);
         nv[3 * j + 0] = o.nx;
         nv[3 * j + 1] = o.ny;
         nv[3 * j + 2] = o.nz;
         codes |= o.code << (8 * j);
     }
-    const int64_t p = (int64_t)y * f.W + x0;
-    f4 *np = reinterpret_cast<f4 *>(f.normals + 3 * p);
-    __builtin_nontemporal_store(f4{nv[0], nv[1], nv[2], nv[3]}, np + 0);
-    __builtin_nontemporal_store(f4{nv[4], nv[5], nv[6], nv[7]}, np + 1);
-    __builtin_nontemporal_store(f4{nv[8], nv[9], nv[10], nv[11]}, np + 2);
-    __builtin_nontemporal_store(codes, reinterpret_cast<uint32_t *>(f.mask + p));
-    codes_out = codes;
+    s_out[3 * t + 0] = f4{nv[0], nv[1], nv[2], nv[3]};
+    s_out[3 * t + 1] = f4{nv[4], nv[5], nv[6], nv[7]};
+    s_out[3 * t + 2] = f4{nv[8], nv[9], nv[10], nv[11]};
+    if (live) __builtin_nontemporal_store(codes, reinterpret_cast<uint32_t *>(f.mask) + i);
+    return codes;
 }
 
-// Per-wave counts of the four codes packed in `codes` (one byte each).
-__device__ __forceinline__ void count_codes(bool live, uint32_t codes, uint32_t &cv, uint32_t &cb,
-                                            uint32_t &ci) {
+// Contiguous store of the tile's normals from LDS: 12 floats per group.
+__device__ __forceinline__ void store_tile_normals(const FrameArgs &f, uint32_t tile,
+                                                   const f4 *s_out) {
+    const uint32_t ngr = min((uint32_t)kBlock, f.nitems - tile * kBlock);
+    f4 *out = reinterpret_cast<f4 *>(f.normals) + 3 * (int64_t)tile * kBlock;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t j = k * kBlock + threadIdx.x;
+        if (j < 3 * ngr) __builtin_nontemporal_store(s_out[j], out + j);
+    }
+}
+
+__device__ __forceinline__ void count_codes(bool live, uint32_t codes, uint32_t &cv,
+                                            uint32_t &cb) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const uint32_t c = (codes >> (8 * j)) & 0xffu;
         cv += wave_count(live & (c == BN_VALID));
         cb += wave_count(live & (c == BN_BOUNDARY));
-        ci += wave_count(live & (c == BN_INVALID));
     }
 }
 
 template <int A, int G>
 __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
-    // G groups of 4 pixels per thread, kBlock groups apart (coalesced).
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    uint32_t cv = 0, cb = 0, ci = 0;
+    __shared__ f4 s_out[3 * kBlock];
+    const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
+    uint32_t cv = 0, cb = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const uint32_t i = (tile * G + g) * kBlock + threadIdx.x;
-        const bool live = i < f.nitems;
-        uint32_t codes = 0;
-        if (live) {
-            const uint32_t y = row_of(i, f.inv_gpr);
-            const uint32_t x0 = (i - y * f.gpr) * 4;
-            process_group4<A>(f, y, x0, codes);
-        }
-        if (f.stats) count_codes(live, codes, cv, cb, ci);
+        const uint32_t tile = blk * G + g;
+        if (tile * kBlock >= f.nitems) break;  // uniform over the workgroup
+        if (g > 0) __syncthreads();             // LDS reuse
+        bool live;
+        const uint32_t codes = vec4_group<A>(f, tile, s_out, live);
+        if (f.stats) count_codes(live, codes, cv, cb);
+        __syncthreads();
+        store_tile_normals(f, tile, s_out);
     }
-    if (f.stats) flush_counts(f.stats, cv, cb, ci);
+    if (f.stats) block_counts(f.stats, blk, gridDim.x, cv, cb, f.npix);
 }
 
 // ---------------------------------------------------------------------------

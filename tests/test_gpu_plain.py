@@ -138,7 +138,7 @@ def test_empty_frames():
         n, m, st = bn.estimate_normals(d, 500.0, 500.0, 1.0, 1.0)
         torch.cuda.synchronize()
         assert n.shape == (H, W, 3) and m.shape == (H, W)
-        assert st.cpu().tolist() == [0, 0, 0, 0]
+        assert not st.cpu().any()
 
 
 def test_deterministic_and_variant_invariant(f1080):
@@ -158,12 +158,16 @@ def test_stats_accumulate(f640):
     import torch
     s = f640
     d = to_gpu(s.depth)
-    st = torch.zeros(4, dtype=torch.int32, device="cuda")
-    bn.estimate_normals(d, *s.intrinsics, 2, stats=st)
-    bn.estimate_normals(d, *s.intrinsics, 2, stats=st)
-    torch.cuda.synchronize()
     ref = oracle.normals_f32(s.depth, *s.intrinsics, 2)
-    assert st.cpu().tolist()[:3] == [2 * int(c) for c in ref["counts"]]
+    for variant in [0] + ALL_VARIANTS:
+        st = bn.new_stats()
+        for _ in range(3):
+            bn.estimate_normals(d, *s.intrinsics, 2, stats=st, variant=variant)
+        torch.cuda.synchronize()
+        h = st.cpu()
+        assert h[:3].tolist() == [3 * int(c) for c in ref["counts"]]
+        # the reduction workspace is left zero
+        assert not h[4:].any()
 
 
 def test_argument_errors():
