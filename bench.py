@@ -184,12 +184,75 @@ def run_plain(args, torch, bn, scenes):
     }
 
 
+def run_batch(args, torch, bn, scenes):
+    """The 256-frame mixed batch, one persistent graph launch per step."""
+    workers = min(16, os.cpu_count() or 1)
+    log(f"generating the 256-frame mixed batch ({workers} workers)")
+    t0 = time.perf_counter()
+    frames_h = scenes.batch_frames(seed0=1000, workers=workers)
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    frames = [bn.BatchFrame(torch.from_numpy(s.depth).to(dev), s.fx, s.fy, s.cx, s.cy)
+              for s in frames_h]
+    plan = bn.BatchPlan(frames, alpha=args.alpha, mode=args.mode, tau=args.tau)
+    info = plan.info()
+    px = info["pixels"]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(max(args.batch_warmup, 1)):
+            plan.run(stream)
+    torch.cuda.synchronize()
+    # correctness of the benchmarked configuration: a sample of frames
+    import numpy as np
+    import oracle
+    for k in (0, 100, 200, 255):
+        s, fr = frames_h[k], frames[k]
+        ref = oracle.normals_f32(s.depth, s.fx, s.fy, s.cx, s.cy, args.alpha, args.mode, args.tau)
+        ok = bool(np.array_equal(fr.mask.cpu().numpy(), ref["mask"]))
+        err = float(np.abs(fr.normals.cpu().numpy().astype(np.float64) - ref["normals"]).max())
+        if not ok or err > 1e-5:
+            raise SystemExit(f"batched frame {k} disagrees with the oracle")
+    log("batched parity sample ok")
+    for fr in frames:
+        fr.stats.zero_()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    steps = args.batch_steps
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        for _ in range(steps):
+            plan.run(stream)
+        end.record(stream)
+    end.synchronize()
+    ms = start.elapsed_time(end) / steps
+    ref0 = oracle.normals_f32(frames_h[0].depth, frames_h[0].fx, frames_h[0].fy,
+                              frames_h[0].cx, frames_h[0].cy, args.alpha, args.mode, args.tau)
+    got0 = frames[0].stats[:3].cpu().tolist()
+    if got0 != [steps * int(c) for c in ref0["counts"]]:
+        raise SystemExit("batched counts wrong after timing")
+    achieved = BYTES_PER_PIXEL * px / (ms * 1e-3) / 1e9
+    plan.close()
+    return {
+        "workload": "256 frames: 64x 320x240, 96x 640x480, 64x 1280x720, 32x 1920x1080 "
+                    "(seeds 1000..1255, fx=fy=525*W/640), one persistent graph launch",
+        "pixels": px, "tiles": info["tiles"], "workgroups": info["workgroups"],
+        "value": px / (ms * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_step": ms, "steps": steps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": load_traffic("batch256", px)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3200)
     ap.add_argument("--warmup", type=int, default=320)
-    ap.add_argument("--workload", default="plain1080", choices=["plain1080"])
+    ap.add_argument("--workload", default="plain1080", choices=["plain1080", "batch"])
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-warmup", type=int, default=10)
     ap.add_argument("--ring", type=int, default=32)
     ap.add_argument("--distinct", type=int, default=8)
     ap.add_argument("--alpha", type=int, default=2)
@@ -213,7 +276,25 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     bn.lib()
-    out = run_plain(args, torch, bn, scenes)
+    if args.workload == "batch":
+        b = run_batch(args, torch, bn, scenes)
+        out = {"metric": "normals Mpix/s (batched persistent launch)", "value": b["value"],
+               "unit": "Mpix/s", "steps": b["steps"], "warmup": args.batch_warmup,
+               "ms_per_step": b["ms_per_step"],
+               "config": {"workload": b["workload"], "alpha": args.alpha, "mask": args.mode,
+                          "tau": args.tau, "pixels": b["pixels"]},
+               "roofline": b["roofline"], "cpu_baseline": None}
+        if not args.no_cpu_baseline:
+            from synth import scenes as sc
+            sample = sc.batch_frames(seed0=1000, indices=[0, 64, 160, 224])
+            out["cpu_baseline"] = cpu_baseline(sample, args.alpha, args.mode, args.tau,
+                                               args.cpu_seconds)
+    else:
+        out = run_plain(args, torch, bn, scenes)
+        if not args.no_batch:
+            b = run_batch(args, torch, bn, scenes)
+            out["batched"] = {k: b[k] for k in ("workload", "value", "unit", "ms_per_step",
+                                                "steps", "pixels", "roofline")}
     line = {
         "metric": out["metric"],
         "value": out["value"],

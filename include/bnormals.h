@@ -148,6 +148,43 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width,
                         const bn_params *params, float *normals, uint8_t *mask,
                         bn_frame_stats *stats, void *stream);
 
+/*
+ * Batches: many frames of any mix of sizes, one persistent launch.
+ *
+ * A plan holds the frame descriptors in device memory and a HIP graph with a
+ * single kernel node that processes every tile of every frame; running the
+ * plan replays the graph.  Frames are described by bn_frame (device
+ * pointers, owned by the caller, which must stay valid while the plan runs).
+ * All frames share `params` (alpha, mode, tau; params->variant must be 0);
+ * each frame has its own size, stride, intrinsics and outputs, and its
+ * counts go to its own bn_frame_stats (zeroed before first use) or nowhere
+ * (stats = NULL).  Each frame's outputs are identical to those of
+ * bn_estimate_normals on that frame.
+ *
+ * bn_batch_plan_create: validates every frame (the checks of
+ *   bn_estimate_normals), allocates the plan (device descriptor table of
+ *   n_frames entries, two pinned staging copies) and instantiates the graph.
+ *   Capacity = n_frames.  Returns BN_OK, BN_ERR_INVALID_ARG,
+ *   BN_ERR_UNSUPPORTED, BN_ERR_OOM or BN_ERR_DEVICE; *out_plan is NULL on
+ *   error.  Synchronous.
+ * bn_batch_plan_update: replaces the frame list (n_frames <= capacity) with
+ *   an asynchronous copy on `stream`, ordered after earlier work and before
+ *   later runs on that stream; the graph is reused unchanged.
+ * bn_batch_run: one launch over the current frame list on `stream`.
+ * bn_batch_plan_info: pixels, tiles and workgroups of the current list.
+ * bn_batch_plan_destroy: frees the plan; the caller makes sure no run of it
+ *   is still in flight.
+ */
+typedef struct bn_batch_plan bn_batch_plan;
+int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn_params *params,
+                         bn_batch_plan **out_plan);
+int bn_batch_plan_update(bn_batch_plan *plan, const bn_frame *frames_host, int32_t n_frames,
+                         void *stream);
+int bn_batch_run(bn_batch_plan *plan, void *stream);
+int bn_batch_plan_info(const bn_batch_plan *plan, int64_t *n_pixels, int64_t *n_tiles,
+                       int32_t *n_workgroups);
+void bn_batch_plan_destroy(bn_batch_plan *plan);
+
 /* Number of kernel variants of the plain entry point, and a name for each
  * id 1..count (NULL for an unknown id). */
 int bn_variant_count(void);

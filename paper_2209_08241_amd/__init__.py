@@ -99,8 +99,11 @@ def _bind_batch(L) -> None:
     L.bn_batch_plan_create.argtypes = [ctypes.POINTER(Frame), i32, ctypes.POINTER(Params),
                                        ctypes.POINTER(vp)]
     L.bn_batch_plan_create.restype = ctypes.c_int
-    L.bn_batch_plan_update.argtypes = [vp, ctypes.POINTER(Frame), i32]
+    L.bn_batch_plan_update.argtypes = [vp, ctypes.POINTER(Frame), i32, vp]
     L.bn_batch_plan_update.restype = ctypes.c_int
+    L.bn_batch_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
+    L.bn_batch_plan_info.restype = ctypes.c_int
     L.bn_batch_run.argtypes = [vp, vp]
     L.bn_batch_run.restype = ctypes.c_int
     L.bn_batch_plan_destroy.argtypes = [vp]
@@ -192,3 +195,89 @@ def raw_estimate_normals(depth_ptr: int, H: int, W: int, stride: int, fx, fy, cx
                                      ctypes.byref(params), ctypes.c_void_p(normals_ptr),
                                      ctypes.c_void_p(mask_ptr), ctypes.c_void_p(stats_ptr),
                                      ctypes.c_void_p(stream))
+
+
+# ---------------------------------------------------------------------------
+# batches
+# ---------------------------------------------------------------------------
+
+class BatchFrame:
+    """One frame of a batch: device depth plus intrinsics; outputs are
+    allocated when not given."""
+
+    def __init__(self, depth, fx, fy, cx, cy, normals=None, mask=None, stats=None,
+                 want_stats: bool = True):
+        import torch
+        _check_depth(depth)
+        H, W = depth.shape
+        dev = depth.device
+        self.depth = depth
+        self.fx, self.fy, self.cx, self.cy = float(fx), float(fy), float(cx), float(cy)
+        self.normals = normals if normals is not None else torch.empty(
+            (H, W, 3), dtype=torch.float32, device=dev)
+        self.mask = mask if mask is not None else torch.empty((H, W), dtype=torch.uint8,
+                                                              device=dev)
+        if stats is None and want_stats:
+            stats = new_stats(device=dev)
+        self.stats = stats
+
+    def _c(self) -> Frame:
+        H, W = self.depth.shape
+        return Frame(self.depth.data_ptr(), H, W, self.depth.stride(0) if H > 0 else W,
+                     self.fx, self.fy, self.cx, self.cy, self.normals.data_ptr(),
+                     self.mask.data_ptr(), self.stats.data_ptr() if self.stats is not None else 0)
+
+
+class BatchPlan:
+    """A bn_batch_plan: every frame of the list in one persistent launch."""
+
+    def __init__(self, frames, alpha: int = 2, mode="rel", tau: float = 4.0):
+        L = lib()
+        self._frames = list(frames)
+        arr = (Frame * len(self._frames))(*[f._c() for f in self._frames])
+        self.params = make_params(alpha, mode, tau, 0)
+        h = ctypes.c_void_p()
+        rc = L.bn_batch_plan_create(arr, len(self._frames), ctypes.byref(self.params),
+                                    ctypes.byref(h))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_batch_plan_create")
+        self._h = h
+
+    @property
+    def frames(self):
+        return self._frames
+
+    def run(self, stream=None) -> None:
+        rc = lib().bn_batch_run(self._h, ctypes.c_void_p(_stream_handle(stream)))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_batch_run")
+
+    def update(self, frames, stream=None) -> None:
+        frames = list(frames)
+        arr = (Frame * len(frames))(*[f._c() for f in frames])
+        rc = lib().bn_batch_plan_update(self._h, arr, len(frames),
+                                        ctypes.c_void_p(_stream_handle(stream)))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_batch_plan_update")
+        self._frames = frames
+
+    def info(self):
+        px, tiles, wg = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        rc = lib().bn_batch_plan_info(self._h, ctypes.byref(px), ctypes.byref(tiles),
+                                      ctypes.byref(wg))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_batch_plan_info")
+        return {"pixels": px.value, "tiles": tiles.value, "workgroups": wg.value}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().bn_batch_plan_destroy(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        import torch
+        torch.cuda.synchronize()
+        self.close()

@@ -12,11 +12,11 @@
 
 using namespace bn;
 
-namespace {
+namespace bn {
 
-bool finite(float v) { return std::isfinite(v); }
+static bool finite(float v) { return std::isfinite(v); }
 
-int check_params(const bn_params *p) {
+int check_params_args(const bn_params *p) {
     if (!p) return BN_ERR_INVALID_ARG;
     if (p->alpha < 1) return BN_ERR_INVALID_ARG;
     if (p->alpha > BN_MAX_ALPHA) return BN_ERR_UNSUPPORTED;
@@ -29,8 +29,8 @@ int check_params(const bn_params *p) {
     return BN_OK;
 }
 
-int check_frame(const float *depth, int32_t H, int32_t W, int64_t stride, float fx, float fy,
-                float cx, float cy, const float *normals, const uint8_t *mask) {
+int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, float fx,
+                     float fy, float cx, float cy, const float *normals, const uint8_t *mask) {
     if (H < 0 || W < 0) return BN_ERR_INVALID_ARG;
     if (W > BN_MAX_WIDTH) return BN_ERR_UNSUPPORTED;
     if ((int64_t)H * (int64_t)W > BN_MAX_PIXELS) return BN_ERR_UNSUPPORTED;
@@ -43,24 +43,24 @@ int check_frame(const float *depth, int32_t H, int32_t W, int64_t stride, float 
     return BN_OK;
 }
 
-bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+static bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
-bool vec4_layout_ok(const float *depth, int32_t W, int64_t stride, const float *normals,
-                    const uint8_t *mask) {
+bool vec4_layout(const float *depth, int32_t W, int64_t stride, const float *normals,
+                 const uint8_t *mask) {
     return (W % 4 == 0) && (stride % 4 == 0) && aligned(depth, 16) && aligned(normals, 16) &&
            aligned(mask, 4);
 }
 
-bool variant_ok(int v, const float *depth, int32_t W, int64_t stride, const float *normals,
-                const uint8_t *mask) {
+static bool variant_ok(int v, const float *depth, int32_t W, int64_t stride,
+                       const float *normals, const uint8_t *mask) {
     const VariantInfo *vi = variant_info(v);
     if (!vi) return false;
-    if (vi->px_per_item == 4) return vec4_layout_ok(depth, W, stride, normals, mask);
+    if (vi->px_per_item == 4) return vec4_layout(depth, W, stride, normals, mask);
     return true;
 }
 
 // r = |n| > tau on the scale of q = |m|^2: |m| = (4 fx fy / alpha) r.
-float abs_threshold(float fx, float fy, float tau, int alpha) {
+static float abs_threshold(float fx, float fy, float tau, int alpha) {
     double k = 4.0 * (double)fx;
     k = k * (double)fy;
     k = k * (double)tau;
@@ -69,15 +69,15 @@ float abs_threshold(float fx, float fy, float tau, int alpha) {
     return (float)k;
 }
 
-int pick_variant(const float *depth, int32_t W, int64_t stride, const float *normals,
-                 const uint8_t *mask) {
-    if (vec4_layout_ok(depth, W, stride, normals, mask)) return VAR_VEC4;
+static int pick_variant(const float *depth, int32_t W, int64_t stride, const float *normals,
+                        const uint8_t *mask) {
+    if (vec4_layout(depth, W, stride, normals, mask)) return VAR_VEC4;
     return VAR_SCALAR;
 }
 
-void fill_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t stride, float fx,
-               float fy, float cx, float cy, const bn_params *p, float *normals, uint8_t *mask,
-               bn_frame_stats *stats, int px_per_item) {
+void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t stride,
+                     float fx, float fy, float cx, float cy, const bn_params *p, float *normals,
+                     uint8_t *mask, bn_frame_stats *stats, int px_per_item) {
     f.depth = depth;
     f.normals = normals;
     f.mask = mask;
@@ -99,16 +99,16 @@ void fill_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t s
     f.inv_gpr = 1.0 / (double)f.gpr;
 }
 
-}  // namespace
+}  // namespace bn
 
 extern "C" {
 
 int bn_estimate_normals(const float *depth, int32_t height, int32_t width, int64_t depth_stride,
                         float fx, float fy, float cx, float cy, const bn_params *params,
                         float *normals, uint8_t *mask, bn_frame_stats *stats, void *stream) {
-    int rc = check_params(params);
+    int rc = check_params_args(params);
     if (rc != BN_OK) return rc;
-    rc = check_frame(depth, height, width, depth_stride, fx, fy, cx, cy, normals, mask);
+    rc = check_frame_args(depth, height, width, depth_stride, fx, fy, cx, cy, normals, mask);
     if (rc != BN_OK) return rc;
     if (height == 0 || width == 0) return BN_OK;
     int v = (int)params->variant;
@@ -118,8 +118,8 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width, int64
         return BN_ERR_UNSUPPORTED;
     }
     FrameArgs f;
-    fill_args(f, depth, height, width, depth_stride, fx, fy, cx, cy, params, normals, mask, stats,
-              variant_info(v)->px_per_item);
+    fill_frame_args(f, depth, height, width, depth_stride, fx, fy, cx, cy, params, normals, mask,
+                    stats, variant_info(v)->px_per_item);
     hipError_t e = launch_plain(v, f, (hipStream_t)stream);
     return e == hipSuccess ? BN_OK : BN_ERR_DEVICE;
 }

@@ -25,6 +25,18 @@ struct VariantInfo {
 
 const VariantInfo *variant_info(int v);
 
+// Argument checks shared by the entry points (bn status codes).
+int check_params_args(const bn_params *p);
+int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, float fx,
+                     float fy, float cx, float cy, const float *normals, const uint8_t *mask);
+// True when the frame can use the 4-pixel vector tiles.
+bool vec4_layout(const float *depth, int32_t W, int64_t stride, const float *normals,
+                 const uint8_t *mask);
+// Per-frame kernel arguments (derived constants included).
+void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t stride,
+                     float fx, float fy, float cx, float cy, const bn_params *p, float *normals,
+                     uint8_t *mask, bn_frame_stats *stats, int px_per_item);
+
 // Launch one frame with the given variant.  FrameArgs.gpr / nitems /
 // inv_gpr must match the variant's pixels per work item.
 hipError_t launch_plain(int variant, const FrameArgs &f, hipStream_t stream);

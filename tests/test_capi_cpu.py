@@ -1,0 +1,104 @@
+"""The C-ABI library on the CPU: it loads, exports every function that
+include/bnormals.h declares, and rejects bad arguments before any HIP call
+(so no GPU is needed for these)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2209_08241_amd as bn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bnormals.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w ]*?\**\s*\b(bn_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for want in ("bn_estimate_normals", "bn_batch_plan_create", "bn_batch_plan_update",
+                 "bn_batch_run", "bn_batch_plan_destroy", "bn_status_string", "bn_version"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = bn.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(bn.Params) == 16
+    assert ctypes.sizeof(bn.FrameStats) == bn.STATS_BYTES == 4224
+    assert ctypes.sizeof(bn.Frame) == 64
+
+
+def test_version_and_status_strings():
+    L = bn.lib()
+    assert L.bn_version() == 1
+    for s in range(5):
+        assert L.bn_status_string(s)
+    assert L.bn_status_string(99) == b"unknown status"
+    assert L.bn_variant_count() >= 2
+    assert L.bn_variant_name(0) is None and L.bn_variant_name(1) == b"scalar"
+
+
+@pytest.mark.parametrize("kw,dims,want", [
+    (dict(alpha=0), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(alpha=9), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_UNSUPPORTED),
+    (dict(tau=0.0), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(tau=float("inf")), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(mode=3), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(variant=17), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(), (8, 8, 7, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(), (-1, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(), (8, 8, 8, -5.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(), (8, 8, 8, 500.0, float("nan")), bn.BN_ERR_INVALID_ARG),
+    (dict(), (8, 65537, 65537, 500.0, 500.0), bn.BN_ERR_UNSUPPORTED),
+    (dict(), (1 << 15, 1 << 14, 1 << 14, 500.0, 500.0), bn.BN_ERR_UNSUPPORTED),
+])
+def test_argument_errors_before_launch(kw, dims, want):
+    H, W, stride, fx, fy = dims
+    p = bn.make_params(**kw)
+    # fake, never-dereferenced addresses: validation fails before any HIP call
+    rc = bn.raw_estimate_normals(0x10000, H, W, stride, fx, fy, 3.5, 3.5, p, 0x20000, 0x30000, 0)
+    assert rc == want
+
+
+def test_null_pointers_rejected():
+    p = bn.make_params()
+    assert bn.raw_estimate_normals(0, 8, 8, 8, 500.0, 500.0, 1.0, 1.0, p, 0x20000, 0x30000, 0) \
+        == bn.BN_ERR_INVALID_ARG
+    assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 1.0, 1.0, p, 0, 0x30000, 0) \
+        == bn.BN_ERR_INVALID_ARG
+    assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 1.0, 1.0, p, 0x20000, 0, 0) \
+        == bn.BN_ERR_INVALID_ARG
+    assert bn.lib().bn_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 1.0, 1.0, None,
+                                        0x20000, 0x30000, 0, 0) == bn.BN_ERR_INVALID_ARG
+
+
+def test_empty_frame_is_a_no_op():
+    p = bn.make_params()
+    assert bn.raw_estimate_normals(0, 0, 0, 0, 500.0, 500.0, 1.0, 1.0, p, 0, 0, 0) == bn.BN_OK
+
+
+def test_batch_plan_argument_errors():
+    L = bn.lib()
+    h = ctypes.c_void_p()
+    p = bn.make_params()
+    assert L.bn_batch_plan_create(None, 1, ctypes.byref(p), ctypes.byref(h)) == bn.BN_ERR_INVALID_ARG
+    assert h.value is None
+    fr = (bn.Frame * 1)(bn.Frame(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, 0x20000, 0x30000, 0))
+    assert L.bn_batch_plan_create(fr, 0, ctypes.byref(p), ctypes.byref(h)) == bn.BN_ERR_INVALID_ARG
+    bad = bn.make_params(alpha=0)
+    assert L.bn_batch_plan_create(fr, 1, ctypes.byref(bad), ctypes.byref(h)) == bn.BN_ERR_INVALID_ARG
+    forced = bn.make_params(variant=2)
+    assert L.bn_batch_plan_create(fr, 1, ctypes.byref(forced), ctypes.byref(h)) == bn.BN_ERR_UNSUPPORTED
+    assert L.bn_batch_run(None, None) == bn.BN_ERR_INVALID_ARG
+    L.bn_batch_plan_destroy(None)

@@ -1,0 +1,171 @@
+"""GPU parity of the batched entry points (bn_batch_plan_*): each frame's
+outputs equal the plain entry point's bit for bit and the oracle's (masks
+and counts exact, normals within 1e-5)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2209_08241_amd as bn
+from gpu_util import assert_parity, log, to_gpu
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _plain(fr, alpha, mode, tau):
+    n, m, st = bn.estimate_normals(fr.depth, fr.fx, fr.fy, fr.cx, fr.cy, alpha, mode, tau)
+    return n, m, st
+
+
+def _check_against_plain(frames, alpha=2, mode="rel", tau=4.0):
+    import torch
+    for k, fr in enumerate(frames):
+        n, m, st = _plain(fr, alpha, mode, tau)
+        torch.cuda.synchronize()
+        assert torch.equal(fr.mask, m), f"frame {k}: mask differs from plain"
+        assert torch.equal(fr.normals.view(torch.int32), n.view(torch.int32)), \
+            f"frame {k}: normals differ from plain"
+        if fr.stats is not None:
+            assert torch.equal(fr.stats[:3], st[:3]), f"frame {k}: counts differ from plain"
+
+
+@pytest.fixture(scope="module")
+def mixed_batch():
+    log("generating the 256-frame mixed batch")
+    return scenes.batch_frames(seed0=1000, workers=8)
+
+
+def test_mixed_256(mixed_batch):
+    """The 256-frame mix (64x 320x240, 96x 640x480, 64x 1280x720,
+    32x 1920x1080) in one launch, as the benchmark runs it."""
+    import torch
+    frames = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in mixed_batch]
+    with bn.BatchPlan(frames, alpha=2, mode="rel", tau=4.0) as plan:
+        info = plan.info()
+        assert info["pixels"] == 159_744_000
+        plan.run()
+        torch.cuda.synchronize()
+        log("batch ran; checking every frame against the oracle")
+        for k, (s, fr) in enumerate(zip(mixed_batch, frames)):
+            ref = oracle.normals_f32(s.depth, s.fx, s.fy, s.cx, s.cy, 2, "rel", 4.0)
+            st = fr.stats.cpu()
+            assert st[:3].tolist() == [int(c) for c in ref["counts"]], f"frame {k} counts"
+            assert not st[4:].any(), f"frame {k}: workspace not cleared"
+            if k % 8 == 0:
+                assert_parity(ref, fr.normals.cpu().numpy(), fr.mask.cpu().numpy(),
+                              what=f"batch frame {k}")
+        log("checking every frame against the plain entry point")
+        for fr in frames:
+            fr.stats.zero_()
+        plan.run()
+        torch.cuda.synchronize()
+        _check_against_plain(frames)
+
+
+def _odd_frames(rng, alpha):
+    import torch
+    frames, host = [], []
+    shapes = [(7, 9), (1, 1), (0, 5), (5, 0), (33, 65), (64, 64), (17, 1028), (240, 321),
+              (2 * alpha, 50), (120, 160), (3, 4), (480, 640)]
+    for H, W in shapes:
+        d = rng.uniform(0.7, 3.0, size=(H, W)).astype(np.float32)
+        if d.size:
+            d[rng.random((H, W)) < 0.03] = 0.0
+        host.append(d)
+    for k, d in enumerate(host):
+        H, W = d.shape
+        pad = 3 if k % 3 == 1 else 0          # strided rows -> scalar tiles
+        t = to_gpu(d, stride_pad=pad)
+        fx = 200.0 + 10 * k
+        fr = bn.BatchFrame(t, fx, fx * 1.05, (W - 1) / 2, (H - 1) / 2,
+                           want_stats=(k % 4 != 2))
+        frames.append(fr)
+    return frames, host
+
+
+@pytest.mark.parametrize("alpha", [1, 2, 3, 6])
+@pytest.mark.parametrize("mode,tau", [("rel", 4.0), ("abs", 5e-4), ("none", 1.0)])
+def test_mixed_layouts(alpha, mode, tau):
+    """Vector and scalar tiles, empty and tiny frames, frames without counts."""
+    import torch
+    rng = np.random.default_rng(alpha * 7 + len(mode))
+    frames, host = _odd_frames(rng, alpha)
+    with bn.BatchPlan(frames, alpha=alpha, mode=mode, tau=tau) as plan:
+        plan.run()
+        torch.cuda.synchronize()
+        for k, (d, fr) in enumerate(zip(host, frames)):
+            ref = oracle.normals_f32(d, fr.fx, fr.fy, fr.cx, fr.cy, alpha, mode, tau)
+            st = fr.stats.cpu().numpy() if fr.stats is not None else None
+            assert_parity(ref, fr.normals.cpu().numpy(), fr.mask.cpu().numpy(), st,
+                          what=f"odd frame {k} {d.shape}")
+        for fr in frames:
+            if fr.stats is not None:
+                fr.stats.zero_()
+        plan.run()
+        torch.cuda.synchronize()
+        _check_against_plain(frames, alpha, mode, tau)
+
+
+def test_update_and_repeat():
+    import torch
+    rng = np.random.default_rng(11)
+    frames, host = _odd_frames(rng, 2)
+    with bn.BatchPlan(frames, alpha=2) as plan:
+        for _ in range(3):
+            plan.run()
+        torch.cuda.synchronize()
+        for k, (d, fr) in enumerate(zip(host, frames)):
+            if fr.stats is None:
+                continue
+            ref = oracle.normals_f32(d, fr.fx, fr.fy, fr.cx, fr.cy, 2, "rel", 4.0)
+            st = fr.stats.cpu()
+            assert st[:3].tolist() == [3 * int(c) for c in ref["counts"]]
+            assert not st[4:].any()
+        # a different, shorter list through the same plan (same graph)
+        new = [scenes.sized_frame(240, 320, seed=77), scenes.sized_frame(480, 640, seed=78)]
+        nf = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in new]
+        plan.update(nf)
+        plan.run()
+        torch.cuda.synchronize()
+        assert plan.info()["pixels"] == 240 * 320 + 480 * 640
+        for s, fr in zip(new, nf):
+            ref = oracle.normals_f32(s.depth, s.fx, s.fy, s.cx, s.cy, 2, "rel", 4.0)
+            assert_parity(ref, fr.normals.cpu().numpy(), fr.mask.cpu().numpy(),
+                          fr.stats.cpu().numpy(), what="updated frame")
+        with pytest.raises(bn.BnError):
+            plan.update(nf * 20)        # over capacity
+
+
+def test_plan_errors():
+    import torch
+    d = torch.ones((8, 8), dtype=torch.float32, device="cuda")
+    good = bn.BatchFrame(d, 500.0, 500.0, 3.5, 3.5)
+    bad = bn.BatchFrame(d, -1.0, 500.0, 3.5, 3.5)
+    for frames, kw, status in (([good, bad], {}, bn.BN_ERR_INVALID_ARG),
+                               ([good], {"alpha": 9}, bn.BN_ERR_UNSUPPORTED),
+                               ([good], {"alpha": 0}, bn.BN_ERR_INVALID_ARG),
+                               ([good], {"tau": -1.0}, bn.BN_ERR_INVALID_ARG)):
+        with pytest.raises(bn.BnError) as e:
+            bn.BatchPlan(frames, **kw)
+        assert e.value.status == status
+    with pytest.raises(bn.BnError):
+        bn.BatchPlan([])
+
+
+def test_graph_replay_deterministic(mixed_batch):
+    import torch
+    sub = mixed_batch[::16]
+    frames = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in sub]
+    with bn.BatchPlan(frames) as plan:
+        plan.run()
+        torch.cuda.synchronize()
+        first = [(f.normals.clone(), f.mask.clone(), f.stats[:3].clone()) for f in frames]
+        for _ in range(4):
+            for f in frames:
+                f.stats.zero_()
+            plan.run()
+            torch.cuda.synchronize()
+            for (n0, m0, s0), f in zip(first, frames):
+                assert torch.equal(n0.view(torch.int32), f.normals.view(torch.int32))
+                assert torch.equal(m0, f.mask)
+                assert torch.equal(s0, f.stats[:3])
