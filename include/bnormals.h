@@ -149,6 +149,22 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width,
                         bn_frame_stats *stats, void *stream);
 
 /*
+ * Adjoint of bn_estimate_normals with respect to the depth (the
+ * vector-Jacobian product), with every pixel's code held fixed:
+ *   grad_depth[j] = sum over VALID pixels p of (d normal_p / d depth_j) . grad_normals[p]
+ * The codes are recomputed exactly as bn_estimate_normals decides them; the
+ * entries of grad_normals at masked pixels are ignored (their normal is the
+ * constant 0).  d1 does not enter Eqs. 10-12, so a pixel's own depth gets
+ * gradient only through its four neighbours' normals.
+ *   grad_normals [height][width][3] binary32, dense
+ *   grad_depth   [height][width] binary32 out, dense, overwritten
+ * Same argument rules and errors as bn_estimate_normals (params->variant 0).
+ */
+int bn_normals_vjp(const float *depth, int32_t height, int32_t width, int64_t depth_stride,
+                   float fx, float fy, float cx, float cy, const bn_params *params,
+                   const float *grad_normals, float *grad_depth, void *stream);
+
+/*
  * Batches: many frames of any mix of sizes, one persistent launch.
  *
  * A plan holds the frame descriptors in device memory and a HIP graph with a
@@ -184,6 +200,33 @@ int bn_batch_run(bn_batch_plan *plan, void *stream);
 int bn_batch_plan_info(const bn_batch_plan *plan, int64_t *n_pixels, int64_t *n_tiles,
                        int32_t *n_workgroups);
 void bn_batch_plan_destroy(bn_batch_plan *plan);
+
+/*
+ * Autotuning.  Choices are kept per process in a table keyed by GPU
+ * architecture, alpha and frame-size class (bit length of the pixel count);
+ * when the environment variable BN_AUTOTUNE_CACHE names a file, the table
+ * is loaded from it on first use and saved to it after each tuning.
+ *
+ * bn_autotune_plain: times every kernel variant of bn_estimate_normals on
+ *   a ring of scratch frames of height x width (allocated and freed here,
+ *   about 512 MiB) and records the fastest; later calls with params->variant
+ *   == 0 on frames of that size class use it.  Synchronous.
+ * bn_batch_plan_autotune: times the plan's launch with the flat grid (one
+ *   workgroup per tile; *best_blocks_per_cu = 0) and with 2, 4 and 8
+ *   persistent workgroups per compute unit, keeps the fastest for this plan
+ *   and records it for new plans of the same size class.  It RUNS the plan
+ *   (outputs are rewritten, counts accumulate): zero the counts afterwards.
+ * bn_autotune_save / _load: write / read the table as JSON.
+ * bn_autotune_reset: forget every entry.  bn_autotune_entries: table size.
+ */
+int bn_autotune_plain(int32_t height, int32_t width, const bn_params *params,
+                      int32_t *best_variant, float *best_us);
+int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_blocks_per_cu,
+                           float *best_us);
+int bn_autotune_save(const char *path);
+int bn_autotune_load(const char *path);
+void bn_autotune_reset(void);
+int bn_autotune_entries(void);
 
 /* Number of kernel variants of the plain entry point, and a name for each
  * id 1..count (NULL for an unknown id). */

@@ -62,6 +62,14 @@ def load(path: str = LIB):
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_double, dp, up, qp, dp, dp, dp]
     L.bno_normals_f64.restype = ctypes.c_int
+    L.bno_normals_frozen_f64.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, up, dp]
+    L.bno_normals_frozen_f64.restype = ctypes.c_int
+    L.bno_normals_vjp_f64.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int, up, dp, dp]
+    L.bno_normals_vjp_f64.restype = ctypes.c_int
     L.bno_abs_threshold_f32.argtypes = [ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, ctypes.c_int]
     L.bno_abs_threshold_f32.restype = ctypes.c_float
@@ -153,6 +161,33 @@ class Oracle:
         return _run(self.L.bno_normals_f64, depth, np.float64, ctypes.c_double,
                     fx, fy, cx, cy, alpha, mode, tau, want_r, want_rho, eq7)
 
+    def normals_frozen_f64(self, depth, fx, fy, cx, cy, alpha, codes):
+        """FP64 normals of the pixels whose code is VALID, codes held fixed."""
+        depth = np.ascontiguousarray(depth, dtype=np.float64)
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        H, W = depth.shape
+        out = np.zeros((H, W, 3), dtype=np.float64)
+        rc = self.L.bno_normals_frozen_f64(_ptr(depth, ctypes.c_double), H, W, W, fx, fy, cx, cy,
+                                           int(alpha), _ptr(codes, ctypes.c_uint8),
+                                           _ptr(out, ctypes.c_double))
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        return out
+
+    def normals_vjp_f64(self, depth, fx, fy, cx, cy, alpha, codes, grad_normals):
+        """FP64 d(sum normals . grad_normals)/d depth with the codes frozen."""
+        depth = np.ascontiguousarray(depth, dtype=np.float64)
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        g = np.ascontiguousarray(grad_normals, dtype=np.float64)
+        H, W = depth.shape
+        out = np.zeros((H, W), dtype=np.float64)
+        rc = self.L.bno_normals_vjp_f64(_ptr(depth, ctypes.c_double), H, W, W, fx, fy, cx, cy,
+                                        int(alpha), _ptr(codes, ctypes.c_uint8),
+                                        _ptr(g, ctypes.c_double), _ptr(out, ctypes.c_double))
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        return out
+
     def abs_threshold_f32(self, fx, fy, tau, alpha) -> float:
         """Binary32 threshold on |m|^2 that ABS mode compares against."""
         return float(self.L.bno_abs_threshold_f32(fx, fy, tau, int(alpha)))
@@ -182,3 +217,11 @@ def normals_f32_rows(*args, **kw):
 
 def abs_threshold_f32(*args, **kw):
     return default().abs_threshold_f32(*args, **kw)
+
+
+def normals_frozen_f64(*args, **kw):
+    return default().normals_frozen_f64(*args, **kw)
+
+
+def normals_vjp_f64(*args, **kw):
+    return default().normals_vjp_f64(*args, **kw)

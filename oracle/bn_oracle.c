@@ -412,6 +412,103 @@ int bno_normals_f64(const double *depth, int H, int W, int64_t stride,
     return ORC_OK;
 }
 
+/*
+ * Differentiation (test infrastructure for the adjoint kernel).
+ *
+ * With the codes frozen (the mask is piecewise constant in the depth), the
+ * output of a VALID pixel is out = -n/|n| with n the closed form of
+ * Eqs. 10-12, a smooth function of its taps d2..d5 (d1 does not enter);
+ * masked pixels output a constant 0.
+ */
+
+/* FP64 normals of the pixels whose given code is VALID (others 0). */
+int bno_normals_frozen_f64(const double *depth, int H, int W, int64_t stride,
+                           double fx, double fy, double cx, double cy, int alpha,
+                           const uint8_t *codes, double *normals)
+{
+    if (check_common(H, W, stride, fx, fy, alpha, ORC_NONE, 1.0) != ORC_OK)
+        return ORC_EARG;
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            int64_t i = (int64_t)y * W + x;
+            double *o = normals + 3 * i;
+            o[0] = o[1] = o[2] = 0.0;
+            if (codes[i] != ORC_VALID)
+                continue;
+            if (x - alpha < 0 || x + alpha > W - 1 || y - alpha < 0 || y + alpha > H - 1)
+                return ORC_EARG;
+            const double *row = depth + (int64_t)y * stride;
+            double r, rho;
+            pixel_normal(row[x], row[x + alpha], depth[(int64_t)(y + alpha) * stride + x],
+                         row[x - alpha], depth[(int64_t)(y - alpha) * stride + x],
+                         x, y, fx, fy, cx, cy, alpha, o, &r, &rho, NULL);
+        }
+    }
+    return ORC_OK;
+}
+
+/*
+ * Vector-Jacobian product of the frozen normal map:
+ *   grad_depth[j] = sum over VALID pixels p of (d out_p / d depth_j) . grad_normals[p]
+ * Chain rule through Eqs. 10-12, scattered pixel by pixel onto the four taps:
+ *   g_n = d/dn of out . g = -(g - (nh . g) nh) / |n|,  nh = n/|n|
+ *   with P = d2-d4, S = d2+d4, Q = d3-d5, T = d3+d5, u1 = (x-cx)/fx, v1 = (y-cy)/fy:
+ *   dL/dP = (g_nx - u1 g_nz) (-alpha T / (4 fy))
+ *   dL/dT = (g_nx - u1 g_nz) (-alpha P / (4 fy)) + g_nz alpha^2 S / (4 fx fy)
+ *   dL/dQ = (g_ny - v1 g_nz) (-alpha S / (4 fx))
+ *   dL/dS = (g_ny - v1 g_nz) (-alpha Q / (4 fx)) + g_nz alpha^2 T / (4 fx fy)
+ *   d2 += dP + dS,  d4 += -dP + dS,  d3 += dQ + dT,  d5 += -dQ + dT.
+ * grad_depth is [H][W] (dense), overwritten.
+ */
+int bno_normals_vjp_f64(const double *depth, int H, int W, int64_t stride,
+                        double fx, double fy, double cx, double cy, int alpha,
+                        const uint8_t *codes, const double *grad_normals, double *grad_depth)
+{
+    if (check_common(H, W, stride, fx, fy, alpha, ORC_NONE, 1.0) != ORC_OK)
+        return ORC_EARG;
+    for (int64_t i = 0; i < (int64_t)H * W; ++i)
+        grad_depth[i] = 0.0;
+    const double a = (double)alpha;
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            int64_t i = (int64_t)y * W + x;
+            if (codes[i] != ORC_VALID)
+                continue;
+            if (x - alpha < 0 || x + alpha > W - 1 || y - alpha < 0 || y + alpha > H - 1)
+                return ORC_EARG;
+            const double *row = depth + (int64_t)y * stride;
+            double d2 = row[x + alpha];
+            double d4 = row[x - alpha];
+            double d3 = depth[(int64_t)(y + alpha) * stride + x];
+            double d5 = depth[(int64_t)(y - alpha) * stride + x];
+            double u1 = ((double)x - cx) / fx;
+            double v1 = ((double)y - cy) / fy;
+            double n[3];
+            normal_closed_form(d2, d3, d4, d5, u1, v1, fx, fy, a, n);
+            double len = norm3(n);
+            double nh[3] = {n[0] / len, n[1] / len, n[2] / len};
+            const double *g = grad_normals + 3 * i;
+            double ng = nh[0] * g[0] + nh[1] * g[1] + nh[2] * g[2];
+            double gn[3];
+            for (int k = 0; k < 3; ++k)
+                gn[k] = -(g[k] - ng * nh[k]) / len;
+            double P = d2 - d4, S = d2 + d4, Q = d3 - d5, T = d3 + d5;
+            double ex = gn[0] - u1 * gn[2];
+            double ey = gn[1] - v1 * gn[2];
+            double k2 = a * a / (4.0 * fx * fy);
+            double dP = ex * (-a * T / (4.0 * fy));
+            double dT = ex * (-a * P / (4.0 * fy)) + gn[2] * k2 * S;
+            double dQ = ey * (-a * S / (4.0 * fx));
+            double dS = ey * (-a * Q / (4.0 * fx)) + gn[2] * k2 * T;
+            grad_depth[i + alpha] += dP + dS;
+            grad_depth[i - alpha] += -dP + dS;
+            grad_depth[i + (int64_t)alpha * W] += dQ + dT;
+            grad_depth[i - (int64_t)alpha * W] += -dQ + dT;
+        }
+    }
+    return ORC_OK;
+}
+
 /* The binary32 threshold of ABS mode, exposed for the closed-form tests. */
 float bno_abs_threshold_f32(float fx, float fy, float tau, int alpha)
 {

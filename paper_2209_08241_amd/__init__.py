@@ -85,6 +85,9 @@ def lib() -> ctypes.CDLL:
         L.bn_variant_supported.restype = ctypes.c_int
         L.bn_status_string.argtypes = [ctypes.c_int]
         L.bn_status_string.restype = ctypes.c_char_p
+        L.bn_normals_vjp.argtypes = [vp, i32, i32, i64, f32, f32, f32, f32,
+                                     ctypes.POINTER(Params), vp, vp, vp]
+        L.bn_normals_vjp.restype = ctypes.c_int
         L.bn_version.argtypes = []
         L.bn_version.restype = ctypes.c_int
         _bind_batch(L)
@@ -108,6 +111,19 @@ def _bind_batch(L) -> None:
     L.bn_batch_run.restype = ctypes.c_int
     L.bn_batch_plan_destroy.argtypes = [vp]
     L.bn_batch_plan_destroy.restype = None
+    L.bn_batch_plan_autotune.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
+    L.bn_batch_plan_autotune.restype = ctypes.c_int
+    L.bn_autotune_plain.argtypes = [i32, i32, ctypes.POINTER(Params), ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_float)]
+    L.bn_autotune_plain.restype = ctypes.c_int
+    L.bn_autotune_save.argtypes = [ctypes.c_char_p]
+    L.bn_autotune_save.restype = ctypes.c_int
+    L.bn_autotune_load.argtypes = [ctypes.c_char_p]
+    L.bn_autotune_load.restype = ctypes.c_int
+    L.bn_autotune_reset.argtypes = []
+    L.bn_autotune_reset.restype = None
+    L.bn_autotune_entries.argtypes = []
+    L.bn_autotune_entries.restype = ctypes.c_int
 
 
 def _status_string(status: int) -> str:
@@ -141,7 +157,7 @@ def _check_depth(depth):
         raise TypeError("depth must be a CUDA (HIP) torch tensor")
     if depth.dtype != torch.float32 or depth.dim() != 2:
         raise TypeError("depth must be a 2-D float32 tensor")
-    if depth.shape[1] > 1 and depth.stride(1) != 1:
+    if depth.numel() > 0 and depth.shape[1] > 1 and depth.stride(1) != 1:
         raise ValueError("depth rows must be contiguous (stride(1) == 1)")
 
 
@@ -261,6 +277,16 @@ class BatchPlan:
             raise BnError(rc, "bn_batch_plan_update")
         self._frames = frames
 
+    def autotune(self, stream=None):
+        """Time 1/2/4/8 workgroups per CU, keep the fastest (runs the plan:
+        counts accumulate).  Returns (workgroups per CU, microseconds)."""
+        best, us = ctypes.c_int32(), ctypes.c_float()
+        rc = lib().bn_batch_plan_autotune(self._h, ctypes.c_void_p(_stream_handle(stream)),
+                                          ctypes.byref(best), ctypes.byref(us))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_batch_plan_autotune")
+        return best.value, us.value
+
     def info(self):
         px, tiles, wg = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         rc = lib().bn_batch_plan_info(self._h, ctypes.byref(px), ctypes.byref(tiles),
@@ -281,3 +307,113 @@ class BatchPlan:
         import torch
         torch.cuda.synchronize()
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# autotuning table
+# ---------------------------------------------------------------------------
+
+def autotune_plain(height: int, width: int, alpha: int = 2, mode="rel", tau: float = 4.0):
+    """Time every plain variant on frames of this size; returns (variant, us)."""
+    p = make_params(alpha, mode, tau, 0)
+    best, us = ctypes.c_int32(), ctypes.c_float()
+    rc = lib().bn_autotune_plain(int(height), int(width), ctypes.byref(p), ctypes.byref(best),
+                                 ctypes.byref(us))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_autotune_plain")
+    return best.value, us.value
+
+
+def autotune_save(path: str) -> None:
+    rc = lib().bn_autotune_save(os.fsencode(path))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_autotune_save")
+
+
+def autotune_load(path: str) -> None:
+    rc = lib().bn_autotune_load(os.fsencode(path))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_autotune_load")
+
+
+def autotune_reset() -> None:
+    lib().bn_autotune_reset()
+
+
+def autotune_entries() -> int:
+    return int(lib().bn_autotune_entries())
+
+
+# ---------------------------------------------------------------------------
+# differentiation
+# ---------------------------------------------------------------------------
+
+def normals_vjp(depth, fx, fy, cx, cy, grad_normals, alpha: int = 2, mode="rel",
+                tau: float = 4.0, grad_depth=None, stream=None):
+    """d(sum normals . grad_normals)/d depth with every pixel's code held
+    fixed (bn_normals_vjp).  Returns grad_depth [H, W] float32."""
+    import torch
+    _check_depth(depth)
+    H, W = depth.shape
+    g = grad_normals
+    if not (g.is_cuda and g.dtype == torch.float32 and g.shape == (H, W, 3)):
+        raise ValueError("grad_normals must be a float32 [H, W, 3] device tensor")
+    g = g.contiguous()
+    if grad_depth is None:
+        grad_depth = torch.empty((H, W), dtype=torch.float32, device=depth.device)
+    p = make_params(alpha, mode, tau, 0)
+    stride = depth.stride(0) if H > 0 else W
+    rc = lib().bn_normals_vjp(ctypes.c_void_p(depth.data_ptr()), H, W, stride, fx, fy, cx, cy,
+                              ctypes.byref(p), ctypes.c_void_p(g.data_ptr()),
+                              ctypes.c_void_p(grad_depth.data_ptr()),
+                              ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_normals_vjp")
+    return grad_depth
+
+
+def _normals_function():
+    import torch
+
+    class NormalsFunction(torch.autograd.Function):
+        """normals, mask = f(depth); backward through the hand-written
+        adjoint kernel (codes frozen; the mask output is not differentiable)."""
+
+        @staticmethod
+        def forward(ctx, depth, fx, fy, cx, cy, alpha, mode, tau):
+            n, m, _ = estimate_normals(depth, fx, fy, cx, cy, alpha, mode, tau, want_stats=False)
+            ctx.save_for_backward(depth)
+            ctx.args = (fx, fy, cx, cy, alpha, mode, tau)
+            ctx.mark_non_differentiable(m)
+            return n, m
+
+        @staticmethod
+        def backward(ctx, grad_n, grad_m):
+            (depth,) = ctx.saved_tensors
+            fx, fy, cx, cy, alpha, mode, tau = ctx.args
+            gd = None
+            if ctx.needs_input_grad[0]:
+                gd = normals_vjp(depth, fx, fy, cx, cy, grad_n.float(), alpha, mode, tau)
+            return gd, None, None, None, None, None, None, None
+
+    return NormalsFunction
+
+
+_NormalsFunction = None
+
+
+def normals_with_grad(depth, fx, fy, cx, cy, alpha: int = 2, mode="rel", tau: float = 4.0):
+    """Differentiable estimate_normals: returns (normals, mask); gradients
+    flow to `depth` through bn_normals_vjp."""
+    global _NormalsFunction
+    if _NormalsFunction is None:
+        _NormalsFunction = _normals_function()
+    return _NormalsFunction.apply(depth, float(fx), float(fy), float(cx), float(cy), int(alpha),
+                                  mode, float(tau))
+
+
+def cosine_loss(normals, target, mask, target_mask):
+    """mean over pixels valid in both of (1 - normals . target)."""
+    U = (mask == VALID) & (target_mask == VALID)
+    cos = (normals * target).sum(-1)
+    return (1.0 - cos)[U].sum() / U.sum().clamp(min=1)

@@ -1,0 +1,145 @@
+// Adjoint of the normal map with respect to the depth (vector-Jacobian
+// product), codes held fixed: the mask is piecewise constant in the depth,
+// so its derivative vanishes almost everywhere.
+//
+// For a VALID pixel the output is o/|o| with o = (mx, my, -mz) the scaled
+// vector of Eqs. 10-12 (see bn_device.h), a smooth function of the taps
+// d2..d5 through P = d2-d4, S = d2+d4, Q = d3-d5, T = d3+d5.  With
+// g_o = (g - (n.g) n)/|o| the gradient with respect to o,
+//   dP = g_ox fx T - g_oz xc T          dQ = g_oy fy S - g_oz yc S
+//   dS = g_oy fy Q - g_oz (yc Q + a T)  dT = g_ox fx P - g_oz (xc P + a S)
+// and the taps receive  d2: dP + dS,  d4: -dP + dS,  d3: dQ + dT,
+// d5: -dQ + dT.
+//
+// Gather form: a workgroup owns a 64 x 16 tile of output depths.  It stages
+// the depth of the tile plus a 2-alpha ring in LDS, evaluates every pixel of
+// the tile plus an alpha ring once (its code and its four tap gradients, in
+// LDS), and each output depth then sums the four contributions that land on
+// it, in a fixed order.  No atomics: the result is deterministic.
+#include "bn_device.h"
+#include "bn_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace bn {
+
+constexpr int kAdjTX = 64;
+constexpr int kAdjTY = 16;
+
+template <int A>
+__global__ __launch_bounds__(kBlock) void k_vjp(FrameArgs f, const float *__restrict__ gn,
+                                                float *__restrict__ gd, uint32_t tiles_x) {
+    constexpr int DX = kAdjTX + 4 * A, DY = kAdjTY + 4 * A;  // depth tile
+    constexpr int GX = kAdjTX + 2 * A, GY = kAdjTY + 2 * A;  // evaluated pixels
+    __shared__ float s_d[DY * DX];
+    __shared__ float s_g[4][GY * GX];  // tap gradients: to d2, d3, d4, d5
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (int)(tile % tiles_x) * kAdjTX;
+    const int y0 = (int)(tile / tiles_x) * kAdjTY;
+    for (int k = threadIdx.x; k < DY * DX; k += kBlock) {
+        const int X = x0 - 2 * A + k % DX;
+        const int Y = y0 - 2 * A + k / DX;
+        float v = 0.f;
+        if (X >= 0 && X < f.W && Y >= 0 && Y < f.H) v = f.depth[(int64_t)Y * f.stride + X];
+        s_d[k] = v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < GY * GX; k += kBlock) {
+        const int c = k % GX, r = k / GX;
+        const int X = x0 - A + c;
+        const int Y = y0 - A + r;
+        float g2 = 0.f, g3 = 0.f, g4 = 0.f, g5 = 0.f;
+        if (X >= 0 && X < f.W && Y >= 0 && Y < f.H) {
+            const int dc = c + A, dr = r + A;  // position in the depth tile
+            const float d1 = s_d[dr * DX + dc];
+            const float d2 = s_d[dr * DX + dc + A];
+            const float d4 = s_d[dr * DX + dc - A];
+            const float d3 = s_d[(dr + A) * DX + dc];
+            const float d5 = s_d[(dr - A) * DX + dc];
+            const bool inside = (X >= A) & (X + A < f.W) & (Y >= A) & (Y + A < f.H);
+            const float xc = (float)X - f.cx;
+            const float yc = (float)Y - f.cy;
+            const PixelTerms t = eval_terms(inside, d1, d2, d3, d4, d5, xc, yc, f);
+            if (t.code == BN_VALID) {
+                const float *g = gn + 3 * ((int64_t)Y * f.W + X);
+                const float inv = __builtin_amdgcn_rsqf(t.q);
+                const float nx = t.mx * inv, ny = t.my * inv, nz = -(t.mz * inv);
+                const float gx = g[0], gy = g[1], gz = g[2];
+                const float dot = (nx * gx + ny * gy) + nz * gz;
+                const float ox = (gx - dot * nx) * inv;
+                const float oy = (gy - dot * ny) * inv;
+                const float oz = (gz - dot * nz) * inv;
+                const float dP = ox * f.fx * t.T - oz * xc * t.T;
+                const float dQ = oy * f.fy * t.S - oz * yc * t.S;
+                const float dS = oy * f.fy * t.Q - oz * (yc * t.Q + f.af * t.T);
+                const float dT = ox * f.fx * t.P - oz * (xc * t.P + f.af * t.S);
+                g2 = dP + dS;
+                g4 = dS - dP;
+                g3 = dQ + dT;
+                g5 = dT - dQ;
+            }
+        }
+        s_g[0][k] = g2;
+        s_g[1][k] = g3;
+        s_g[2][k] = g4;
+        s_g[3][k] = g5;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kAdjTX * kAdjTY; k += kBlock) {
+        const int c = k % kAdjTX, r = k / kAdjTX;
+        const int X = x0 + c, Y = y0 + r;
+        if (X >= f.W || Y >= f.H) continue;
+        const int gc = c + A, gr = r + A;  // this depth's own position among evaluated pixels
+        // it is tap 2 of (X-A, Y), tap 4 of (X+A, Y), tap 3 of (X, Y-A), tap 5 of (X, Y+A)
+        const float v = ((s_g[0][gr * GX + gc - A] + s_g[2][gr * GX + gc + A]) +
+                         s_g[1][(gr - A) * GX + gc]) +
+                        s_g[3][(gr + A) * GX + gc];
+        gd[(int64_t)Y * f.W + X] = v;
+    }
+}
+
+typedef void (*VjpFn)(FrameArgs, const float *, float *, uint32_t);
+
+static VjpFn vjp_kernel(int a) {
+    switch (a) {
+        case 1: return k_vjp<1>;
+        case 2: return k_vjp<2>;
+        case 3: return k_vjp<3>;
+        case 4: return k_vjp<4>;
+        case 5: return k_vjp<5>;
+        case 6: return k_vjp<6>;
+        case 7: return k_vjp<7>;
+        case 8: return k_vjp<8>;
+    }
+    return nullptr;
+}
+
+}  // namespace bn
+
+using namespace bn;
+
+extern "C" int bn_normals_vjp(const float *depth, int32_t height, int32_t width,
+                              int64_t depth_stride, float fx, float fy, float cx, float cy,
+                              const bn_params *params, const float *grad_normals,
+                              float *grad_depth, void *stream) {
+    int rc = check_params_args(params);
+    if (rc != BN_OK) return rc;
+    if (params->variant != VAR_AUTO) return BN_ERR_UNSUPPORTED;
+    // the frame checks of the forward entry point; the gradients stand in
+    // for its outputs
+    rc = check_frame_args(depth, height, width, depth_stride, fx, fy, cx, cy,
+                          grad_normals ? grad_normals : nullptr,
+                          reinterpret_cast<const uint8_t *>(grad_depth));
+    if (rc != BN_OK) return rc;
+    if (height == 0 || width == 0) return BN_OK;
+    VjpFn fn = vjp_kernel(params->alpha);
+    if (!fn) return BN_ERR_UNSUPPORTED;
+    FrameArgs f;
+    fill_frame_args(f, depth, height, width, depth_stride, fx, fy, cx, cy, params, nullptr,
+                    nullptr, nullptr, 1);
+    const uint32_t tx = ((uint32_t)width + kAdjTX - 1) / kAdjTX;
+    const uint32_t ty = ((uint32_t)height + kAdjTY - 1) / kAdjTY;
+    hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(kBlock), 0, (hipStream_t)stream, f, grad_normals,
+                       grad_depth, tx);
+    return hipGetLastError() == hipSuccess ? BN_OK : BN_ERR_DEVICE;
+}

@@ -1,0 +1,266 @@
+// Autotuner: measured choice of the plain kernel variant per (alpha, frame
+// size class) and of the persistent grid (workgroups per compute unit) of
+// batch plans.  Choices live in a process-wide table keyed by the GPU
+// architecture name; the table can be saved to and loaded from a small JSON
+// file, and is loaded from $BN_AUTOTUNE_CACHE on first use when that is set.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bn_internal.h"
+#include "bnormals.h"
+
+namespace bn {
+
+namespace {
+
+struct Entry {
+    std::string arch;
+    int kind;   // 0 plain, 1 batch
+    int alpha;
+    int cls;    // bit length of the pixel count
+    int value;  // variant id or workgroups per CU
+    float us;
+};
+
+std::mutex g_mu;
+std::vector<Entry> g_table;
+bool g_env_loaded = false;
+
+std::string current_arch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+int bit_length(uint64_t v) {
+    int n = 0;
+    while (v) {
+        ++n;
+        v >>= 1;
+    }
+    return n;
+}
+
+int load_locked(const char *path);
+
+void ensure_env_loaded_locked() {
+    if (g_env_loaded) return;
+    g_env_loaded = true;
+    const char *p = std::getenv("BN_AUTOTUNE_CACHE");
+    if (p && *p) (void)load_locked(p);
+}
+
+void put_locked(const Entry &e) {
+    for (auto &x : g_table) {
+        if (x.arch == e.arch && x.kind == e.kind && x.alpha == e.alpha && x.cls == e.cls) {
+            x = e;
+            return;
+        }
+    }
+    g_table.push_back(e);
+}
+
+const Entry *find_locked(const std::string &arch, int kind, int alpha, int cls) {
+    for (const auto &x : g_table)
+        if (x.arch == arch && x.kind == kind && x.alpha == alpha && x.cls == cls) return &x;
+    return nullptr;
+}
+
+// Minimal reader for the file written by save_locked: one entry object per
+// line, fields in a fixed order.
+int load_locked(const char *path) {
+    FILE *fh = std::fopen(path, "r");
+    if (!fh) return BN_ERR_INVALID_ARG;
+    char line[512];
+    while (std::fgets(line, sizeof(line), fh)) {
+        char arch[64], kind[16];
+        int alpha, cls, value;
+        float us;
+        if (std::sscanf(line,
+                        " {\"arch\": \"%63[^\"]\", \"kind\": \"%15[^\"]\", \"alpha\": %d, "
+                        "\"class\": %d, \"value\": %d, \"us\": %f}",
+                        arch, kind, &alpha, &cls, &value, &us) == 6) {
+            Entry e{arch, std::strcmp(kind, "batch") == 0 ? 1 : 0, alpha, cls, value, us};
+            put_locked(e);
+        }
+    }
+    std::fclose(fh);
+    return BN_OK;
+}
+
+int save_locked(const char *path) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *fh = std::fopen(tmp.c_str(), "w");
+    if (!fh) return BN_ERR_INVALID_ARG;
+    std::fprintf(fh, "{\"entries\": [\n");
+    for (size_t i = 0; i < g_table.size(); ++i) {
+        const Entry &e = g_table[i];
+        std::fprintf(fh,
+                     " {\"arch\": \"%s\", \"kind\": \"%s\", \"alpha\": %d, \"class\": %d, "
+                     "\"value\": %d, \"us\": %.3f}%s\n",
+                     e.arch.c_str(), e.kind ? "batch" : "plain", e.alpha, e.cls, e.value, e.us,
+                     i + 1 < g_table.size() ? "," : "");
+    }
+    std::fprintf(fh, "]}\n");
+    std::fclose(fh);
+    return std::rename(tmp.c_str(), path) == 0 ? BN_OK : BN_ERR_INVALID_ARG;
+}
+
+}  // namespace
+
+int tuned_plain_variant(int alpha, uint64_t pixels) {
+    std::lock_guard<std::mutex> g(g_mu);
+    ensure_env_loaded_locked();
+    if (g_table.empty()) return 0;
+    const Entry *e = find_locked(current_arch(), 0, alpha, bit_length(pixels));
+    return e ? e->value : 0;
+}
+
+int tuned_batch_blocks_per_cu(int alpha, uint64_t pixels) {
+    std::lock_guard<std::mutex> g(g_mu);
+    ensure_env_loaded_locked();
+    if (g_table.empty()) return 0;
+    const Entry *e = find_locked(current_arch(), 1, alpha, bit_length(pixels));
+    return e ? e->value : 0;
+}
+
+void record_tuning(int kind, int alpha, uint64_t pixels, int value, float us) {
+    std::lock_guard<std::mutex> g(g_mu);
+    ensure_env_loaded_locked();
+    put_locked(Entry{current_arch(), kind, alpha, bit_length(pixels), value, us});
+    const char *p = std::getenv("BN_AUTOTUNE_CACHE");
+    if (p && *p) (void)save_locked(p);
+}
+
+}  // namespace bn
+
+using namespace bn;
+
+namespace {
+
+struct Scratch {
+    std::vector<void *> ptrs;
+    ~Scratch() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    void *alloc(size_t bytes) {
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return p;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int bn_autotune_plain(int32_t height, int32_t width, const bn_params *params, int32_t *best_variant,
+                      float *best_us) {
+    int rc = check_params_args(params);
+    if (rc != BN_OK) return rc;
+    if (height < 1 || width < 1 || width > BN_MAX_WIDTH ||
+        (int64_t)height * width > BN_MAX_PIXELS)
+        return BN_ERR_INVALID_ARG;
+    const uint64_t px = (uint64_t)height * (uint64_t)width;
+    // a ring of distinct frames of about 512 MiB, so that timings see HBM
+    const uint64_t per = px * 17 + sizeof(bn_frame_stats);
+    int ring = (int)((512ull << 20) / per);
+    if (ring < 1) ring = 1;
+    if (ring > 64) ring = 64;
+    Scratch s;
+    std::vector<float *> d(ring), n(ring);
+    std::vector<uint8_t *> m(ring);
+    bn_frame_stats *st = static_cast<bn_frame_stats *>(s.alloc(sizeof(bn_frame_stats) * ring));
+    if (!st) return BN_ERR_OOM;
+    for (int k = 0; k < ring; ++k) {
+        d[k] = static_cast<float *>(s.alloc(px * 4));
+        n[k] = static_cast<float *>(s.alloc(px * 12));
+        m[k] = static_cast<uint8_t *>(s.alloc(px));
+        if (!d[k] || !n[k] || !m[k]) return BN_ERR_OOM;
+        // a fronto plane at 1.5 m: every pixel takes the full arithmetic path
+        const float v = 1.5f;
+        uint32_t bits;
+        std::memcpy(&bits, &v, 4);
+        if (hipMemsetD32(d[k], (int)bits, px) != hipSuccess) return BN_ERR_DEVICE;
+    }
+    if (hipMemset(st, 0, sizeof(bn_frame_stats) * ring) != hipSuccess) return BN_ERR_DEVICE;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return BN_ERR_DEVICE;
+    const float cx = 0.5f * (float)(width - 1), cy = 0.5f * (float)(height - 1);
+    const float f = 525.0f * (float)width / 640.0f;
+    int best = 0;
+    float best_t = 1e30f;
+    for (int v = 1; v <= (int)VAR_COUNT; ++v) {
+        bn_params p = *params;
+        p.variant = (uint32_t)v;
+        if (!bn_variant_supported(v, d[0], height, width, width, n[0], m[0])) continue;
+        const int reps = ring * ((px < (1u << 20)) ? 8 : 3);
+        bool ok = true;
+        for (int k = 0; k < ring && ok; ++k)  // warm-up
+            ok = bn_estimate_normals(d[k], height, width, width, f, f, cx, cy, &p, n[k], m[k],
+                                     st + k, nullptr) == BN_OK;
+        if (!ok) continue;
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps; ++r) {
+            const int k = r % ring;
+            (void)bn_estimate_normals(d[k], height, width, width, f, f, cx, cy, &p, n[k], m[k],
+                                      st + k, nullptr);
+        }
+        (void)hipEventRecord(e1, nullptr);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return BN_ERR_DEVICE;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const float us = 1000.f * ms / (float)reps;
+        if (us < best_t) {
+            best_t = us;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!best) return BN_ERR_UNSUPPORTED;
+    record_tuning(0, params->alpha, px, best, best_t);
+    if (best_variant) *best_variant = best;
+    if (best_us) *best_us = best_t;
+    return BN_OK;
+}
+
+int bn_autotune_save(const char *path) {
+    if (!path) return BN_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(g_mu);
+    return save_locked(path);
+}
+
+int bn_autotune_load(const char *path) {
+    if (!path) return BN_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(g_mu);
+    g_env_loaded = true;
+    return load_locked(path);
+}
+
+void bn_autotune_reset(void) {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_table.clear();
+    g_env_loaded = true;
+}
+
+int bn_autotune_entries(void) {
+    std::lock_guard<std::mutex> g(g_mu);
+    return (int)g_table.size();
+}
+
+}  // extern "C"

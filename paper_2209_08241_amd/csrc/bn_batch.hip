@@ -2,14 +2,22 @@
 // a persistent kernel, instantiated once as a HIP graph.
 //
 // Frames of different sizes are cut into tiles of 256 work items (1024
-// pixels for vector frames).  The grid is sized to the machine (8 workgroups
-// per compute unit, all resident at once); workgroup b owns the contiguous
-// tile range [b*chunk, (b+1)*chunk) of the concatenated tile sequence, so the
-// load is balanced whatever the frame mix, a workgroup touches few frames
-// (one count reduction per frame segment), and - through the XCD-contiguous
-// numbering of workgroups - neighbouring tiles, which share stencil rows,
-// are processed by the same XCD.  The frame descriptors live in device
-// memory, so a plan's graph is replayed unchanged when the frames change.
+// pixels for vector frames).  Workgroup b owns the contiguous tile range
+// [b*chunk, (b+1)*chunk) of the concatenated tile sequence, so the load is
+// balanced whatever the frame mix, a workgroup touches few frames (one count
+// reduction per frame segment), and - through the XCD-contiguous numbering
+// of workgroups - neighbouring tiles, which share stencil rows, are
+// processed by the same XCD.  Two grid shapes, picked by the autotuner:
+//   * flat (default): one tile per workgroup, as many workgroups as tiles;
+//     a workgroup retires with its stores still in flight and the
+//     dispatcher refills the compute unit at once;
+//   * persistent: k workgroups per compute unit, all resident, each looping
+//     over its chunk.  On gfx9 one counter tracks loads and stores, so a
+//     wait for the next tile's loads also waits for the previous tile's
+//     stores; this shape wins only when launch work dominates.
+// The frame descriptors live in device memory, so a plan's graph is
+// replayed as is when the frames change (the grid of the flat shape is
+// updated in place).
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -37,23 +45,13 @@ struct BatchHeader {
     uint32_t pad;
 };
 
-// Index of the frame that holds tile t: the last frame whose tile_begin is
-// <= t (frames without tiles share their tile_begin with the next frame).
-__device__ __forceinline__ uint32_t find_frame(const BatchFrame *fr, uint32_t nf, uint32_t t) {
-    uint32_t lo = 0, hi = nf;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (fr[mid].tile_begin <= t)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
+// tile_frame[t] is the index of the frame that holds tile t, so that a
+// workgroup finds its first frame with one load (a search over the frame
+// descriptors is a chain of dependent loads, long next to a 1024-pixel tile).
 template <int A>
 __global__ __launch_bounds__(kBlock) void k_batch(const BatchHeader *__restrict__ hdr,
-                                                  const BatchFrame *__restrict__ frames) {
+                                                  const BatchFrame *__restrict__ frames,
+                                                  const uint32_t *__restrict__ tile_frame) {
     __shared__ TileLds lds;
     const uint32_t T = hdr->ntiles;
     const uint32_t c = hdr->chunk;
@@ -62,8 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchHeader *__restrict_
     uint32_t t = blk * c;
     if (c == 0 || t >= T) return;  // uniform: this workgroup has no tiles
     const uint32_t tend = min(t + c, T);
-    uint32_t fi = find_frame(frames, nf, t);
-    bool first = true;
+    uint32_t fi = tile_frame[t];
     while (t < tend && fi < nf) {
         const FrameArgs f = frames[fi].a;
         const uint32_t tb = frames[fi].tile_begin;
@@ -71,11 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchHeader *__restrict_
         const bool vec = frames[fi].vec != 0;
         const uint32_t seg_end = min(tend, tb + nt);
         uint32_t cv = 0, cb = 0;
-        for (; t < seg_end; ++t) {
-            if (!first) __syncthreads();  // LDS reuse
-            first = false;
-            run_tile<A>(f, vec, t - tb, lds, cv, cb);
-        }
+        for (; t < seg_end; ++t) run_tile<A>(f, vec, t - tb, lds, cv, cb);
         if (f.stats) {
             // the frame's parts are the workgroups whose chunks meet it
             const uint32_t b_first = tb / c;
@@ -88,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchHeader *__restrict_
     }
 }
 
-typedef void (*BatchKernelFn)(const BatchHeader *, const BatchFrame *);
+typedef void (*BatchKernelFn)(const BatchHeader *, const BatchFrame *, const uint32_t *);
 
 static BatchKernelFn batch_kernel(int alpha) {
     switch (alpha) {
@@ -111,50 +104,87 @@ using namespace bn;
 struct bn_batch_plan {
     int device = -1;
     bn_params params{};
-    int32_t capacity = 0;
+    int32_t capacity = 0;          // frames
+    uint64_t tile_capacity = 0;    // entries of the tile -> frame table
+    int cus = 0;
+    uint32_t blocks_per_cu = 0;    // 0: flat grid
     uint32_t grid = 0;
-    void *dbuf = nullptr;            // BatchHeader followed by BatchFrame[capacity]
-    size_t table_bytes = 0;
-    void *staging[2] = {nullptr, nullptr};  // pinned host copies for updates
+    size_t buf_bytes = 0;
+    // device buffer and two pinned host images of it:
+    //   BatchHeader | BatchFrame[capacity] | uint32 tile_frame[tile_capacity]
+    void *dbuf = nullptr;
+    void *staging[2] = {nullptr, nullptr};
     hipEvent_t staged[2] = {nullptr, nullptr};
-    int next = 0;
+    int next = 0;                  // staging copy the next update writes
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node = nullptr;
+    BatchKernelFn fn = nullptr;
     uint64_t total_tiles = 0;
     uint64_t total_pixels = 0;
 };
 
 namespace {
 
-constexpr uint32_t kBlocksPerCU = 8;
+constexpr uint32_t kFlat = 0;  // blocks_per_cu value of the flat shape
 
-// Host image of the descriptor table for `frames`; returns a bn status.
-int build_table(const bn_frame *frames, int32_t n, const bn_params *p, uint32_t grid,
-                void *out, uint64_t *tiles_out, uint64_t *pixels_out) {
-    auto *hdr = static_cast<BatchHeader *>(out);
-    auto *fr = reinterpret_cast<BatchFrame *>(hdr + 1);
-    uint64_t tiles = 0, pixels = 0;
+size_t table_offset(int32_t capacity) {
+    return sizeof(BatchHeader) + sizeof(BatchFrame) * (size_t)capacity;
+}
+
+size_t buffer_bytes(int32_t capacity, uint64_t tile_capacity) {
+    return table_offset(capacity) + sizeof(uint32_t) * (size_t)tile_capacity;
+}
+
+// Validate the frames; total tiles and pixels.
+int count_frames(const bn_frame *frames, int32_t n, uint64_t *tiles, uint64_t *pixels) {
+    uint64_t t = 0, px = 0;
     for (int32_t k = 0; k < n; ++k) {
         const bn_frame &s = frames[k];
         int rc = check_frame_args(s.depth, s.height, s.width, s.depth_stride, s.fx, s.fy, s.cx,
                                   s.cy, s.normals, s.mask);
         if (rc != BN_OK) return rc;
+        if (s.height > 0 && s.width > 0) {
+            const bool vec = vec4_layout(s.depth, s.width, s.depth_stride, s.normals, s.mask);
+            const uint64_t items = (uint64_t)s.height * (uint64_t)(vec ? s.width / 4 : s.width);
+            t += (items + kBlock - 1) / kBlock;
+            px += (uint64_t)s.height * (uint64_t)s.width;
+        }
+    }
+    if (t > 0x7fffffffull) return BN_ERR_UNSUPPORTED;
+    *tiles = t;
+    *pixels = px;
+    return BN_OK;
+}
+
+uint32_t grid_for(uint64_t tiles, int cus, uint32_t blocks_per_cu) {
+    if (blocks_per_cu == kFlat) return tiles ? (uint32_t)tiles : 1u;
+    return (uint32_t)cus * blocks_per_cu;
+}
+
+// Host image of the descriptors of `frames` (already validated) in `base`.
+int build_table(const bn_frame *frames, int32_t n, const bn_params *p, int32_t capacity,
+                uint32_t grid, void *base) {
+    auto *hdr = static_cast<BatchHeader *>(base);
+    auto *fr = reinterpret_cast<BatchFrame *>(hdr + 1);
+    auto *tf = reinterpret_cast<uint32_t *>(static_cast<char *>(base) + table_offset(capacity));
+    uint64_t tiles = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const bn_frame &s = frames[k];
         const bool vec = vec4_layout(s.depth, s.width, s.depth_stride, s.normals, s.mask);
         BatchFrame b;
         std::memset(&b, 0, sizeof(b));
+        uint64_t nt = 0;
         if (s.height > 0 && s.width > 0) {
             fill_frame_args(b.a, s.depth, s.height, s.width, s.depth_stride, s.fx, s.fy, s.cx,
                             s.cy, p, s.normals, s.mask, s.stats, vec ? 4 : 1);
+            nt = ((uint64_t)b.a.nitems + kBlock - 1) / kBlock;
         }
-        const uint64_t nt = (s.height > 0 && s.width > 0)
-                                ? ((uint64_t)b.a.nitems + kBlock - 1) / kBlock
-                                : 0;
         b.tile_begin = (uint32_t)tiles;
         b.ntiles = (uint32_t)nt;
         b.vec = vec ? 1u : 0u;
+        for (uint64_t t = 0; t < nt; ++t) tf[tiles + t] = (uint32_t)k;
         tiles += nt;
-        pixels += (uint64_t)s.height * (uint64_t)s.width;
-        if (tiles > 0xFFF00000ull) return BN_ERR_UNSUPPORTED;
         fr[k] = b;
     }
     hdr->nframes = (uint32_t)n;
@@ -162,8 +192,58 @@ int build_table(const bn_frame *frames, int32_t n, const bn_params *p, uint32_t 
     hdr->chunk = tiles ? (uint32_t)((tiles + grid - 1) / grid) : 0;
     hdr->pad = 0;
     if (hdr->chunk > 4096) return BN_ERR_UNSUPPORTED;  // parts stay below 2^22 pixels
-    *tiles_out = tiles;
-    *pixels_out = pixels;
+    return BN_OK;
+}
+
+hipKernelNodeParams node_params(bn_batch_plan *pl, void **args) {
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.func = reinterpret_cast<void *>(pl->fn);
+    kp.gridDim = dim3(pl->grid);
+    kp.blockDim = dim3(kBlock);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return kp;
+}
+
+// Kernel node parameters (buffer pointers and grid) into the graph, or a
+// fresh graph when none exists yet.
+int refresh_node(bn_batch_plan *pl) {
+    const BatchHeader *d_hdr = static_cast<const BatchHeader *>(pl->dbuf);
+    const BatchFrame *d_frames = reinterpret_cast<const BatchFrame *>(d_hdr + 1);
+    const uint32_t *d_tf = reinterpret_cast<const uint32_t *>(
+        static_cast<const char *>(pl->dbuf) + table_offset(pl->capacity));
+    void *args[3] = {(void *)&d_hdr, (void *)&d_frames, (void *)&d_tf};
+    hipKernelNodeParams kp = node_params(pl, args);
+    if (!pl->exec) {
+        if (hipGraphCreate(&pl->graph, 0) != hipSuccess ||
+            hipGraphAddKernelNode(&pl->node, pl->graph, nullptr, 0, &kp) != hipSuccess ||
+            hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess)
+            return BN_ERR_DEVICE;
+        return BN_OK;
+    }
+    return hipGraphExecKernelNodeSetParams(pl->exec, pl->node, &kp) == hipSuccess
+               ? BN_OK
+               : BN_ERR_DEVICE;
+}
+
+void free_buffers(bn_batch_plan *pl) {
+    for (int k = 0; k < 2; ++k) {
+        if (pl->staging[k]) (void)hipHostFree(pl->staging[k]);
+        pl->staging[k] = nullptr;
+    }
+    if (pl->dbuf) (void)hipFree(pl->dbuf);
+    pl->dbuf = nullptr;
+}
+
+int alloc_buffers(bn_batch_plan *pl, uint64_t tile_capacity) {
+    pl->tile_capacity = tile_capacity;
+    pl->buf_bytes = buffer_bytes(pl->capacity, tile_capacity);
+    for (int k = 0; k < 2; ++k)
+        if (hipHostMalloc(&pl->staging[k], pl->buf_bytes, hipHostMallocDefault) != hipSuccess)
+            return BN_ERR_OOM;
+    if (hipMalloc(&pl->dbuf, pl->buf_bytes) != hipSuccess) return BN_ERR_OOM;
     return BN_OK;
 }
 
@@ -174,12 +254,25 @@ void free_plan(bn_batch_plan *pl) {
             (void)hipEventSynchronize(pl->staged[k]);
             (void)hipEventDestroy(pl->staged[k]);
         }
-        if (pl->staging[k]) (void)hipHostFree(pl->staging[k]);
     }
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
-    if (pl->dbuf) (void)hipFree(pl->dbuf);
+    free_buffers(pl);
     delete pl;
+}
+
+// Write `frames` into the staging copy `k` and send it to the device on
+// `stream` (header, descriptors and the used part of the tile table).
+int upload(bn_batch_plan *pl, const bn_frame *frames, int32_t n, int k, hipStream_t stream,
+           uint64_t tiles) {
+    int rc = build_table(frames, n, &pl->params, pl->capacity, pl->grid, pl->staging[k]);
+    if (rc != BN_OK) return rc;
+    const size_t bytes = table_offset(pl->capacity) + sizeof(uint32_t) * (size_t)tiles;
+    if (hipMemcpyAsync(pl->dbuf, pl->staging[k], bytes, hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipEventRecord(pl->staged[k], stream) != hipSuccess)
+        return BN_ERR_DEVICE;
+    return BN_OK;
 }
 
 }  // namespace
@@ -196,11 +289,15 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
     if (params->variant != VAR_AUTO) return BN_ERR_UNSUPPORTED;
     BatchKernelFn fn = batch_kernel(params->alpha);
     if (!fn) return BN_ERR_UNSUPPORTED;
+    uint64_t tiles = 0, pixels = 0;
+    rc = count_frames(frames_host, n_frames, &tiles, &pixels);
+    if (rc != BN_OK) return rc;
 
     bn_batch_plan *pl = new (std::nothrow) bn_batch_plan();
     if (!pl) return BN_ERR_OOM;
     pl->params = *params;
     pl->capacity = n_frames;
+    pl->fn = fn;
     if (hipGetDevice(&pl->device) != hipSuccess) {
         free_plan(pl);
         return BN_ERR_DEVICE;
@@ -210,51 +307,32 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
             hipSuccess ||
         cus <= 0)
         cus = 256;
-    pl->grid = (uint32_t)cus * kBlocksPerCU;
-    pl->table_bytes = sizeof(BatchHeader) + sizeof(BatchFrame) * (size_t)n_frames;
-
+    pl->cus = cus;
+    // the grid shape tuned for this alpha and batch size class, if recorded
+    // (the table stores the flat shape as -1)
+    const int tuned = tuned_batch_blocks_per_cu(params->alpha, pixels);
+    pl->blocks_per_cu = tuned > 0 ? (uint32_t)tuned : kFlat;
+    pl->grid = grid_for(tiles, cus, pl->blocks_per_cu);
+    pl->total_tiles = tiles;
+    pl->total_pixels = pixels;
     for (int k = 0; k < 2; ++k) {
-        if (hipHostMalloc(&pl->staging[k], pl->table_bytes, hipHostMallocDefault) != hipSuccess ||
-            hipEventCreateWithFlags(&pl->staged[k], hipEventDisableTiming) != hipSuccess) {
+        if (hipEventCreateWithFlags(&pl->staged[k], hipEventDisableTiming) != hipSuccess) {
             free_plan(pl);
-            return BN_ERR_OOM;
+            return BN_ERR_DEVICE;
         }
     }
-    rc = build_table(frames_host, n_frames, params, pl->grid, pl->staging[0], &pl->total_tiles,
-                     &pl->total_pixels);
+    rc = alloc_buffers(pl, tiles > 0 ? tiles : 1);
+    if (rc == BN_OK) rc = build_table(frames_host, n_frames, params, pl->capacity, pl->grid,
+                                      pl->staging[0]);
+    if (rc == BN_OK &&
+        hipMemcpy(pl->dbuf, pl->staging[0], pl->buf_bytes, hipMemcpyHostToDevice) != hipSuccess)
+        rc = BN_ERR_DEVICE;
+    if (rc == BN_OK) rc = refresh_node(pl);
     if (rc != BN_OK) {
         free_plan(pl);
         return rc;
     }
-    if (hipMalloc(&pl->dbuf, pl->table_bytes) != hipSuccess) {
-        free_plan(pl);
-        return BN_ERR_OOM;
-    }
-    if (hipMemcpy(pl->dbuf, pl->staging[0], pl->table_bytes, hipMemcpyHostToDevice) !=
-        hipSuccess) {
-        free_plan(pl);
-        return BN_ERR_DEVICE;
-    }
-
-    // one kernel node: the persistent launch over the whole batch
-    const BatchHeader *d_hdr = static_cast<const BatchHeader *>(pl->dbuf);
-    const BatchFrame *d_frames = reinterpret_cast<const BatchFrame *>(d_hdr + 1);
-    void *args[2] = {(void *)&d_hdr, (void *)&d_frames};
-    hipKernelNodeParams kp;
-    std::memset(&kp, 0, sizeof(kp));
-    kp.func = reinterpret_cast<void *>(fn);
-    kp.gridDim = dim3(pl->grid);
-    kp.blockDim = dim3(kBlock);
-    kp.sharedMemBytes = 0;
-    kp.kernelParams = args;
-    kp.extra = nullptr;
-    hipGraphNode_t node;
-    if (hipGraphCreate(&pl->graph, 0) != hipSuccess ||
-        hipGraphAddKernelNode(&node, pl->graph, nullptr, 0, &kp) != hipSuccess ||
-        hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess) {
-        free_plan(pl);
-        return BN_ERR_DEVICE;
-    }
+    pl->next = 1;  // staging[0] holds the current table
     *out_plan = pl;
     return BN_OK;
 }
@@ -263,21 +341,35 @@ int bn_batch_plan_update(bn_batch_plan *plan, const bn_frame *frames_host, int32
                          void *stream) {
     if (!plan || !frames_host || n_frames < 1) return BN_ERR_INVALID_ARG;
     if (n_frames > plan->capacity) return BN_ERR_UNSUPPORTED;
-    const int k = plan->next;
-    // the staging buffer may still feed the copy issued two updates ago
-    if (hipEventSynchronize(plan->staged[k]) != hipSuccess) return BN_ERR_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
     uint64_t tiles = 0, pixels = 0;
-    int rc = build_table(frames_host, n_frames, &plan->params, plan->grid, plan->staging[k],
-                         &tiles, &pixels);
+    int rc = count_frames(frames_host, n_frames, &tiles, &pixels);
     if (rc != BN_OK) return rc;
-    const size_t bytes = sizeof(BatchHeader) + sizeof(BatchFrame) * (size_t)n_frames;
-    if (hipMemcpyAsync(plan->dbuf, plan->staging[k], bytes, hipMemcpyHostToDevice,
-                       (hipStream_t)stream) != hipSuccess ||
-        hipEventRecord(plan->staged[k], (hipStream_t)stream) != hipSuccess)
-        return BN_ERR_DEVICE;
+    const uint32_t grid = grid_for(tiles, plan->cus, plan->blocks_per_cu);
+    if (tiles > 0 && (tiles + grid - 1) / grid > 4096) return BN_ERR_UNSUPPORTED;
+    bool repoint = false;
+    if (tiles > plan->tile_capacity) {
+        // a larger tile table: wait for every use of the old buffers first
+        if (hipStreamSynchronize(s) != hipSuccess ||
+            hipEventSynchronize(plan->staged[0]) != hipSuccess ||
+            hipEventSynchronize(plan->staged[1]) != hipSuccess)
+            return BN_ERR_DEVICE;
+        free_buffers(plan);
+        rc = alloc_buffers(plan, tiles + tiles / 4);
+        if (rc != BN_OK) return rc;
+        repoint = true;
+    }
+    const int k = plan->next;
+    // the staging copy may still feed the upload issued two updates ago
+    if (hipEventSynchronize(plan->staged[k]) != hipSuccess) return BN_ERR_DEVICE;
+    const uint32_t old_grid = plan->grid;
+    plan->grid = grid;
+    rc = upload(plan, frames_host, n_frames, k, s, tiles);
+    if (rc != BN_OK) return rc;
     plan->next = 1 - k;
     plan->total_tiles = tiles;
     plan->total_pixels = pixels;
+    if (repoint || grid != old_grid) return refresh_node(plan);
     return BN_OK;
 }
 
@@ -292,6 +384,80 @@ int bn_batch_plan_info(const bn_batch_plan *plan, int64_t *n_pixels, int64_t *n_
     if (n_pixels) *n_pixels = (int64_t)plan->total_pixels;
     if (n_tiles) *n_tiles = (int64_t)plan->total_tiles;
     if (n_workgroups) *n_workgroups = (int32_t)plan->grid;
+    return BN_OK;
+}
+
+// Re-grid the plan: the header's chunk (ordered on `stream`) and the
+// launch's workgroup count.  The staging copy written last (index
+// 1 - next) holds the current table.
+static int set_grid(bn_batch_plan *plan, uint32_t blocks_per_cu, hipStream_t stream) {
+    const int last = 1 - plan->next;
+    if (hipEventSynchronize(plan->staged[last]) != hipSuccess) return BN_ERR_DEVICE;
+    auto *hdr = static_cast<BatchHeader *>(plan->staging[last]);
+    const uint32_t grid = grid_for(hdr->ntiles, plan->cus, blocks_per_cu);
+    const uint32_t chunk = hdr->ntiles ? (hdr->ntiles + grid - 1) / grid : 0;
+    if (chunk > 4096) return BN_ERR_UNSUPPORTED;
+    plan->blocks_per_cu = blocks_per_cu;
+    plan->grid = grid;
+    hdr->chunk = chunk;
+    if (hipMemcpyAsync(plan->dbuf, hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipEventRecord(plan->staged[last], stream) != hipSuccess)
+        return BN_ERR_DEVICE;
+    return refresh_node(plan);
+}
+
+int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_blocks_per_cu,
+                           float *best_us) {
+    if (!plan || !plan->exec) return BN_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return BN_ERR_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return BN_ERR_DEVICE;
+    }
+    const uint32_t cands[] = {kFlat, 2, 4, 8};
+    uint32_t best = 0;
+    bool found = false;
+    float best_t = 1e30f;
+    int rc = BN_OK;
+    for (uint32_t c : cands) {
+        rc = set_grid(plan, c, s);
+        if (rc == BN_ERR_UNSUPPORTED) continue;
+        if (rc != BN_OK) break;
+        if (hipGraphLaunch(plan->exec, s) != hipSuccess) {
+            rc = BN_ERR_DEVICE;
+            break;
+        }
+        (void)hipEventRecord(e0, s);
+        const int reps = 3;
+        for (int r = 0; r < reps; ++r) (void)hipGraphLaunch(plan->exec, s);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = BN_ERR_DEVICE;
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const float us = 1000.f * ms / reps;
+        if (us < best_t) {
+            best_t = us;
+            best = c;
+            found = true;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != BN_OK && rc != BN_ERR_UNSUPPORTED) return rc;
+    if (!found) return BN_ERR_UNSUPPORTED;
+    rc = set_grid(plan, best, s);
+    if (rc != BN_OK) return rc;
+    // the table stores the flat shape as -1 (0 means "nothing recorded")
+    record_tuning(1, plan->params.alpha, plan->total_pixels, best == kFlat ? -1 : (int)best,
+                  best_t);
+    if (best_blocks_per_cu) *best_blocks_per_cu = (int32_t)best;
+    if (best_us) *best_us = best_t;
     return BN_OK;
 }
 

@@ -69,8 +69,10 @@ static float abs_threshold(float fx, float fy, float tau, int alpha) {
     return (float)k;
 }
 
-static int pick_variant(const float *depth, int32_t W, int64_t stride, const float *normals,
-                        const uint8_t *mask) {
+static int pick_variant(const float *depth, int32_t H, int32_t W, int64_t stride,
+                        const float *normals, const uint8_t *mask, int alpha) {
+    const int tuned = tuned_plain_variant(alpha, (uint64_t)H * (uint64_t)W);
+    if (tuned > 0 && variant_ok(tuned, depth, W, stride, normals, mask)) return tuned;
     if (vec4_layout(depth, W, stride, normals, mask)) return VAR_VEC4;
     return VAR_SCALAR;
 }
@@ -113,7 +115,7 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width, int64
     if (height == 0 || width == 0) return BN_OK;
     int v = (int)params->variant;
     if (v == VAR_AUTO) {
-        v = pick_variant(depth, width, depth_stride, normals, mask);
+        v = pick_variant(depth, height, width, depth_stride, normals, mask, params->alpha);
     } else if (!variant_ok(v, depth, width, depth_stride, normals, mask)) {
         return BN_ERR_UNSUPPORTED;
     }

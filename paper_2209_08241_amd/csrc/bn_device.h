@@ -57,48 +57,66 @@ __device__ __forceinline__ uint32_t row_of(uint32_t i, double inv_gpr) {
     return (uint32_t)(((double)i + 0.5) * inv_gpr);
 }
 
+// One pixel, keeping the scaled vector and its pieces.  inside: the stencil
+// lies in the image.  Taps d1..d5 as in the stencil of Section 3.1.
+// Branch-free: lanes with bad input compute garbage that the code discards.
+struct PixelTerms {
+    float P, S, Q, T;
+    float mx, my, mz;  // mz = t3 + w, the negated third component of m
+    float q;
+    uint32_t code;
+};
+
+__device__ __forceinline__ PixelTerms eval_terms(bool inside, float d1, float d2, float d3,
+                                                 float d4, float d5, float xc, float yc,
+                                                 const FrameArgs &f) {
+    PixelTerms r;
+    r.P = d2 - d4;
+    r.S = d2 + d4;
+    r.Q = d3 - d5;
+    r.T = d3 + d5;
+    const float a = r.T * r.P;
+    const float b = r.S * r.Q;
+    const float c = r.S * r.T;
+    r.mx = f.fx * a;
+    r.my = f.fy * b;
+    const float xa = xc * a;
+    const float yb = yc * b;
+    const float t3 = xa + yb;
+    const float w = f.af * c;
+    r.mz = t3 + w;
+    const float mx2 = r.mx * r.mx;
+    const float my2 = r.my * r.my;
+    const float mz2 = r.mz * r.mz;
+    r.q = (mx2 + my2) + mz2;
+    const float ww = w * w;
+    const float hrel = f.tt * ww;
+    const float h = f.rel ? hrel : f.hconst;
+    const bool ok = ((inside ? 1u : 0u) & tap_ok(d1) & tap_ok(d2) & tap_ok(d3) & tap_ok(d4) &
+                     tap_ok(d5) & q_ok(r.q)) != 0u;
+    const bool fire = r.q > h;
+    r.code = ok ? (fire ? (uint32_t)BN_BOUNDARY : (uint32_t)BN_VALID) : (uint32_t)BN_INVALID;
+    return r;
+}
+
 struct PixelOut {
     float nx, ny, nz;
     uint32_t code;
 };
 
-// One pixel.  inside: the stencil lies in the image.  Taps d1..d5 as in
-// the stencil of Section 3.1.  Branch-free: lanes with bad input compute
-// garbage that the selects discard.
+// One pixel: its code and, when VALID, the camera-facing unit normal
+// (mx, my, -mz) / sqrt(q); the zero vector otherwise.
 __device__ __forceinline__ PixelOut eval_pixel(bool inside, float d1, float d2, float d3,
                                                float d4, float d5, float xc, float yc,
                                                const FrameArgs &f) {
-    const float P = d2 - d4;
-    const float S = d2 + d4;
-    const float Q = d3 - d5;
-    const float T = d3 + d5;
-    const float a = T * P;
-    const float b = S * Q;
-    const float c = S * T;
-    const float mx = f.fx * a;
-    const float my = f.fy * b;
-    const float xa = xc * a;
-    const float yb = yc * b;
-    const float t3 = xa + yb;
-    const float w = f.af * c;
-    const float mz = t3 + w;
-    const float mx2 = mx * mx;
-    const float my2 = my * my;
-    const float mz2 = mz * mz;
-    const float q = (mx2 + my2) + mz2;
-    const float ww = w * w;
-    const float hrel = f.tt * ww;
-    const float h = f.rel ? hrel : f.hconst;
-    const bool ok = ((inside ? 1u : 0u) & tap_ok(d1) & tap_ok(d2) & tap_ok(d3) & tap_ok(d4) &
-                     tap_ok(d5) & q_ok(q)) != 0u;
-    const bool fire = q > h;
+    const PixelTerms t = eval_terms(inside, d1, d2, d3, d4, d5, xc, yc, f);
     PixelOut o;
-    o.code = ok ? (fire ? (uint32_t)BN_BOUNDARY : (uint32_t)BN_VALID) : (uint32_t)BN_INVALID;
-    const bool valid = ok && !fire;
-    const float inv = __builtin_amdgcn_rsqf(q);
-    o.nx = valid ? mx * inv : 0.0f;
-    o.ny = valid ? my * inv : 0.0f;
-    o.nz = valid ? -(mz * inv) : 0.0f;
+    o.code = t.code;
+    const bool valid = t.code == BN_VALID;
+    const float inv = __builtin_amdgcn_rsqf(t.q);
+    o.nx = valid ? t.mx * inv : 0.0f;
+    o.ny = valid ? t.my * inv : 0.0f;
+    o.nz = valid ? -(t.mz * inv) : 0.0f;
     return o;
 }
 

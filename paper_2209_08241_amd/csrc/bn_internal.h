@@ -37,6 +37,11 @@ void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int
                      float fx, float fy, float cx, float cy, const bn_params *p, float *normals,
                      uint8_t *mask, bn_frame_stats *stats, int px_per_item);
 
+// Autotuning table (bn_autotune.hip): 0 when nothing is recorded.
+int tuned_plain_variant(int alpha, uint64_t pixels);
+int tuned_batch_blocks_per_cu(int alpha, uint64_t pixels);
+void record_tuning(int kind, int alpha, uint64_t pixels, int value, float us);
+
 // Launch one frame with the given variant.  FrameArgs.gpr / nitems /
 // inv_gpr must match the variant's pixels per work item.
 hipError_t launch_plain(int variant, const FrameArgs &f, hipStream_t stream);

@@ -45,7 +45,6 @@ __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
     for (int g = 0; g < G; ++g) {
         const uint32_t tile = blk * G + g;
         if (tile * kBlock >= f.nitems) break;  // uniform over the workgroup
-        if (g > 0) __syncthreads();             // LDS reuse
         run_tile<A>(f, true, tile, lds, cv, cb);
     }
     if (f.stats) block_counts(f.stats, blk, gridDim.x, cv, cb, f.npix);

@@ -2,8 +2,12 @@
 //
 // A tile is kBlock = 256 consecutive work items of one frame, one per
 // thread: 4 consecutive pixels of a row (vector tiles, width % 4 == 0 and
-// 16-byte aligned rows) or 1 pixel (scalar tiles, any layout).  A tile's
-// normals are staged in LDS and written back with contiguous stores.
+// 16-byte aligned rows) or 1 pixel (scalar tiles, any layout).  Each
+// wavefront stages the normals of its 64 work items in its own slice of LDS
+// and writes them back with contiguous stores: a wavefront's LDS accesses
+// execute in program order, so no workgroup barrier is needed - a barrier
+// would also carry a release fence that waits for the previous tile's
+// global stores, serialising the tiles of a persistent workgroup.
 #pragma once
 
 #include "bn_device.h"
@@ -13,10 +17,18 @@
 namespace bn {
 
 // LDS staging area of one tile: 3 float4 (12 floats) per vector work item,
-// or 3 floats per scalar work item.
+// or 3 floats per scalar work item; wavefront w owns v[192w .. 192w+191].
 struct TileLds {
     f4 v[3 * kBlock];
 };
+
+// Orders this wavefront's LDS accesses for the compiler; the hardware
+// already executes them in order.  Emits no wait instruction.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int A>
 struct Win {
@@ -25,10 +37,11 @@ struct Win {
 };
 
 // ---------------------------------------------------------------------------
-// Vector tile, first half: evaluate the group of thread threadIdx.x (pixels
-// 4i .. 4i+3 of the frame, i = tile*256 + t).  Its 12 normal floats go to
-// LDS, its four codes to the mask (one 32-bit store); returns the codes one
-// per byte.  Every lane of the workgroup must call this (DPP lane shifts).
+// Vector tile: evaluate the group of thread threadIdx.x (pixels 4i .. 4i+3
+// of the frame, i = tile*256 + t) and write its outputs: the four codes with
+// one 32-bit store, the 12 normal floats through the wavefront's LDS slice
+// with contiguous 16-byte stores.  Returns the codes one per byte.  Every
+// lane of the workgroup must call this (DPP lane shifts).
 // ---------------------------------------------------------------------------
 template <int A>
 __device__ __forceinline__ uint32_t vec4_group(const FrameArgs &f, uint32_t tile, TileLds &lds,
@@ -100,23 +113,27 @@ __device__ __forceinline__ uint32_t vec4_group(const FrameArgs &f, uint32_t tile
         nv[3 * j + 2] = o.nz;
         codes |= o.code << (8 * j);
     }
-    lds.v[3 * t + 0] = f4{nv[0], nv[1], nv[2], nv[3]};
-    lds.v[3 * t + 1] = f4{nv[4], nv[5], nv[6], nv[7]};
-    lds.v[3 * t + 2] = f4{nv[8], nv[9], nv[10], nv[11]};
     if (live) __builtin_nontemporal_store(codes, reinterpret_cast<uint32_t *>(f.mask) + i);
-    return codes;
-}
-
-// Vector tile, second half (after a workgroup barrier): contiguous store of
-// the tile's normals from LDS, 12 floats per group.
-__device__ __forceinline__ void vec4_store(const FrameArgs &f, uint32_t tile, const TileLds &lds) {
-    const uint32_t ngr = min((uint32_t)kBlock, f.nitems - tile * kBlock);
-    f4 *out = reinterpret_cast<f4 *>(f.normals) + 3 * (int64_t)tile * kBlock;
+    // wavefront-local transpose: lane l holds groups 3l..3l+2 of the slice,
+    // store k writes float4s 64k .. 64k+63 of it (one contiguous KiB)
+    const uint32_t w = t >> 6;
+    f4 *slice = lds.v + 192 * w;
+    wave_lds_sync();
+    slice[3 * lane + 0] = f4{nv[0], nv[1], nv[2], nv[3]};
+    slice[3 * lane + 1] = f4{nv[4], nv[5], nv[6], nv[7]};
+    slice[3 * lane + 2] = f4{nv[8], nv[9], nv[10], nv[11]};
+    wave_lds_sync();
+    const uint32_t g0 = tile * kBlock + 64 * w;  // first group of this wavefront
+    if (g0 < f.nitems) {
+        const uint32_t n = 3 * min(64u, f.nitems - g0);
+        f4 *out = reinterpret_cast<f4 *>(f.normals) + 3 * (int64_t)g0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const uint32_t j = k * kBlock + threadIdx.x;
-        if (j < 3 * ngr) __builtin_nontemporal_store(lds.v[j], out + j);
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t j = 64 * k + lane;
+            if (j < n) __builtin_nontemporal_store(slice[j], out + j);
+        }
     }
+    return codes;
 }
 
 __device__ __forceinline__ void vec4_count(bool live, uint32_t codes, uint32_t &cv, uint32_t &cb) {
@@ -129,7 +146,8 @@ __device__ __forceinline__ void vec4_count(bool live, uint32_t codes, uint32_t &
 }
 
 // ---------------------------------------------------------------------------
-// Scalar tile: pixel i = tile*256 + t, any stride and alignment.
+// Scalar tile: pixel i = tile*256 + t, any stride and alignment; outputs
+// written like the vector tile's.
 // ---------------------------------------------------------------------------
 template <int A>
 __device__ __forceinline__ uint32_t scalar_pixel(const FrameArgs &f, uint32_t tile, TileLds &lds,
@@ -161,22 +179,26 @@ __device__ __forceinline__ uint32_t scalar_pixel(const FrameArgs &f, uint32_t ti
         code = o.code;
         f.mask[i] = (uint8_t)code;
     }
-    s[3 * threadIdx.x + 0] = nx;
-    s[3 * threadIdx.x + 1] = ny;
-    s[3 * threadIdx.x + 2] = nz;
-    return code;
-}
-
-__device__ __forceinline__ void scalar_store(const FrameArgs &f, uint32_t tile, const TileLds &lds) {
-    const float *s = reinterpret_cast<const float *>(lds.v);
-    const uint32_t base = tile * kBlock;
-    const uint32_t n = min((uint32_t)kBlock, f.nitems - base) * 3u;
-    float *out = f.normals + 3 * (int64_t)base;
+    // wavefront-local transpose through this wavefront's LDS slice
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t w = threadIdx.x >> 6;
+    float *slice = s + 192 * w;
+    wave_lds_sync();
+    slice[3 * lane + 0] = nx;
+    slice[3 * lane + 1] = ny;
+    slice[3 * lane + 2] = nz;
+    wave_lds_sync();
+    const uint32_t p0 = tile * kBlock + 64 * w;  // first pixel of this wavefront
+    if (p0 < f.nitems) {
+        const uint32_t n = 3 * min(64u, f.nitems - p0);
+        float *out = f.normals + 3 * (int64_t)p0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const uint32_t j = k * kBlock + threadIdx.x;
-        if (j < n) out[j] = s[j];
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t j = 64 * k + lane;
+            if (j < n) out[j] = slice[j];
+        }
     }
+    return code;
 }
 
 __device__ __forceinline__ void scalar_count(bool live, uint32_t code, uint32_t &cv, uint32_t &cb) {
@@ -184,8 +206,8 @@ __device__ __forceinline__ void scalar_count(bool live, uint32_t code, uint32_t 
     cb += wave_count(live & (code == BN_BOUNDARY));
 }
 
-// One whole tile of either kind: evaluate, barrier, store.  The caller
-// places a barrier between consecutive tiles (LDS reuse).
+// One whole tile of either kind.  No workgroup barrier: consecutive tiles
+// of a workgroup may overlap freely.
 template <int A>
 __device__ __forceinline__ void run_tile(const FrameArgs &f, bool vec, uint32_t tile, TileLds &lds,
                                          uint32_t &cv, uint32_t &cb) {
@@ -193,13 +215,9 @@ __device__ __forceinline__ void run_tile(const FrameArgs &f, bool vec, uint32_t 
     if (vec) {
         const uint32_t codes = vec4_group<A>(f, tile, lds, live);
         if (f.stats) vec4_count(live, codes, cv, cb);
-        __syncthreads();
-        vec4_store(f, tile, lds);
     } else {
         const uint32_t code = scalar_pixel<A>(f, tile, lds, live);
         if (f.stats) scalar_count(live, code, cv, cb);
-        __syncthreads();
-        scalar_store(f, tile, lds);
     }
 }
 

@@ -1,0 +1,142 @@
+"""Summaries of rocprofv3 output for the kernels of this library.
+
+    python -m paper_2209_08241_amd.profiling trace  <kernel_stats.csv> <out.md> [--cmd "..."]
+    python -m paper_2209_08241_amd.profiling traffic --fetch <dir> --write <dir> \
+        --kernel <substring> --pixels <per launch> --workload <name> --out <json> [--cmd "..."]
+
+`trace` turns a `--kernel-trace --stats` kernel_stats.csv into a short table.
+`traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs into HBM bytes
+per launch of one kernel.  Each counter is calibrated against the copy
+kernel that bench.py runs first (`--calibration-mib`): its bytes read and
+written are known exactly, so the factor is known bytes / counter reading.
+The record carries the hash of the kernel sources it was measured on;
+bench.py reports it only while the sources are unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _csv_rows(path_or_dir: str, pattern: str):
+    if os.path.isdir(path_or_dir):
+        files = glob.glob(os.path.join(path_or_dir, "**", pattern), recursive=True)
+    else:
+        files = [path_or_dir]
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def trace_summary(stats_csv: str, out_md: str, cmd: str = "") -> str:
+    rows = _csv_rows(stats_csv, "*kernel_stats.csv")
+    lines = ["# rocprofv3 kernel statistics", ""]
+    if cmd:
+        lines += ["Command:", "", "```", cmd, "```", ""]
+    lines += ["| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.3f} | "
+                     f"{float(r['MinNs']) / 1e3:.3f} | {float(r['MaxNs']) / 1e3:.3f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    text = "\n".join(lines) + "\n"
+    with open(out_md, "w") as fh:
+        fh.write(text)
+    return text
+
+
+def _per_dispatch(rows, counter: str):
+    """{dispatch id: (kernel name, value)} for one counter."""
+    out = {}
+    for r in rows:
+        name = r.get("Counter_Name") or r.get("Counter-Name")
+        if name != counter:
+            continue
+        did = r.get("Dispatch_Id") or r.get("Dispatch-Id") or r.get("Correlation_Id")
+        val = float(r.get("Counter_Value") or r.get("Counter-Value"))
+        k = r.get("Kernel_Name") or r.get("Kernel-Name")
+        prev = out.get(did)
+        out[did] = (k, val + (prev[1] if prev else 0.0))
+    return out
+
+
+def _kernel_values(disp, needle: str):
+    return [v for (k, v) in disp.values() if needle in k]
+
+
+def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: str,
+            out_json: str, calib_bytes: int, calib_kernel: str, cmd: str = "") -> dict:
+    sys.path.insert(0, ROOT)
+    from bench import kernel_hash   # noqa: E402  (same hash bench.py checks)
+    f_rows = _csv_rows(fetch_dir, "*counter_collection.csv")
+    w_rows = _csv_rows(write_dir, "*counter_collection.csv")
+    f = _per_dispatch(f_rows, "FETCH_SIZE")
+    w = _per_dispatch(w_rows, "WRITE_SIZE")
+    fc = _kernel_values(f, calib_kernel)
+    wc = _kernel_values(w, calib_kernel)
+    fk = _kernel_values(f, kernel)
+    wk = _kernel_values(w, kernel)
+    if not (fc and wc and fk and wk):
+        raise SystemExit(f"missing dispatches: calib {len(fc)}/{len(wc)}, kernel {len(fk)}/{len(wk)}")
+    # copy kernel: reads and writes calib_bytes each
+    f_factor = calib_bytes / statistics.median(fc)
+    w_factor = calib_bytes / statistics.median(wc)
+    rb = statistics.median(fk) * f_factor
+    wb = statistics.median(wk) * w_factor
+    rec = {
+        "workload": workload,
+        "kernel": kernel,
+        "pixels_per_launch": pixels,
+        "algorithmic_bytes_per_launch": 17 * pixels,
+        "hbm_read_bytes_per_launch": rb,
+        "hbm_write_bytes_per_launch": wb,
+        "hbm_bytes_per_launch": rb + wb,
+        "read_bytes_per_pixel": rb / pixels,
+        "write_bytes_per_pixel": wb / pixels,
+        "fetch_factor": f_factor,
+        "write_factor": w_factor,
+        "calibration": f"{calib_kernel}: {calib_bytes} bytes read and written",
+        "dispatches": {"fetch": len(fk), "write": len(wk)},
+        "kernel_hash": kernel_hash(),
+        "command": cmd,
+    }
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("stats_csv")
+    t.add_argument("out_md")
+    t.add_argument("--cmd", default="")
+    p = sub.add_parser("traffic")
+    p.add_argument("--fetch", required=True)
+    p.add_argument("--write", required=True)
+    p.add_argument("--kernel", required=True)
+    p.add_argument("--pixels", type=int, required=True)
+    p.add_argument("--workload", required=True)
+    p.add_argument("--out", required=True)
+    p.add_argument("--calib-bytes", type=int, required=True)
+    p.add_argument("--calib-kernel", default="elementwise")
+    p.add_argument("--cmd", default="")
+    a = ap.parse_args()
+    if a.what == "trace":
+        print(trace_summary(a.stats_csv, a.out_md, a.cmd))
+    else:
+        print(json.dumps(traffic(a.fetch, a.write, a.kernel, a.pixels, a.workload, a.out,
+                                 a.calib_bytes, a.calib_kernel, a.cmd), indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,57 @@
+"""The autotuner picks among variants / grids that all give identical output."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2209_08241_amd as bn
+from gpu_util import assert_parity, gpu_normals, log, to_gpu
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_plain_and_cache(tmp_path):
+    bn.autotune_reset()
+    v, us = bn.autotune_plain(1080, 1920, alpha=2)
+    log(f"plain 1920x1080 tuned: variant {v} ({dict(bn.variants())[v]}), {us:.2f} us")
+    assert v in dict(bn.variants()) and us > 0
+    assert bn.autotune_entries() == 1
+    s = scenes.frame_1920x1080(seed=3)
+    ref = oracle.normals_f32(s.depth, *s.intrinsics, 2, "rel", 4.0)
+    n, m, st = gpu_normals(s.depth, *s.intrinsics, 2, "rel", 4.0, 0)
+    assert_parity(ref, n, m, st, what="after plain autotune")
+    p = str(tmp_path / "tune.json")
+    bn.autotune_save(p)
+    bn.autotune_reset()
+    assert bn.autotune_entries() == 0
+    bn.autotune_load(p)
+    assert bn.autotune_entries() == 1
+    bn.autotune_reset()
+
+
+def test_autotune_batch_grid():
+    import torch
+    bn.autotune_reset()
+    frs = scenes.batch_frames(seed0=1000, indices=range(0, 256, 8))
+    frames = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in frs]
+    with bn.BatchPlan(frames) as plan:
+        k, us = plan.autotune()
+        tuned_wg = plan.info()["workgroups"]
+        log(f"batch grid tuned: {k} workgroups per CU, {us:.1f} us")
+        assert k in (0, 2, 4, 8)
+        info = plan.info()
+        assert info["workgroups"] == (info["tiles"] if k == 0 else 256 * k)
+        for f in frames:
+            f.stats.zero_()
+        plan.run()
+        torch.cuda.synchronize()
+        for s, f in zip(frs, frames):
+            ref = oracle.normals_f32(s.depth, *s.intrinsics, 2, "rel", 4.0)
+            assert_parity(ref, f.normals.cpu().numpy(), f.mask.cpu().numpy(),
+                          f.stats.cpu().numpy(), what="after batch autotune")
+    # a new plan of the same size class starts from the tuned grid
+    with bn.BatchPlan(frames) as plan2:
+        assert plan2.info()["workgroups"] == tuned_wg
+    bn.autotune_reset()
