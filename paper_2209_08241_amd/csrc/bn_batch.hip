@@ -48,40 +48,84 @@ struct BatchHeader {
 // tile_frame[t] is the index of the frame that holds tile t, so that a
 // workgroup finds its first frame with one load (a search over the frame
 // descriptors is a chain of dependent loads, long next to a 1024-pixel tile).
+//
+// Counts: each wavefront stores the VALID / BOUNDARY counts of its quarter
+// of a tile (VALID | BOUNDARY << 16, at most 256 pixels each) into
+// wave_counts[4 t + w]; a second kernel of the same graph sums them per
+// frame.  The main kernel thus has neither atomics nor workgroup barriers.
 template <int A>
-__global__ __launch_bounds__(kBlock) void k_batch(const BatchHeader *__restrict__ hdr,
-                                                  const BatchFrame *__restrict__ frames,
-                                                  const uint32_t *__restrict__ tile_frame) {
+__global__ __launch_bounds__(kBlock) void k_batch(const BatchFrame *__restrict__ frames,
+                                                  const uint32_t *__restrict__ tile_frame,
+                                                  uint32_t *__restrict__ wave_counts,
+                                                  uint32_t ntiles, uint32_t chunk,
+                                                  uint32_t nframes) {
     __shared__ TileLds lds;
-    const uint32_t T = hdr->ntiles;
-    const uint32_t c = hdr->chunk;
-    const uint32_t nf = hdr->nframes;
     const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
-    uint32_t t = blk * c;
-    if (c == 0 || t >= T) return;  // uniform: this workgroup has no tiles
-    const uint32_t tend = min(t + c, T);
+    uint32_t t = blk * chunk;
+    if (chunk == 0 || t >= ntiles) return;  // uniform: this workgroup has no tiles
+    const uint32_t tend = min(t + chunk, ntiles);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
     uint32_t fi = tile_frame[t];
-    while (t < tend && fi < nf) {
+    while (t < tend && fi < nframes) {
         const FrameArgs f = frames[fi].a;
         const uint32_t tb = frames[fi].tile_begin;
         const uint32_t nt = frames[fi].ntiles;
         const bool vec = frames[fi].vec != 0;
         const uint32_t seg_end = min(tend, tb + nt);
-        uint32_t cv = 0, cb = 0;
-        for (; t < seg_end; ++t) run_tile<A>(f, vec, t - tb, lds, cv, cb);
-        if (f.stats) {
-            // the frame's parts are the workgroups whose chunks meet it
-            const uint32_t b_first = tb / c;
-            const uint32_t b_last = (tb + nt - 1) / c;
-            block_counts(f.stats, blk - b_first, b_last - b_first + 1, cv, cb, f.npix);
+        for (; t < seg_end; ++t) {
+            uint32_t cv = 0, cb = 0;
+            run_tile<A>(f, vec, t - tb, lds, cv, cb);
+            if (f.stats && lane == 0) wave_counts[4 * (int64_t)t + wave] = cv | (cb << 16);
         }
         do {
             ++fi;
-        } while (fi < nf && frames[fi].ntiles == 0);
+        } while (fi < nframes && frames[fi].ntiles == 0);
     }
 }
 
-typedef void (*BatchKernelFn)(const BatchHeader *, const BatchFrame *, const uint32_t *);
+// One workgroup per frame: sum the frame's wavefront counts and add the
+// totals to its bn_frame_stats.
+__global__ __launch_bounds__(kBlock) void k_batch_counts(const BatchFrame *__restrict__ frames,
+                                                         const uint32_t *__restrict__ wave_counts,
+                                                         uint32_t nframes) {
+    __shared__ uint32_t s_sum[kBlock / 64][2];
+    const uint32_t fi = blockIdx.x;
+    if (fi >= nframes) return;
+    bn_frame_stats *st = frames[fi].a.stats;
+    const uint32_t nt = frames[fi].ntiles;
+    if (!st || nt == 0) return;  // uniform over the workgroup
+    const uint32_t *wc = wave_counts + 4 * (int64_t)frames[fi].tile_begin;
+    uint32_t v = 0, b = 0;
+    for (uint32_t k = threadIdx.x; k < 4 * nt; k += kBlock) {
+        const uint32_t c = wc[k];
+        v += c & 0xffffu;
+        b += c >> 16;
+    }
+    // wavefront sums through DPP-free shuffles, then across the 4 wavefronts
+    for (int off = 32; off > 0; off >>= 1) {
+        v += __shfl_xor(v, off);
+        b += __shfl_xor(b, off);
+    }
+    if ((threadIdx.x & 63u) == 0) {
+        s_sum[threadIdx.x >> 6][0] = v;
+        s_sum[threadIdx.x >> 6][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t vt = 0, bt = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            vt += s_sum[w][0];
+            bt += s_sum[w][1];
+        }
+        atomicAdd(&st->n_valid, vt);
+        atomicAdd(&st->n_boundary, bt);
+        atomicAdd(&st->n_invalid, frames[fi].a.npix - vt - bt);
+    }
+}
+
+typedef void (*BatchKernelFn)(const BatchFrame *, const uint32_t *, uint32_t *, uint32_t,
+                              uint32_t, uint32_t);
 
 static BatchKernelFn batch_kernel(int alpha) {
     switch (alpha) {
@@ -116,10 +160,13 @@ struct bn_batch_plan {
     void *staging[2] = {nullptr, nullptr};
     hipEvent_t staged[2] = {nullptr, nullptr};
     int next = 0;                  // staging copy the next update writes
+    uint32_t *dcounts = nullptr;   // 4 wavefront counts per tile (tile_capacity tiles)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t node = nullptr;
+    hipGraphNode_t node = nullptr;         // the tile kernel
+    hipGraphNode_t count_node = nullptr;   // the per-frame count sums
     BatchKernelFn fn = nullptr;
+    BatchHeader hdr{};                     // current header (kernel arguments)
     uint64_t total_tiles = 0;
     uint64_t total_pixels = 0;
 };
@@ -195,11 +242,11 @@ int build_table(const bn_frame *frames, int32_t n, const bn_params *p, int32_t c
     return BN_OK;
 }
 
-hipKernelNodeParams node_params(bn_batch_plan *pl, void **args) {
+hipKernelNodeParams kernel_params(void *func, uint32_t grid, void **args) {
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof(kp));
-    kp.func = reinterpret_cast<void *>(pl->fn);
-    kp.gridDim = dim3(pl->grid);
+    kp.func = func;
+    kp.gridDim = dim3(grid);
     kp.blockDim = dim3(kBlock);
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
@@ -207,25 +254,34 @@ hipKernelNodeParams node_params(bn_batch_plan *pl, void **args) {
     return kp;
 }
 
-// Kernel node parameters (buffer pointers and grid) into the graph, or a
-// fresh graph when none exists yet.
+// Kernel node parameters (buffer pointers, header values, grids) into the
+// graph, or a fresh graph [tile kernel] -> [count sums] when none exists.
 int refresh_node(bn_batch_plan *pl) {
-    const BatchHeader *d_hdr = static_cast<const BatchHeader *>(pl->dbuf);
-    const BatchFrame *d_frames = reinterpret_cast<const BatchFrame *>(d_hdr + 1);
+    const BatchFrame *d_frames = reinterpret_cast<const BatchFrame *>(
+        static_cast<const char *>(pl->dbuf) + sizeof(BatchHeader));
     const uint32_t *d_tf = reinterpret_cast<const uint32_t *>(
         static_cast<const char *>(pl->dbuf) + table_offset(pl->capacity));
-    void *args[3] = {(void *)&d_hdr, (void *)&d_frames, (void *)&d_tf};
-    hipKernelNodeParams kp = node_params(pl, args);
+    uint32_t *d_wc = pl->dcounts;
+    uint32_t ntiles = pl->hdr.ntiles, chunk = pl->hdr.chunk, nframes = pl->hdr.nframes;
+    void *args[6] = {(void *)&d_frames, (void *)&d_tf, (void *)&d_wc,
+                     (void *)&ntiles,   (void *)&chunk, (void *)&nframes};
+    hipKernelNodeParams kp = kernel_params(reinterpret_cast<void *>(pl->fn), pl->grid, args);
+    const uint32_t *d_wc_c = pl->dcounts;
+    void *cargs[3] = {(void *)&d_frames, (void *)&d_wc_c, (void *)&nframes};
+    hipKernelNodeParams cp = kernel_params(reinterpret_cast<void *>(k_batch_counts),
+                                           nframes ? nframes : 1u, cargs);
     if (!pl->exec) {
         if (hipGraphCreate(&pl->graph, 0) != hipSuccess ||
             hipGraphAddKernelNode(&pl->node, pl->graph, nullptr, 0, &kp) != hipSuccess ||
+            hipGraphAddKernelNode(&pl->count_node, pl->graph, &pl->node, 1, &cp) != hipSuccess ||
             hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess)
             return BN_ERR_DEVICE;
         return BN_OK;
     }
-    return hipGraphExecKernelNodeSetParams(pl->exec, pl->node, &kp) == hipSuccess
-               ? BN_OK
-               : BN_ERR_DEVICE;
+    if (hipGraphExecKernelNodeSetParams(pl->exec, pl->node, &kp) != hipSuccess ||
+        hipGraphExecKernelNodeSetParams(pl->exec, pl->count_node, &cp) != hipSuccess)
+        return BN_ERR_DEVICE;
+    return BN_OK;
 }
 
 void free_buffers(bn_batch_plan *pl) {
@@ -235,6 +291,8 @@ void free_buffers(bn_batch_plan *pl) {
     }
     if (pl->dbuf) (void)hipFree(pl->dbuf);
     pl->dbuf = nullptr;
+    if (pl->dcounts) (void)hipFree(pl->dcounts);
+    pl->dcounts = nullptr;
 }
 
 int alloc_buffers(bn_batch_plan *pl, uint64_t tile_capacity) {
@@ -244,6 +302,8 @@ int alloc_buffers(bn_batch_plan *pl, uint64_t tile_capacity) {
         if (hipHostMalloc(&pl->staging[k], pl->buf_bytes, hipHostMallocDefault) != hipSuccess)
             return BN_ERR_OOM;
     if (hipMalloc(&pl->dbuf, pl->buf_bytes) != hipSuccess) return BN_ERR_OOM;
+    if (hipMalloc(&pl->dcounts, sizeof(uint32_t) * 4 * (size_t)tile_capacity) != hipSuccess)
+        return BN_ERR_OOM;
     return BN_OK;
 }
 
@@ -267,6 +327,7 @@ int upload(bn_batch_plan *pl, const bn_frame *frames, int32_t n, int k, hipStrea
            uint64_t tiles) {
     int rc = build_table(frames, n, &pl->params, pl->capacity, pl->grid, pl->staging[k]);
     if (rc != BN_OK) return rc;
+    pl->hdr = *static_cast<const BatchHeader *>(pl->staging[k]);
     const size_t bytes = table_offset(pl->capacity) + sizeof(uint32_t) * (size_t)tiles;
     if (hipMemcpyAsync(pl->dbuf, pl->staging[k], bytes, hipMemcpyHostToDevice, stream) !=
             hipSuccess ||
@@ -324,6 +385,7 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
     rc = alloc_buffers(pl, tiles > 0 ? tiles : 1);
     if (rc == BN_OK) rc = build_table(frames_host, n_frames, params, pl->capacity, pl->grid,
                                       pl->staging[0]);
+    if (rc == BN_OK) pl->hdr = *static_cast<const BatchHeader *>(pl->staging[0]);
     if (rc == BN_OK &&
         hipMemcpy(pl->dbuf, pl->staging[0], pl->buf_bytes, hipMemcpyHostToDevice) != hipSuccess)
         rc = BN_ERR_DEVICE;
@@ -347,30 +409,43 @@ int bn_batch_plan_update(bn_batch_plan *plan, const bn_frame *frames_host, int32
     if (rc != BN_OK) return rc;
     const uint32_t grid = grid_for(tiles, plan->cus, plan->blocks_per_cu);
     if (tiles > 0 && (tiles + grid - 1) / grid > 4096) return BN_ERR_UNSUPPORTED;
-    bool repoint = false;
     if (tiles > plan->tile_capacity) {
         // a larger tile table: wait for every use of the old buffers first
         if (hipStreamSynchronize(s) != hipSuccess ||
             hipEventSynchronize(plan->staged[0]) != hipSuccess ||
             hipEventSynchronize(plan->staged[1]) != hipSuccess)
             return BN_ERR_DEVICE;
+        // allocate the new buffers before releasing the old ones, so that a
+        // failed allocation leaves the plan as it was
+        bn_batch_plan fresh;
+        fresh.capacity = plan->capacity;
+        rc = alloc_buffers(&fresh, tiles + tiles / 4);
+        if (rc != BN_OK) {
+            free_buffers(&fresh);
+            return rc;
+        }
         free_buffers(plan);
-        rc = alloc_buffers(plan, tiles + tiles / 4);
-        if (rc != BN_OK) return rc;
-        repoint = true;
+        for (int j = 0; j < 2; ++j) {
+            plan->staging[j] = fresh.staging[j];
+            fresh.staging[j] = nullptr;
+        }
+        plan->dbuf = fresh.dbuf;
+        plan->dcounts = fresh.dcounts;
+        plan->buf_bytes = fresh.buf_bytes;
+        plan->tile_capacity = fresh.tile_capacity;
+        fresh.dbuf = nullptr;
+        fresh.dcounts = nullptr;
     }
     const int k = plan->next;
     // the staging copy may still feed the upload issued two updates ago
     if (hipEventSynchronize(plan->staged[k]) != hipSuccess) return BN_ERR_DEVICE;
-    const uint32_t old_grid = plan->grid;
     plan->grid = grid;
     rc = upload(plan, frames_host, n_frames, k, s, tiles);
     if (rc != BN_OK) return rc;
     plan->next = 1 - k;
     plan->total_tiles = tiles;
     plan->total_pixels = pixels;
-    if (repoint || grid != old_grid) return refresh_node(plan);
-    return BN_OK;
+    return refresh_node(plan);  // new header values, grids and pointers
 }
 
 int bn_batch_run(bn_batch_plan *plan, void *stream) {
@@ -387,23 +462,16 @@ int bn_batch_plan_info(const bn_batch_plan *plan, int64_t *n_pixels, int64_t *n_
     return BN_OK;
 }
 
-// Re-grid the plan: the header's chunk (ordered on `stream`) and the
-// launch's workgroup count.  The staging copy written last (index
-// 1 - next) holds the current table.
+// Re-grid the plan: new chunk and workgroup count in the graph's kernel
+// arguments (they take effect at the next run).
 static int set_grid(bn_batch_plan *plan, uint32_t blocks_per_cu, hipStream_t stream) {
-    const int last = 1 - plan->next;
-    if (hipEventSynchronize(plan->staged[last]) != hipSuccess) return BN_ERR_DEVICE;
-    auto *hdr = static_cast<BatchHeader *>(plan->staging[last]);
-    const uint32_t grid = grid_for(hdr->ntiles, plan->cus, blocks_per_cu);
-    const uint32_t chunk = hdr->ntiles ? (hdr->ntiles + grid - 1) / grid : 0;
+    (void)stream;
+    const uint32_t grid = grid_for(plan->hdr.ntiles, plan->cus, blocks_per_cu);
+    const uint32_t chunk = plan->hdr.ntiles ? (plan->hdr.ntiles + grid - 1) / grid : 0;
     if (chunk > 4096) return BN_ERR_UNSUPPORTED;
     plan->blocks_per_cu = blocks_per_cu;
     plan->grid = grid;
-    hdr->chunk = chunk;
-    if (hipMemcpyAsync(plan->dbuf, hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, stream) !=
-            hipSuccess ||
-        hipEventRecord(plan->staged[last], stream) != hipSuccess)
-        return BN_ERR_DEVICE;
+    plan->hdr.chunk = chunk;
     return refresh_node(plan);
 }
 

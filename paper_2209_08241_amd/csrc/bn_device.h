@@ -170,22 +170,41 @@ __device__ __forceinline__ unsigned long long *stats_word(bn_frame_stats *st, ui
         slot < BN_STATS_SLOTS ? &st->work[14 + 16 * slot] : &st->work[0]);
 }
 
-__device__ __forceinline__ void reduce_counts(bn_frame_stats *st, uint32_t part, uint32_t nparts,
-                                              uint32_t nvalid, uint32_t nboundary,
-                                              uint32_t npix) {
+// First half: the level-1 atomic.  Its result is used only in the second
+// half, so the caller can place other work (the output stores) in between
+// and hide the atomic's round trip behind it.
+struct CountTicket {
+    bn_frame_stats *st;
+    unsigned long long *w1;
+    unsigned long long mine1;
+    unsigned long long old1;
+    uint32_t ns, nparts, npix;
+};
+
+__device__ __forceinline__ CountTicket count_issue(bn_frame_stats *st, uint32_t part,
+                                                   uint32_t nparts, uint32_t nvalid,
+                                                   uint32_t nboundary, uint32_t npix) {
+    CountTicket k;
     const uint32_t s = part % BN_STATS_SLOTS;
-    const uint32_t ns = nparts / BN_STATS_SLOTS + (s < nparts % BN_STATS_SLOTS ? 1u : 0u);
-    unsigned long long *w1 = stats_word(st, s);
-    const unsigned long long mine1 =
-        (unsigned long long)nvalid | ((unsigned long long)nboundary << 24) | (1ull << 48);
-    const unsigned long long old1 = atomicAdd(w1, mine1);
-    if ((uint32_t)(old1 >> 48) != ns - 1u) return;
-    const unsigned long long tot1 = old1 + mine1;
-    atomicExch(w1, 0ull);
+    k.st = st;
+    k.ns = nparts / BN_STATS_SLOTS + (s < nparts % BN_STATS_SLOTS ? 1u : 0u);
+    k.nparts = nparts;
+    k.npix = npix;
+    k.w1 = stats_word(st, s);
+    k.mine1 = (unsigned long long)nvalid | ((unsigned long long)nboundary << 24) | (1ull << 48);
+    k.old1 = atomicAdd(k.w1, k.mine1);
+    return k;
+}
+
+__device__ __forceinline__ void count_finish(const CountTicket &k) {
+    if ((uint32_t)(k.old1 >> 48) != k.ns - 1u) return;
+    const unsigned long long tot1 = k.old1 + k.mine1;
+    atomicExch(k.w1, 0ull);
     const uint32_t vs = (uint32_t)(tot1 & 0xffffffull);
     const uint32_t bs = (uint32_t)((tot1 >> 24) & 0xffffffull);
-    const uint32_t nactive = nparts < (uint32_t)BN_STATS_SLOTS ? nparts : (uint32_t)BN_STATS_SLOTS;
-    unsigned long long *w2 = stats_word(st, BN_STATS_SLOTS);
+    const uint32_t nactive =
+        k.nparts < (uint32_t)BN_STATS_SLOTS ? k.nparts : (uint32_t)BN_STATS_SLOTS;
+    unsigned long long *w2 = stats_word(k.st, BN_STATS_SLOTS);
     const unsigned long long mine2 =
         (unsigned long long)vs | ((unsigned long long)bs << 29) | (1ull << 58);
     const unsigned long long old2 = atomicAdd(w2, mine2);
@@ -194,14 +213,20 @@ __device__ __forceinline__ void reduce_counts(bn_frame_stats *st, uint32_t part,
     atomicExch(w2, 0ull);
     const uint32_t vt = (uint32_t)(tot2 & ((1ull << 29) - 1));
     const uint32_t bt = (uint32_t)((tot2 >> 29) & ((1ull << 29) - 1));
-    atomicAdd(&st->n_valid, vt);
-    atomicAdd(&st->n_boundary, bt);
-    atomicAdd(&st->n_invalid, npix - vt - bt);
+    atomicAdd(&k.st->n_valid, vt);
+    atomicAdd(&k.st->n_boundary, bt);
+    atomicAdd(&k.st->n_invalid, k.npix - vt - bt);
 }
 
-// Block-wide sum of wave-uniform counts; thread 0 then calls reduce_counts.
-__device__ __forceinline__ void block_counts(bn_frame_stats *st, uint32_t part, uint32_t nparts,
-                                             uint32_t cv, uint32_t cb, uint32_t npix) {
+__device__ __forceinline__ void reduce_counts(bn_frame_stats *st, uint32_t part, uint32_t nparts,
+                                              uint32_t nvalid, uint32_t nboundary,
+                                              uint32_t npix) {
+    count_finish(count_issue(st, part, nparts, nvalid, nboundary, npix));
+}
+
+// Block-wide sum of wave-uniform counts (one workgroup barrier): the totals,
+// valid in thread 0 only.
+__device__ __forceinline__ void block_sum(uint32_t cv, uint32_t cb, uint32_t &v, uint32_t &b) {
     __shared__ uint32_t s_cnt[kBlock / 64][2];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
@@ -210,15 +235,23 @@ __device__ __forceinline__ void block_counts(bn_frame_stats *st, uint32_t part, 
         s_cnt[wave][1] = cb;
     }
     __syncthreads();
+    v = 0;
+    b = 0;
     if (threadIdx.x == 0) {
-        uint32_t v = 0, b = 0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) {
             v += s_cnt[w][0];
             b += s_cnt[w][1];
         }
-        reduce_counts(st, part, nparts, v, b, npix);
     }
+}
+
+// Block-wide sum of wave-uniform counts; thread 0 then calls reduce_counts.
+__device__ __forceinline__ void block_counts(bn_frame_stats *st, uint32_t part, uint32_t nparts,
+                                             uint32_t cv, uint32_t cb, uint32_t npix) {
+    uint32_t v, b;
+    block_sum(cv, cb, v, b);
+    if (threadIdx.x == 0) reduce_counts(st, part, nparts, v, b, npix);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b%8).

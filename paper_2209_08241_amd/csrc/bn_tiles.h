@@ -37,20 +37,24 @@ struct Win {
 };
 
 // ---------------------------------------------------------------------------
-// Vector tile: evaluate the group of thread threadIdx.x (pixels 4i .. 4i+3
-// of the frame, i = tile*256 + t) and write its outputs: the four codes with
-// one 32-bit store, the 12 normal floats through the wavefront's LDS slice
-// with contiguous 16-byte stores.  Returns the codes one per byte.  Every
-// lane of the workgroup must call this (DPP lane shifts).
+// Vector tile, first half: evaluate the group of thread threadIdx.x (pixels
+// 4i .. 4i+3 of the frame, i = tile*256 + t) into registers.  Every lane of
+// the workgroup must call this (DPP lane shifts).
 // ---------------------------------------------------------------------------
+struct Vec4Out {
+    float nv[12];
+    uint32_t codes;  // one per byte
+    bool live;
+};
+
 template <int A>
-__device__ __forceinline__ uint32_t vec4_group(const FrameArgs &f, uint32_t tile, TileLds &lds,
-                                               bool &live) {
+__device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec4Out &o) {
     constexpr int R = Win<A>::R;
     const uint32_t t = threadIdx.x;
     const uint32_t lane = t & 63u;
     const uint32_t i = tile * kBlock + t;
-    live = i < f.nitems;
+    const bool live = i < f.nitems;
+    o.live = live;
     uint32_t y = 0, x0 = 0;
     if (live) {
         y = row_of(i, f.inv_gpr);
@@ -98,7 +102,6 @@ __device__ __forceinline__ uint32_t vec4_group(const FrameArgs &f, uint32_t tile
     const float upv[4] = {up.x, up.y, up.z, up.w};
     const float dnv[4] = {dn.x, dn.y, dn.z, dn.w};
     const float yc = (float)y - f.cy;
-    float nv[12];
     uint32_t codes = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -106,16 +109,27 @@ __device__ __forceinline__ uint32_t vec4_group(const FrameArgs &f, uint32_t tile
         const bool inside = rows_in & (x >= (uint32_t)A) & (x + A < (uint32_t)f.W);
         const float xc = (float)x - f.cx;
         const int cI = 4 * R + j;
-        const PixelOut o = eval_pixel(inside, row[cI], row[cI + A], dnv[j], row[cI - A], upv[j],
+        const PixelOut p = eval_pixel(inside, row[cI], row[cI + A], dnv[j], row[cI - A], upv[j],
                                       xc, yc, f);
-        nv[3 * j + 0] = o.nx;
-        nv[3 * j + 1] = o.ny;
-        nv[3 * j + 2] = o.nz;
-        codes |= o.code << (8 * j);
+        o.nv[3 * j + 0] = p.nx;
+        o.nv[3 * j + 1] = p.ny;
+        o.nv[3 * j + 2] = p.nz;
+        codes |= p.code << (8 * j);
     }
-    if (live) __builtin_nontemporal_store(codes, reinterpret_cast<uint32_t *>(f.mask) + i);
-    // wavefront-local transpose: lane l holds groups 3l..3l+2 of the slice,
-    // store k writes float4s 64k .. 64k+63 of it (one contiguous KiB)
+    o.codes = codes;
+}
+
+// Vector tile, second half: the four codes with one 32-bit store, the 12
+// normal floats through the wavefront's LDS slice with contiguous 16-byte
+// stores (lane l holds groups 3l..3l+2 of the slice; store k writes
+// float4s 64k .. 64k+63 of it, one contiguous KiB).
+__device__ __forceinline__ void vec4_write(const FrameArgs &f, uint32_t tile, TileLds &lds,
+                                           const Vec4Out &o) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t lane = t & 63u;
+    const uint32_t i = tile * kBlock + t;
+    const float *nv = o.nv;
+    if (o.live) __builtin_nontemporal_store(o.codes, reinterpret_cast<uint32_t *>(f.mask) + i);
     const uint32_t w = t >> 6;
     f4 *slice = lds.v + 192 * w;
     wave_lds_sync();
@@ -133,10 +147,11 @@ __device__ __forceinline__ uint32_t vec4_group(const FrameArgs &f, uint32_t tile
             if (j < n) __builtin_nontemporal_store(slice[j], out + j);
         }
     }
-    return codes;
 }
 
-__device__ __forceinline__ void vec4_count(bool live, uint32_t codes, uint32_t &cv, uint32_t &cb) {
+__device__ __forceinline__ void vec4_count(const Vec4Out &o, uint32_t &cv, uint32_t &cb) {
+    const bool live = o.live;
+    const uint32_t codes = o.codes;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const uint32_t c = (codes >> (8 * j)) & 0xffu;
@@ -149,12 +164,17 @@ __device__ __forceinline__ void vec4_count(bool live, uint32_t codes, uint32_t &
 // Scalar tile: pixel i = tile*256 + t, any stride and alignment; outputs
 // written like the vector tile's.
 // ---------------------------------------------------------------------------
+struct ScalarOut {
+    float nx, ny, nz;
+    uint32_t code;
+    bool live;
+};
+
 template <int A>
-__device__ __forceinline__ uint32_t scalar_pixel(const FrameArgs &f, uint32_t tile, TileLds &lds,
-                                                 bool &live) {
-    float *s = reinterpret_cast<float *>(lds.v);
+__device__ __forceinline__ void scalar_eval(const FrameArgs &f, uint32_t tile, ScalarOut &r) {
     const uint32_t i = tile * kBlock + threadIdx.x;
-    live = i < f.nitems;
+    const bool live = i < f.nitems;
+    r.live = live;
     uint32_t code = BN_INVALID;
     float nx = 0.f, ny = 0.f, nz = 0.f;
     if (live) {
@@ -177,8 +197,19 @@ __device__ __forceinline__ uint32_t scalar_pixel(const FrameArgs &f, uint32_t ti
         ny = o.ny;
         nz = o.nz;
         code = o.code;
-        f.mask[i] = (uint8_t)code;
     }
+    r.nx = nx;
+    r.ny = ny;
+    r.nz = nz;
+    r.code = code;
+}
+
+__device__ __forceinline__ void scalar_write(const FrameArgs &f, uint32_t tile, TileLds &lds,
+                                             const ScalarOut &r) {
+    float *s = reinterpret_cast<float *>(lds.v);
+    const uint32_t i = tile * kBlock + threadIdx.x;
+    if (r.live) f.mask[i] = (uint8_t)r.code;
+    const float nx = r.nx, ny = r.ny, nz = r.nz;
     // wavefront-local transpose through this wavefront's LDS slice
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = threadIdx.x >> 6;
@@ -198,12 +229,11 @@ __device__ __forceinline__ uint32_t scalar_pixel(const FrameArgs &f, uint32_t ti
             if (j < n) out[j] = slice[j];
         }
     }
-    return code;
 }
 
-__device__ __forceinline__ void scalar_count(bool live, uint32_t code, uint32_t &cv, uint32_t &cb) {
-    cv += wave_count(live & (code == BN_VALID));
-    cb += wave_count(live & (code == BN_BOUNDARY));
+__device__ __forceinline__ void scalar_count(const ScalarOut &r, uint32_t &cv, uint32_t &cb) {
+    cv += wave_count(r.live & (r.code == BN_VALID));
+    cb += wave_count(r.live & (r.code == BN_BOUNDARY));
 }
 
 // One whole tile of either kind.  No workgroup barrier: consecutive tiles
@@ -211,13 +241,16 @@ __device__ __forceinline__ void scalar_count(bool live, uint32_t code, uint32_t 
 template <int A>
 __device__ __forceinline__ void run_tile(const FrameArgs &f, bool vec, uint32_t tile, TileLds &lds,
                                          uint32_t &cv, uint32_t &cb) {
-    bool live;
     if (vec) {
-        const uint32_t codes = vec4_group<A>(f, tile, lds, live);
-        if (f.stats) vec4_count(live, codes, cv, cb);
+        Vec4Out o;
+        vec4_eval<A>(f, tile, o);
+        vec4_write(f, tile, lds, o);
+        if (f.stats) vec4_count(o, cv, cb);
     } else {
-        const uint32_t code = scalar_pixel<A>(f, tile, lds, live);
-        if (f.stats) scalar_count(live, code, cv, cb);
+        ScalarOut r;
+        scalar_eval<A>(f, tile, r);
+        scalar_write(f, tile, lds, r);
+        if (f.stats) scalar_count(r, cv, cb);
     }
 }
 
