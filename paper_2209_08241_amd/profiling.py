@@ -72,16 +72,24 @@ def _kernel_values(disp, needle: str):
     return [v for (k, v) in disp.values() if needle in k]
 
 
+def _calibration_values(disp, needle: str, count: int):
+    """The `count` largest readings of the calibration kernel: bench.py runs
+    its calibration copy `count` times; smaller dispatches of the same
+    kernel are unrelated host-to-device copies."""
+    return sorted(_kernel_values(disp, needle), reverse=True)[:count]
+
+
 def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: str,
-            out_json: str, calib_bytes: int, calib_kernel: str, cmd: str = "") -> dict:
+            out_json: str, calib_bytes: int, calib_kernel: str, cmd: str = "",
+            calib_count: int = 4) -> dict:
     sys.path.insert(0, ROOT)
     from bench import kernel_hash   # noqa: E402  (same hash bench.py checks)
     f_rows = _csv_rows(fetch_dir, "*counter_collection.csv")
     w_rows = _csv_rows(write_dir, "*counter_collection.csv")
     f = _per_dispatch(f_rows, "FETCH_SIZE")
     w = _per_dispatch(w_rows, "WRITE_SIZE")
-    fc = _kernel_values(f, calib_kernel)
-    wc = _kernel_values(w, calib_kernel)
+    fc = _calibration_values(f, calib_kernel, calib_count)
+    wc = _calibration_values(w, calib_kernel, calib_count)
     fk = _kernel_values(f, kernel)
     wk = _kernel_values(w, kernel)
     if not (fc and wc and fk and wk):
@@ -103,7 +111,8 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: 
         "write_bytes_per_pixel": wb / pixels,
         "fetch_factor": f_factor,
         "write_factor": w_factor,
-        "calibration": f"{calib_kernel}: {calib_bytes} bytes read and written",
+        "calibration": f"{calib_kernel} (largest {calib_count} dispatches): {calib_bytes} bytes "
+                       f"read and written each",
         "dispatches": {"fetch": len(fk), "write": len(wk)},
         "kernel_hash": kernel_hash(),
         "command": cmd,
@@ -128,14 +137,15 @@ def main():
     p.add_argument("--workload", required=True)
     p.add_argument("--out", required=True)
     p.add_argument("--calib-bytes", type=int, required=True)
-    p.add_argument("--calib-kernel", default="elementwise")
+    p.add_argument("--calib-kernel", default="copyBuffer")
+    p.add_argument("--calib-count", type=int, default=4)
     p.add_argument("--cmd", default="")
     a = ap.parse_args()
     if a.what == "trace":
         print(trace_summary(a.stats_csv, a.out_md, a.cmd))
     else:
         print(json.dumps(traffic(a.fetch, a.write, a.kernel, a.pixels, a.workload, a.out,
-                                 a.calib_bytes, a.calib_kernel, a.cmd), indent=1))
+                                 a.calib_bytes, a.calib_kernel, a.cmd, a.calib_count), indent=1))
 
 
 if __name__ == "__main__":
