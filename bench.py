@@ -244,6 +244,45 @@ def run_batch(args, torch, bn, scenes):
     }
 
 
+def run_serve(args, torch, bn, scenes, capacity_mpix_s):
+    """Poisson request streams over the serving sizes at fractions of the
+    batched capacity measured in the same run; device-resident inputs."""
+    import numpy as np
+    workers = min(5, os.cpu_count() or 1)
+    log("generating one frame per serving size (seeds 3000..3004)")
+    import concurrent.futures as cf
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        frames_h = list(ex.map(scenes._sized_job, [(H, W, 3000 + k, {})
+                                                  for k, (H, W) in enumerate(scenes.SERVE_SIZES)]))
+    pool = [bn.BatchFrame(torch.from_numpy(s.depth).cuda(), s.fx, s.fy, s.cx, s.cy,
+                          want_stats=True) for s in frames_h]
+    mean_px = float(np.mean([s.depth.size for s in frames_h]))
+    cap_hz = capacity_mpix_s * 1e6 / mean_px
+    out = []
+    with bn.Server(args.serve_budget_gib << 30, max_batch=args.serve_max_batch,
+                   max_batches_in_flight=2, alpha=args.alpha, mode=args.mode,
+                   tau=args.tau) as srv:
+        srv.run_poisson(pool, cap_hz * 0.3, 200, seed=2999)       # warm-up
+        for load in (0.5, 0.9):
+            rate = cap_hz * load
+            r = srv.run_poisson(pool, rate, args.serve_requests, seed=3000)
+            lat = r["latency_s"]
+            st = srv.stats()
+            out.append({"load": load, "rate_hz": rate, "requests": args.serve_requests,
+                        "p50_us": 1e6 * float(np.median(lat)),
+                        "p99_us": 1e6 * float(np.quantile(lat, 0.99)),
+                        "mean_us": 1e6 * float(np.mean(lat)),
+                        "mpix_s": r["pixels"] / r["wall_s"] / 1e6,
+                        "launches_total": st["batches"], "largest_launch": st["max_batch_seen"]})
+            log(f"serve load {load}: {rate:.0f} req/s p50 {out[-1]['p50_us']:.0f} us "
+                f"p99 {out[-1]['p99_us']:.0f} us")
+    return {"workload": "Poisson arrivals, sizes uniform over 320x240, 640x480, 1280x720, "
+                        "1920x1080, 4096x3072 (fx=525*W/640, seeds 3000..3004), device-resident "
+                        "inputs, continuous batching, HBM budget "
+                        f"{args.serve_budget_gib} GiB",
+            "mean_request_mpix": mean_px / 1e6, "capacity_req_s": cap_hz, "rates": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +301,10 @@ def main():
     ap.add_argument("--eager", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-budget-gib", type=int, default=16)
+    ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--calibration-mib", type=int, default=0,
                     help="first run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -306,6 +349,8 @@ def main():
             out["batched"] = {k: b[k] for k in ("workload", "value", "unit", "ms_per_step",
                                                 "steps", "pixels", "tiles", "workgroups",
                                                 "roofline")}
+            if not args.no_serve:
+                out["serving"] = run_serve(args, torch, bn, scenes, b["value"])
     line = {
         "metric": out["metric"],
         "value": out["value"],
@@ -323,7 +368,7 @@ def main():
         "roofline": out["roofline"],
         "cpu_baseline": out["cpu_baseline"],
     }
-    for k in ("batched",):
+    for k in ("batched", "serving"):
         if k in out:
             line[k] = out[k]
     print(json.dumps(line), flush=True)

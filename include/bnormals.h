@@ -71,6 +71,7 @@ extern "C" {
 #define BN_ERR_UNSUPPORTED 2
 #define BN_ERR_DEVICE 3
 #define BN_ERR_OOM 4
+#define BN_ERR_TIMEOUT 5
 
 /* boundary-test modes */
 #define BN_MASK_REL 0
@@ -227,6 +228,101 @@ int bn_autotune_save(const char *path);
 int bn_autotune_load(const char *path);
 void bn_autotune_reset(void);
 int bn_autotune_entries(void);
+
+/*
+ * Serving: continuous batching of frames of mixed sizes.
+ *
+ * Requests are queued first come, first served.  A request is admitted when
+ * its slot - normals (12 B/px), mask (1 B/px), a bn_frame_stats and, for a
+ * depth in host memory, a copy of the depth (4 B/px) - fits in the HBM
+ * budget; admission zeroes its counts and starts the host-to-device copy on
+ * a copy stream.  Whenever fewer than max_batches_in_flight launches are
+ * queued on the GPU, all admitted requests whose input is on the device (up
+ * to max_batch) form one batched launch (bn_batch_plan) on a compute
+ * stream.  New requests are therefore admitted and copied while earlier
+ * batches run.  Outputs stay in device memory until the client releases the
+ * request, which returns its slot to the budget.  Each request's outputs are
+ * those of bn_estimate_normals on its frame, whatever it was batched with.
+ *
+ * The HIP backend runs the scheduler on a worker thread.  The fake backend
+ * (tests, CPU only) runs nothing: bn_server_progress schedules what the
+ * current time allows, bn_server_fake_advance moves a virtual clock, and copies and
+ * launches take fake_copy_gbs / fake_launch_ns + fake_ns_per_pixel of
+ * virtual time; bn_server_fake_fail makes one request's result fail.
+ */
+#define BN_BACKEND_HIP 0
+#define BN_BACKEND_FAKE 1
+
+#define BN_REQ_PENDING 0
+#define BN_REQ_ADMITTED 1
+#define BN_REQ_READY 2
+#define BN_REQ_RUNNING 3
+#define BN_REQ_DONE 4
+#define BN_REQ_FAILED 5
+
+typedef struct bn_server_config {
+    int64_t hbm_budget_bytes;      /* device memory for request slots, > 0 */
+    int32_t max_batch;             /* frames per launch, >= 1 */
+    int32_t max_batches_in_flight; /* launches queued on the GPU at once, >= 1 */
+    bn_params params;              /* shared by all requests (variant 0) */
+    int32_t backend;               /* BN_BACKEND_HIP or BN_BACKEND_FAKE */
+    int32_t reserved;
+    double fake_ns_per_pixel;      /* fake backend: kernel time per pixel */
+    double fake_launch_ns;         /* fake backend: time per launch */
+    double fake_copy_gbs;          /* fake backend: host-to-device GB/s */
+} bn_server_config;
+
+typedef struct bn_request_info {
+    int32_t state;       /* BN_REQ_* */
+    int32_t status;      /* BN_OK, or the error of a failed request */
+    int32_t batch_size;  /* frames in its launch */
+    int32_t reserved;
+    uint64_t batch;      /* launch id */
+    double t_submit, t_admit, t_launch, t_done;  /* seconds, monotonic clock */
+    float *normals;      /* device outputs, valid until release */
+    uint8_t *mask;
+    bn_frame_stats *stats;
+} bn_request_info;
+
+typedef struct bn_server_stats {
+    int64_t submitted, completed, failed, released, batches, pending, in_flight_batches;
+    int64_t bytes_in_use, peak_bytes_in_use, max_batch_seen;
+} bn_server_stats;
+
+typedef struct bn_server bn_server;
+/* Errors: BN_ERR_INVALID_ARG, BN_ERR_UNSUPPORTED, BN_ERR_OOM (budget not
+ * allocatable), BN_ERR_DEVICE. */
+int bn_server_create(const bn_server_config *config, bn_server **out_server);
+/* depth: device memory (depth_on_host = 0; must stay valid until the
+ * request completes) or host memory (copied at admission; must stay valid
+ * until then).  BN_ERR_OOM when the request can never fit the budget.
+ * Thread-safe. */
+int bn_server_submit(bn_server *server, const float *depth, int32_t depth_on_host,
+                     int32_t height, int32_t width, int64_t depth_stride, float fx, float fy,
+                     float cx, float cy, uint64_t *request_id);
+int bn_server_query(bn_server *server, uint64_t request_id, bn_request_info *info);
+/* Blocks until the request is done or failed (HIP backend), or
+ * BN_ERR_TIMEOUT after timeout_s (< 0: no limit). */
+int bn_server_wait(bn_server *server, uint64_t request_id, double timeout_s,
+                   bn_request_info *info);
+/* Returns a done or failed request's slot to the budget; its outputs are
+ * no longer valid. */
+int bn_server_release(bn_server *server, uint64_t request_id);
+/* Scheduling passes until nothing changes at the current time (fake
+ * backend; the HIP backend's worker does this continuously); returns the
+ * number of state changes. */
+int bn_server_progress(bn_server *server);
+int bn_server_get_stats(bn_server *server, bn_server_stats *stats);
+int bn_server_fake_advance(bn_server *server, double seconds);
+int bn_server_fake_fail(bn_server *server, uint64_t request_id);
+/* Waits for queued GPU work, then frees everything. */
+void bn_server_destroy(bn_server *server);
+/* Open-loop load: n_requests frames drawn uniformly from `pool` (device
+ * depths), Poisson arrivals at rate_hz, each released on completion.
+ * latency_s[i] = completion - scheduled arrival (n_requests entries). */
+int bn_server_run_poisson(bn_server *server, const bn_frame *pool, int32_t n_pool,
+                          double rate_hz, int32_t n_requests, uint64_t seed, double *latency_s,
+                          double *wall_s, int64_t *pixels);
 
 /* Number of kernel variants of the plain entry point, and a name for each
  * id 1..count (NULL for an unknown id). */

@@ -417,3 +417,194 @@ def cosine_loss(normals, target, mask, target_mask):
     U = (mask == VALID) & (target_mask == VALID)
     cos = (normals * target).sum(-1)
     return (1.0 - cos)[U].sum() / U.sum().clamp(min=1)
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+BACKEND_HIP, BACKEND_FAKE = 0, 1
+REQ_PENDING, REQ_ADMITTED, REQ_READY, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(6)
+BN_ERR_TIMEOUT = 5
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
+                ("max_batches_in_flight", ctypes.c_int32), ("params", Params),
+                ("backend", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fake_ns_per_pixel", ctypes.c_double), ("fake_launch_ns", ctypes.c_double),
+                ("fake_copy_gbs", ctypes.c_double)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("batch", ctypes.c_uint64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("normals", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("submitted", "completed", "failed", "released", "batches", "pending",
+                 "in_flight_batches", "bytes_in_use", "peak_bytes_in_use", "max_batch_seen")]
+
+
+def _bind_server(L) -> None:
+    if getattr(L, "_server_bound", False):
+        return
+    vp, i32, i64, f32, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                              ctypes.c_double)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    L.bn_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    L.bn_server_submit.argtypes = [vp, vp, i32, i32, i32, i64, f32, f32, f32, f32, u64p]
+    L.bn_server_query.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(RequestInfo)]
+    L.bn_server_wait.argtypes = [vp, ctypes.c_uint64, dbl, ctypes.POINTER(RequestInfo)]
+    L.bn_server_release.argtypes = [vp, ctypes.c_uint64]
+    L.bn_server_progress.argtypes = [vp]
+    L.bn_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.bn_server_fake_advance.argtypes = [vp, dbl]
+    L.bn_server_fake_fail.argtypes = [vp, ctypes.c_uint64]
+    L.bn_server_destroy.argtypes = [vp]
+    L.bn_server_destroy.restype = None
+    L.bn_server_run_poisson.argtypes = [vp, ctypes.POINTER(Frame), i32, dbl, i32, ctypes.c_uint64,
+                                        ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                        ctypes.POINTER(i64)]
+    for name in ("bn_server_create", "bn_server_submit", "bn_server_query", "bn_server_wait",
+                 "bn_server_release", "bn_server_progress", "bn_server_get_stats",
+                 "bn_server_fake_advance", "bn_server_fake_fail", "bn_server_run_poisson"):
+        getattr(L, name).restype = ctypes.c_int
+    L._server_bound = True
+
+
+class Server:
+    """bn_server: continuous batching of mixed-size frames under an HBM budget."""
+
+    def __init__(self, budget_bytes: int, max_batch: int = 64, max_batches_in_flight: int = 2,
+                 alpha: int = 2, mode="rel", tau: float = 4.0, backend: str = "hip",
+                 fake_ns_per_pixel: float = 0.004, fake_launch_ns: float = 5000.0,
+                 fake_copy_gbs: float = 25.0):
+        L = lib()
+        _bind_server(L)
+        cfg = ServerConfig(int(budget_bytes), int(max_batch), int(max_batches_in_flight),
+                           make_params(alpha, mode, tau, 0),
+                           BACKEND_FAKE if backend == "fake" else BACKEND_HIP, 0,
+                           float(fake_ns_per_pixel), float(fake_launch_ns), float(fake_copy_gbs))
+        h = ctypes.c_void_p()
+        rc = L.bn_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, depth, fx, fy, cx, cy, *, host: Optional[bool] = None, height=None,
+               width=None, stride=None) -> int:
+        """Queue a frame; `depth` is a torch tensor (device or host), or a raw
+        address with height/width/stride and `host` given.  Returns its id."""
+        L = lib()
+        if isinstance(depth, int):
+            ptr, H, W = depth, int(height), int(width)
+            st = int(stride if stride is not None else W)
+            on_host = bool(host)
+        else:
+            H, W = depth.shape
+            ptr = depth.data_ptr()
+            st = depth.stride(0) if H > 0 else W
+            on_host = not depth.is_cuda if host is None else bool(host)
+        rid = ctypes.c_uint64()
+        rc = L.bn_server_submit(self._h, ctypes.c_void_p(ptr), 1 if on_host else 0, H, W, st,
+                                fx, fy, cx, cy, ctypes.byref(rid))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_server_submit")
+        if not isinstance(depth, int):
+            self._keep[rid.value] = depth       # the input must outlive the request
+        return rid.value
+
+    def query(self, rid: int) -> dict:
+        info = RequestInfo()
+        rc = lib().bn_server_query(self._h, rid, ctypes.byref(info))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_server_query")
+        return info.as_dict()
+
+    def wait(self, rid: int, timeout: float = 60.0) -> dict:
+        info = RequestInfo()
+        rc = lib().bn_server_wait(self._h, rid, float(timeout), ctypes.byref(info))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_server_wait")
+        return info.as_dict()
+
+    def release(self, rid: int) -> None:
+        rc = lib().bn_server_release(self._h, rid)
+        if rc != BN_OK:
+            raise BnError(rc, "bn_server_release")
+        self._keep.pop(rid, None)
+
+    def progress(self) -> int:
+        rc = lib().bn_server_progress(self._h)
+        if rc < 0:
+            raise BnError(-rc, "bn_server_progress")
+        return rc
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        rc = lib().bn_server_get_stats(self._h, ctypes.byref(s))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_server_get_stats")
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def fake_advance(self, seconds: float) -> None:
+        rc = lib().bn_server_fake_advance(self._h, float(seconds))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_server_fake_advance")
+
+    def fake_fail(self, rid: int) -> None:
+        rc = lib().bn_server_fake_fail(self._h, rid)
+        if rc != BN_OK:
+            raise BnError(rc, "bn_server_fake_fail")
+
+    def run_poisson(self, pool, rate_hz: float, n_requests: int, seed: int = 3000):
+        """Open-loop Poisson load over `pool` (BatchFrame list of device
+        frames); returns latencies (s), wall time (s) and pixels."""
+        import numpy as np
+        arr = (Frame * len(pool))(*[f._c() for f in pool])
+        lat = (ctypes.c_double * n_requests)()
+        wall = ctypes.c_double()
+        px = ctypes.c_int64()
+        rc = lib().bn_server_run_poisson(self._h, arr, len(pool), float(rate_hz), int(n_requests),
+                                         int(seed), lat, ctypes.byref(wall), ctypes.byref(px))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_server_run_poisson")
+        return {"latency_s": np.frombuffer(lat, dtype=np.float64).copy(), "wall_s": wall.value,
+                "pixels": px.value}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().bn_server_destroy(self._h)
+        self._h = None
+        self._keep = {}
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def device_to_host(ptr: int, nbytes: int):
+    """Copy device memory at `ptr` into a new numpy uint8 array (tests)."""
+    import numpy as np
+    import torch
+    out = np.empty(nbytes, dtype=np.uint8)
+    if nbytes:
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        torch.cuda.synchronize()
+        rc = hip.hipMemcpy(out.ctypes.data, ctypes.c_void_p(ptr), nbytes, 2)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy failed: {rc}")
+    return out

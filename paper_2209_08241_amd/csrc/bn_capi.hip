@@ -146,6 +146,7 @@ const char *bn_status_string(int status) {
         case BN_ERR_UNSUPPORTED: return "unsupported argument";
         case BN_ERR_DEVICE: return "device error";
         case BN_ERR_OOM: return "out of device memory";
+        case BN_ERR_TIMEOUT: return "timed out";
     }
     return "unknown status";
 }

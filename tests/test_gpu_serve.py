@@ -1,0 +1,105 @@
+"""Serving on the GPU: every request's result is the same as the frame's
+result alone (bit for bit), whatever it was batched with, including under
+budget pressure; the Poisson load generator completes."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2209_08241_amd as bn
+from gpu_util import log
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def serve_frames():
+    log("generating one frame per serving size")
+    out = []
+    for k, (H, W) in enumerate(scenes.SERVE_SIZES):
+        out.append(scenes.sized_frame(H, W, seed=3000 + k))
+    return out
+
+
+def alone(s, depth_t):
+    """The frame through the plain entry point."""
+    import torch
+    n, m, st = bn.estimate_normals(depth_t, s.fx, s.fy, s.cx, s.cy, 2, "rel", 4.0)
+    torch.cuda.synchronize()
+    return n.cpu().numpy(), m.cpu().numpy(), st.cpu().numpy()[:3]
+
+
+def served(info, H, W):
+    n = bn.device_to_host(info["normals"], 12 * H * W).view(np.float32).reshape(H, W, 3)
+    m = bn.device_to_host(info["mask"], H * W).reshape(H, W)
+    st = bn.device_to_host(info["stats"], 16).view(np.uint32)[:3]
+    return n, m, st
+
+
+def check_same(a, b, what):
+    assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32)), f"{what}: normals differ"
+    assert np.array_equal(a[1], b[1]), f"{what}: mask differs"
+    assert np.array_equal(a[2].astype(np.int64), b[2].astype(np.int64)), f"{what}: counts differ"
+
+
+def test_results_are_the_same_alone_and_in_the_mix(serve_frames):
+    import torch
+    dev = [torch.from_numpy(s.depth).cuda() for s in serve_frames]
+    host = [torch.from_numpy(s.depth).pin_memory() for s in serve_frames]
+    refs = [alone(s, d) for s, d in zip(serve_frames, dev)]
+    with bn.Server(8 << 30, max_batch=16, max_batches_in_flight=2) as srv:
+        reqs = []
+        rng = np.random.default_rng(1)
+        for i in range(40):
+            k = int(rng.integers(len(serve_frames)))
+            on_host = bool(i % 3 == 0)
+            s = serve_frames[k]
+            rid = srv.submit(host[k] if on_host else dev[k], s.fx, s.fy, s.cx, s.cy)
+            reqs.append((rid, k, on_host))
+        for rid, k, on_host in reqs:
+            info = srv.wait(rid, 60.0)
+            assert info["state"] == bn.REQ_DONE, info
+            H, W = serve_frames[k].depth.shape
+            check_same(served(info, H, W), refs[k], f"request {rid} size {W}x{H} host={on_host}")
+            srv.release(rid)
+        st = srv.stats()
+        log(f"mix: {st['batches']} launches, largest {st['max_batch_seen']} frames")
+        assert st["completed"] == 40 and st["bytes_in_use"] == 0
+        assert st["batches"] < 40            # requests were batched together
+
+
+def test_budget_pressure_queues_but_completes(serve_frames):
+    import torch
+    dev = [torch.from_numpy(s.depth).cuda() for s in serve_frames]
+    refs = [alone(s, d) for s, d in zip(serve_frames, dev)]
+    big = 13 * 4096 * 3072 + 8192
+    budget = int(2.2 * big)
+    with bn.Server(budget, max_batch=8, max_batches_in_flight=2) as srv:
+        ids = []
+        for i in range(12):
+            k = [4, 4, 1, 4, 0, 2, 3, 4, 1, 4, 4, 3][i]
+            s = serve_frames[k]
+            ids.append((srv.submit(dev[k], s.fx, s.fy, s.cx, s.cy), k))
+        # the client releases results as they complete, freeing budget
+        for rid, k in ids:
+            info = srv.wait(rid, 60.0)
+            assert info["state"] == bn.REQ_DONE
+            H, W = serve_frames[k].depth.shape
+            check_same(served(info, H, W), refs[k], f"request {rid}")
+            srv.release(rid)
+        st = srv.stats()
+        assert st["peak_bytes_in_use"] <= budget and st["completed"] == 12
+
+
+def test_poisson_load_completes(serve_frames):
+    import torch
+    pool = [bn.BatchFrame(torch.from_numpy(s.depth).cuda(), s.fx, s.fy, s.cx, s.cy,
+                          want_stats=False) for s in serve_frames]
+    with bn.Server(16 << 30, max_batch=64, max_batches_in_flight=2) as srv:
+        r = srv.run_poisson(pool, rate_hz=20000.0, n_requests=400, seed=3000)
+        lat = r["latency_s"]
+        assert lat.shape == (400,) and np.all(lat > 0) and np.all(lat < 10.0)
+        log(f"poisson 20k req/s: p50 {1e6 * np.median(lat):.0f} us, p99 "
+            f"{1e6 * np.quantile(lat, 0.99):.0f} us, {r['pixels'] / r['wall_s'] / 1e6:.0f} Mpix/s")
+        assert srv.stats()["completed"] == 400
