@@ -260,7 +260,7 @@ def run_serve(args, torch, bn, scenes, capacity_mpix_s):
     cap_hz = capacity_mpix_s * 1e6 / mean_px
     out = []
     with bn.Server(args.serve_budget_gib << 30, max_batch=args.serve_max_batch,
-                   max_batches_in_flight=2, alpha=args.alpha, mode=args.mode,
+                   max_batches_in_flight=args.serve_in_flight, alpha=args.alpha, mode=args.mode,
                    tau=args.tau) as srv:
         srv.run_poisson(pool, cap_hz * 0.3, 200, seed=2999)       # warm-up
         for load in (0.5, 0.9):
@@ -305,6 +305,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gib", type=int, default=16)
     ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--serve-in-flight", type=int, default=3)
     ap.add_argument("--calibration-mib", type=int, default=0,
                     help="first run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

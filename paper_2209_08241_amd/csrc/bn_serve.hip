@@ -146,22 +146,33 @@ class Backend {
 // ----------------------------------------------------------------------------
 class HipBackend : public Backend {
   public:
-    int init(size_t budget, int32_t max_batch, const bn_params &params) {
+    // A ring of max_batches_in_flight + 1 batch plans: the server never has
+    // more launches queued than that, so the plan a launch takes is idle and
+    // its descriptor table can be rewritten while the other plans' kernels
+    // run.  Tables are uploaded on their own stream; the compute stream
+    // waits for the upload, not for unrelated host-to-device depth copies.
+    int init(size_t budget, int32_t max_batch, int32_t in_flight, const bn_params &params) {
         params_ = params;
         max_batch_ = max_batch;
+        plans_.assign((size_t)in_flight + 1, nullptr);
         if (hipMalloc(&arena_, budget ? budget : 1) != hipSuccess) return BN_ERR_OOM;
         if (hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&upload_, hipStreamNonBlocking) != hipSuccess ||
             hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking) != hipSuccess)
             return BN_ERR_DEVICE;
         return BN_OK;
     }
     ~HipBackend() override {
         if (compute_) (void)hipStreamSynchronize(compute_);
+        if (upload_) (void)hipStreamSynchronize(upload_);
         if (copy_) (void)hipStreamSynchronize(copy_);
         for (auto &kv : batches_) (void)hipEventDestroy(kv.second);
+        for (hipEvent_t e : uploads_) (void)hipEventDestroy(e);
         for (hipEvent_t e : event_pool_) (void)hipEventDestroy(e);
-        if (plan_) bn_batch_plan_destroy(plan_);
+        for (bn_batch_plan *p : plans_)
+            if (p) bn_batch_plan_destroy(p);
         if (copy_) (void)hipStreamDestroy(copy_);
+        if (upload_) (void)hipStreamDestroy(upload_);
         if (compute_) (void)hipStreamDestroy(compute_);
         if (arena_) (void)hipFree(arena_);
     }
@@ -204,16 +215,23 @@ class HipBackend : public Backend {
                              r.normals,   r.mask,    r.stats};
         }
         int rc;
-        if (!plan_) {
+        const size_t j = next_plan_++ % plans_.size();
+        bn_batch_plan *&plan = plans_[j];
+        if (!plan) {
             // capacity max_batch: later lists reuse the plan's graph
             std::vector<bn_frame> cap(fr);
             while ((int32_t)cap.size() < max_batch_) cap.push_back(fr[0]);
-            rc = bn_batch_plan_create(cap.data(), (int32_t)cap.size(), &params_, &plan_);
+            rc = bn_batch_plan_create(cap.data(), (int32_t)cap.size(), &params_, &plan);
             if (rc != BN_OK) return rc;
         }
-        rc = bn_batch_plan_update(plan_, fr.data(), (int32_t)fr.size(), compute_);
+        rc = bn_batch_plan_update(plan, fr.data(), (int32_t)fr.size(), upload_);
         if (rc != BN_OK) return rc;
-        rc = bn_batch_run(plan_, compute_);
+        hipEvent_t up = take_event();
+        if (!up || hipEventRecord(up, upload_) != hipSuccess ||
+            hipStreamWaitEvent(compute_, up, 0) != hipSuccess)
+            return BN_ERR_DEVICE;
+        uploads_.push_back(up);
+        rc = bn_batch_run(plan, compute_);
         if (rc != BN_OK) return rc;
         hipEvent_t e = take_event();
         if (!e || hipEventRecord(e, compute_) != hipSuccess) return BN_ERR_DEVICE;
@@ -226,6 +244,11 @@ class HipBackend : public Backend {
         if (hipEventQuery(it->second) != hipSuccess) return false;
         give_event(it->second);
         batches_.erase(it);
+        // upload events older than a finished launch are complete too
+        while (!uploads_.empty() && hipEventQuery(uploads_.front()) == hipSuccess) {
+            give_event(uploads_.front());
+            uploads_.pop_front();
+        }
         return true;
     }
     void forget(Request &r) override {
@@ -252,8 +275,10 @@ class HipBackend : public Backend {
     bn_params params_{};
     int32_t max_batch_ = 1;
     void *arena_ = nullptr;
-    hipStream_t copy_ = nullptr, compute_ = nullptr;
-    bn_batch_plan *plan_ = nullptr;
+    hipStream_t copy_ = nullptr, upload_ = nullptr, compute_ = nullptr;
+    std::vector<bn_batch_plan *> plans_;
+    size_t next_plan_ = 0;
+    std::deque<hipEvent_t> uploads_;
     std::unordered_map<uint64_t, hipEvent_t> batches_;
     std::vector<hipEvent_t> event_pool_;
 };
@@ -606,7 +631,8 @@ int bn_server_create(const bn_server_config *cfg, bn_server **out) {
     std::unique_ptr<Backend> be;
     if (cfg->backend == BN_BACKEND_HIP) {
         auto h = std::make_unique<HipBackend>();
-        rc = h->init((size_t)cfg->hbm_budget_bytes, cfg->max_batch, cfg->params);
+        rc = h->init((size_t)cfg->hbm_budget_bytes, cfg->max_batch, cfg->max_batches_in_flight,
+                     cfg->params);
         if (rc != BN_OK) {
             delete srv;
             return rc;
