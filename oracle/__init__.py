@@ -23,6 +23,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 VALID, BOUNDARY, INVALID = 0, 1, 2
 MODES = {"rel": 0, "abs": 1, "none": 2}
+METHODS = {"four_pair": 0, "pair_removal": 1, "multiscale": 2}
 
 GCC_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
              "-fexcess-precision=standard", "-fPIC", "-shared", "-Wall", "-Wextra"]
@@ -70,6 +71,20 @@ def load(path: str = LIB):
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_int, up, dp, dp]
     L.bno_normals_vjp_f64.restype = ctypes.c_int
+    L.bno_variant_f32_rows.argtypes = [ctypes.c_int, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_float, ctypes.c_int, ctypes.c_int, dp, up, qp,
+                                       dp, dp, up, dp]
+    L.bno_variant_f32_rows.restype = ctypes.c_int
+    L.bno_variant_f64.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_double, dp, up, qp, dp, dp, up, dp]
+    L.bno_variant_f64.restype = ctypes.c_int
+    L.bno_variant_abs_threshold_f32.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                                                ctypes.c_float, ctypes.c_float, ctypes.c_int]
+    L.bno_variant_abs_threshold_f32.restype = ctypes.c_float
     L.bno_abs_threshold_f32.argtypes = [ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, ctypes.c_int]
     L.bno_abs_threshold_f32.restype = ctypes.c_float
@@ -84,6 +99,10 @@ def _ptr(a: Optional[np.ndarray], ct):
 
 def _mode(mode) -> int:
     return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def _method(method) -> int:
+    return METHODS[method] if isinstance(method, str) else int(method)
 
 
 def _run(fn, depth, dt, ct, fx, fy, cx, cy, alpha, mode, tau, want_r, want_rho, eq7):
@@ -188,6 +207,83 @@ class Oracle:
             raise ValueError("oracle rejected the arguments")
         return out
 
+    def variant_f32(self, depth, fx, fy, cx, cy, alpha=2, mode="rel", tau=4.0, *,
+                    method="four_pair", scales=0, rows=None, want_r=False, want_rho=False,
+                    want_keep=False, gap=False):
+        """Any method (four_pair, pair_removal, multiscale), binary32 depth in,
+        FP64 normals out, binary32 decisions; rows=(begin, end) evaluates
+        those rows of the frame only."""
+        depth = np.asarray(depth)
+        if depth.ndim != 2 or depth.dtype != np.float32:
+            raise TypeError("depth must be a 2-D float32 array")
+        if depth.strides[1] != 4 or depth.strides[0] % 4:
+            depth = np.ascontiguousarray(depth)
+        H, W = depth.shape
+        stride = depth.strides[0] // 4 if H > 0 else W
+        rb, re = (0, H) if rows is None else rows
+        n = re - rb
+        normals = np.zeros((n, W, 3), dtype=np.float64)
+        mask = np.zeros((n, W), dtype=np.uint8)
+        counts = np.zeros(3, dtype=np.uint64)
+        r = np.empty((n, W)) if want_r else None
+        rho = np.empty((n, W)) if want_rho else None
+        keep = np.zeros((n, W), dtype=np.uint8) if want_keep else None
+        g = np.zeros(1) if gap else None
+        rc = self.L.bno_variant_f32_rows(
+            _method(method), int(scales), _ptr(depth, ctypes.c_float), H, W, stride, fx, fy,
+            cx, cy, int(alpha), _mode(mode), tau, int(rb), int(re),
+            _ptr(normals, ctypes.c_double), _ptr(mask, ctypes.c_uint8),
+            _ptr(counts, ctypes.c_uint64), _ptr(r, ctypes.c_double), _ptr(rho, ctypes.c_double),
+            _ptr(keep, ctypes.c_uint8), _ptr(g, ctypes.c_double))
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        out = {"normals": normals, "mask": mask, "counts": counts}
+        if want_r:
+            out["r"] = r
+        if want_rho:
+            out["rho"] = rho
+        if want_keep:
+            out["keep"] = keep
+        if gap:
+            out["gap"] = float(g[0])
+        return out
+
+    def variant_f64(self, depth, fx, fy, cx, cy, alpha=2, mode="rel", tau=4.0, *,
+                    method="four_pair", scales=0, want_r=False, want_rho=False,
+                    want_keep=False, gap=False):
+        """Any method, FP64 depth in, FP64 normals and FP64 decisions."""
+        depth = np.ascontiguousarray(depth, dtype=np.float64)
+        H, W = depth.shape
+        normals = np.zeros((H, W, 3), dtype=np.float64)
+        mask = np.zeros((H, W), dtype=np.uint8)
+        counts = np.zeros(3, dtype=np.uint64)
+        r = np.empty((H, W)) if want_r else None
+        rho = np.empty((H, W)) if want_rho else None
+        keep = np.zeros((H, W), dtype=np.uint8) if want_keep else None
+        g = np.zeros(1) if gap else None
+        rc = self.L.bno_variant_f64(
+            _method(method), int(scales), _ptr(depth, ctypes.c_double), H, W, W, fx, fy, cx, cy,
+            int(alpha), _mode(mode), tau, _ptr(normals, ctypes.c_double),
+            _ptr(mask, ctypes.c_uint8), _ptr(counts, ctypes.c_uint64), _ptr(r, ctypes.c_double),
+            _ptr(rho, ctypes.c_double), _ptr(keep, ctypes.c_uint8), _ptr(g, ctypes.c_double))
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        out = {"normals": normals, "mask": mask, "counts": counts}
+        if want_r:
+            out["r"] = r
+        if want_rho:
+            out["rho"] = rho
+        if want_keep:
+            out["keep"] = keep
+        if gap:
+            out["gap"] = float(g[0])
+        return out
+
+    def variant_abs_threshold_f32(self, method, scales, fx, fy, tau, alpha) -> float:
+        """Binary32 ABS threshold on |m|^2 of a method."""
+        return float(self.L.bno_variant_abs_threshold_f32(_method(method), int(scales), fx, fy,
+                                                          tau, int(alpha)))
+
     def abs_threshold_f32(self, fx, fy, tau, alpha) -> float:
         """Binary32 threshold on |m|^2 that ABS mode compares against."""
         return float(self.L.bno_abs_threshold_f32(fx, fy, tau, int(alpha)))
@@ -217,6 +313,14 @@ def normals_f32_rows(*args, **kw):
 
 def abs_threshold_f32(*args, **kw):
     return default().abs_threshold_f32(*args, **kw)
+
+
+def variant_f32(*args, **kw):
+    return default().variant_f32(*args, **kw)
+
+
+def variant_f64(*args, **kw):
+    return default().variant_f64(*args, **kw)
 
 
 def normals_frozen_f64(*args, **kw):

@@ -509,6 +509,596 @@ int bno_normals_vjp_f64(const double *depth, int H, int W, int64_t stride,
     return ORC_OK;
 }
 
+/* ====================================================================== */
+/* Variants of the estimator                                               */
+/* ====================================================================== */
+/*
+ * Method 0, FOUR_PAIR: everything above (Section 3: the four-pair average
+ *   of Eq. 7 in its closed form, Eqs. 10-12, with the whole pixel removed by
+ *   the test of Section 3.2).
+ *
+ * Method 1, PAIR_REMOVAL: the four perpendicular-pair normals that Eq. 7
+ *   averages, n23 = s12 x s13, n34 = s13 x s14, n45 = s14 x s15 and
+ *   n52 = s15 x s12, each go through the test of Section 3.2 on their own
+ *   (r = |n_jk|, or rho = r / (n_jk . ray)); the pixel's normal is the
+ *   average of the pairs that pass, and the pixel is BOUNDARY when none
+ *   passes.  Only the pairs whose tangents cross a depth discontinuity are
+ *   dropped, instead of the whole pixel.  When all four pass, the average is
+ *   Eq. 7's n exactly.  Each pair has n_jk . ray = alpha^2 d_j d_k/(fx fy) > 0
+ *   (X1 is parallel to the ray, so the triple product keeps only the
+ *   alpha-offset parts), so each pair's rho is well defined.
+ *
+ * Method 2, MULTISCALE: the authors' earlier single-pair estimator
+ *   (Section 2): the normal of the pair (2, 3), Eqs. 1-3, at pixel offsets
+ *   alpha_i = i * alpha for i = 1..K, averaged over i as in Eqs. 4-6; the
+ *   test of Section 3.2 applied to the average.  Only the taps
+ *   (x + alpha_i, y) and (x, y + alpha_i) are read, so the invalid border is
+ *   K*alpha wide on the right and bottom edges only.
+ *
+ * Binary32 decisions.  Each pair normal is decided on its scaled vector
+ *   m_jk = -(fx fy / alpha) n_jk = (fx A, fy B, -(xc A + yc B + alpha C))
+ *   with, for the horizontal tap h (2 or 4, direction sh = +1 or -1 along
+ *   u) and the vertical tap v (3 or 5, sv = +1 or -1 along v):
+ *     A = sh (d_h - d1) d_v,   B = sv d_h (d_v - d1),   C = d_h d_v,
+ *   which for the pair (2, 3) is Eqs. 1-3 multiplied by -fx fy / alpha, and
+ *   for the others follows from the same expansion of the cross product.
+ *   m_jk . ray = -alpha C, so REL compares |m_jk|^2 with tau^2 (alpha C)^2,
+ *   and ABS compares it with (fx fy tau / alpha)^2.  The four m_jk sum to
+ *   the m of method 0.
+ *   MULTISCALE sums alpha_i m(alpha_i), which is -K fx fy times the average
+ *   of Eqs. 4-6; REL compares with tau^2 (sum alpha_i^2 C_i)^2 and ABS with
+ *   (K fx fy tau)^2.
+ */
+
+#define ORC_FOUR_PAIR 0
+#define ORC_PAIR_REMOVAL 1
+#define ORC_MULTISCALE 2
+
+/* Pixel offsets of taps 1..5 (index 0 unused). */
+static const int TAP_DX[6] = {0, 0, 1, 0, -1, 0};
+static const int TAP_DY[6] = {0, 0, 0, 1, 0, -1};
+
+/* The pairs (j, k) of Eq. 7, first line, in its order. */
+static const int PAIR_J[4] = {2, 3, 4, 5};
+static const int PAIR_K[4] = {3, 4, 5, 2};
+
+/* FP64 definition: n_jk = s1j x s1k for the four pairs of Eq. 7. */
+static void pair_normals_definition(const double d[6], int x, int y, int alpha,
+                                    double fx, double fy, double cx, double cy,
+                                    double n[4][3])
+{
+    double X[6][3];
+    for (int t = 1; t <= 5; ++t)
+        backproject((double)(x + alpha * TAP_DX[t]), (double)(y + alpha * TAP_DY[t]), d[t],
+                    fx, fy, cx, cy, X[t]);
+    for (int p = 0; p < 4; ++p) {
+        double sj[3], sk[3];
+        sub3(X[PAIR_J[p]], X[1], sj);
+        sub3(X[PAIR_K[p]], X[1], sk);
+        cross3(sj, sk, n[p]);
+    }
+}
+
+/* Eqs. 1-3: the pair (2, 3) normal at pixel offset a, closed form. */
+static void single_pair_closed_form(double d1, double d2, double d3, double u1, double v1,
+                                    double fx, double fy, double a, double n[3])
+{
+    n[0] = -a / fy * d3 * (d2 - d1);                                   /* Eq. 1 */
+    n[1] = -a / fx * d2 * (d3 - d1);                                   /* Eq. 2 */
+    n[2] = a / fx * v1 * d2 * (d3 - d1) + a / fy * u1 * d3 * (d2 - d1)
+           + a * a / (fx * fy) * d2 * d3;                               /* Eq. 3 */
+}
+
+/* Binary32 scaled vector of one pair, in a fixed operation order; mz holds
+ * the negated third component, w = alpha C. */
+static void fp32_pair(float dh, float dv, float d1, int sh, int sv, float fx, float fy,
+                      float xc, float yc, float af, float *mx, float *my, float *mz,
+                      float *w, float *q)
+{
+    float eh = dh - d1;
+    float ev = dv - d1;
+    float A = eh * dv;
+    float B = dh * ev;
+    if (sh < 0) A = -A;
+    if (sv < 0) B = -B;
+    float C = dh * dv;
+    float x = fx * A;
+    float y = fy * B;
+    float xa = xc * A;
+    float yb = yc * B;
+    float t3 = xa + yb;
+    float ww = af * C;
+    float z = t3 + ww;
+    float x2 = x * x;
+    float y2 = y * y;
+    float z2 = z * z;
+    *mx = x;
+    *my = y;
+    *mz = z;
+    *w = ww;
+    *q = (x2 + y2) + z2;
+}
+
+static int q_degenerate(float q)
+{
+    return !isfinite(q) || q < FLT_MIN;
+}
+
+/* ABS thresholds of methods 1 and 2 on the binary32 |m|^2 scale, computed in
+ * double in this order and rounded once. */
+static float pair_abs_threshold_f32(float fx, float fy, float tau, int alpha)
+{
+    double k = (double)fx;
+    k = k * (double)fy;
+    k = k * (double)tau;
+    k = k / (double)alpha;
+    k = k * k;
+    return (float)k;
+}
+
+static float multiscale_abs_threshold_f32(float fx, float fy, float tau, int scales)
+{
+    double k = (double)scales;
+    k = k * (double)fx;
+    k = k * (double)fy;
+    k = k * (double)tau;
+    k = k * k;
+    return (float)k;
+}
+
+/* Method 1 binary32 decision.  Pairs in Eq. 7's order: (h, v) = (2, 3),
+ * (4, 3), (4, 5), (2, 5).  A pair whose |m|^2 is not a finite number >=
+ * FLT_MIN makes the pixel INVALID; *keep gets bit p for each pair p that
+ * passes the test; the passing pairs' scaled vectors are summed in pair
+ * order, and a sum whose |.|^2 is degenerate is INVALID too. */
+static int fp32_pairs_code(const float d[6], int x, int y, float fx, float fy, float cx,
+                           float cy, int alpha, int mode, float tau, float kpair, int *keep)
+{
+    const int th[4] = {2, 4, 4, 2};
+    const int tv[4] = {3, 3, 5, 5};
+    const int sh[4] = {1, -1, -1, 1};
+    const int sv[4] = {1, 1, -1, -1};
+    float xc = (float)x - cx;
+    float yc = (float)y - cy;
+    float af = (float)alpha;
+    float mx[4], my[4], mz[4], w[4], q[4];
+    *keep = 0;
+    for (int p = 0; p < 4; ++p) {
+        fp32_pair(d[th[p]], d[tv[p]], d[1], sh[p], sv[p], fx, fy, xc, yc, af,
+                  &mx[p], &my[p], &mz[p], &w[p], &q[p]);
+        if (q_degenerate(q[p]))
+            return ORC_INVALID;
+    }
+    int k = 0;
+    for (int p = 0; p < 4; ++p) {
+        int fire = 0;
+        if (mode == ORC_REL) {
+            float tt = tau * tau;
+            float ww = w[p] * w[p];
+            float h = tt * ww;
+            fire = q[p] > h;
+        } else if (mode == ORC_ABS) {
+            fire = q[p] > kpair;
+        }
+        if (!fire) k |= 1 << p;
+    }
+    *keep = k;
+    if (!k)
+        return ORC_BOUNDARY;
+    int first = 1;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    for (int p = 0; p < 4; ++p) {
+        if (!(k & (1 << p)))
+            continue;
+        if (first) {
+            sx = mx[p];
+            sy = my[p];
+            sz = mz[p];
+            first = 0;
+        } else {
+            sx = sx + mx[p];
+            sy = sy + my[p];
+            sz = sz + mz[p];
+        }
+    }
+    float sx2 = sx * sx;
+    float sy2 = sy * sy;
+    float sz2 = sz * sz;
+    float Q = (sx2 + sy2) + sz2;
+    return q_degenerate(Q) ? ORC_INVALID : ORC_VALID;
+}
+
+/* Method 2 binary32 decision: scales i = 1..K at offset a = i*alpha, the
+ * pair (2, 3) vector of each weighted by a and summed in scale order. */
+static int fp32_multiscale_code(float d1, const float *d2s, const float *d3s, int scales, int x,
+                                int y, float fx, float fy, float cx, float cy, int alpha, int mode,
+                                float tau, float kms)
+{
+    float xc = (float)x - cx;
+    float yc = (float)y - cy;
+    float Mx = 0.0f, My = 0.0f, Mz = 0.0f, Wt = 0.0f;
+    for (int i = 1; i <= scales; ++i) {
+        float a = (float)(i * alpha);
+        float mx, my, mz, w, q;
+        fp32_pair(d2s[i - 1], d3s[i - 1], d1, 1, 1, fx, fy, xc, yc, a, &mx, &my, &mz, &w, &q);
+        float ax = a * mx;
+        float ay = a * my;
+        float az = a * mz;
+        float aw = a * w;
+        if (i == 1) {
+            Mx = ax;
+            My = ay;
+            Mz = az;
+            Wt = aw;
+        } else {
+            Mx = Mx + ax;
+            My = My + ay;
+            Mz = Mz + az;
+            Wt = Wt + aw;
+        }
+    }
+    float x2 = Mx * Mx;
+    float y2 = My * My;
+    float z2 = Mz * Mz;
+    float q = (x2 + y2) + z2;
+    if (q_degenerate(q))
+        return ORC_INVALID;
+    if (mode == ORC_NONE)
+        return ORC_VALID;
+    float h;
+    if (mode == ORC_REL) {
+        float tt = tau * tau;
+        float ww = Wt * Wt;
+        h = tt * ww;
+    } else {
+        h = kms;
+    }
+    return (q > h) ? ORC_BOUNDARY : ORC_VALID;
+}
+
+/* FP64 output of method 1 from the passing pairs (bits of keep): the
+ * average n of the pair normals, out = -n/|n|, r = |n|, rho = r/(n . ray).
+ * gap: relative max-norm gap between the sum of all four pair normals and
+ * 4 x Eqs. 10-12. */
+static void pairs_normal_f64(const double d[6], int x, int y, double fx, double fy, double cx,
+                             double cy, int alpha, int keep, double out[3], double *r,
+                             double *rho, double *gap)
+{
+    double np[4][3];
+    pair_normals_definition(d, x, y, alpha, fx, fy, cx, cy, np);
+    double u1 = ((double)x - cx) / fx;
+    double v1 = ((double)y - cy) / fy;
+    double n[3] = {0.0, 0.0, 0.0};
+    int cnt = 0;
+    for (int p = 0; p < 4; ++p) {
+        if (!(keep & (1 << p)))
+            continue;
+        n[0] += np[p][0];
+        n[1] += np[p][1];
+        n[2] += np[p][2];
+        ++cnt;
+    }
+    if (cnt) {
+        n[0] /= cnt;
+        n[1] /= cnt;
+        n[2] /= cnt;
+    }
+    double len = norm3(n);
+    out[0] = -n[0] / len;
+    out[1] = -n[1] / len;
+    out[2] = -n[2] / len;
+    *r = len;
+    *rho = len / (n[0] * u1 + n[1] * v1 + n[2]);
+    if (gap) {
+        double all[3] = {0.0, 0.0, 0.0}, cf[3];
+        for (int p = 0; p < 4; ++p)
+            for (int c = 0; c < 3; ++c)
+                all[c] += np[p][c];
+        normal_closed_form(d[2], d[3], d[4], d[5], u1, v1, fx, fy, (double)alpha, cf);
+        double l = 4.0 * norm3(cf), e = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            double dc = fabs(all[c] - 4.0 * cf[c]);
+            if (dc > e) e = dc;
+        }
+        e = (l > 0.0) ? e / l : (e > 0.0 ? INFINITY : 0.0);
+        if (e > *gap) *gap = e;
+    }
+}
+
+/* FP64 output of method 2: Eqs. 4-6 (the average over scales of Eqs. 1-3).
+ * gap: relative gap between Eqs. 1-3 and the definition s12 x s13 at each
+ * scale. */
+static void multiscale_normal_f64(double d1, const double *d2s, const double *d3s, int scales,
+                                  int x, int y, double fx, double fy, double cx, double cy,
+                                  int alpha, double out[3], double *r, double *rho, double *gap)
+{
+    double u1 = ((double)x - cx) / fx;
+    double v1 = ((double)y - cy) / fy;
+    double n[3] = {0.0, 0.0, 0.0};
+    for (int i = 1; i <= scales; ++i) {
+        double a = (double)(i * alpha), ni[3];
+        single_pair_closed_form(d1, d2s[i - 1], d3s[i - 1], u1, v1, fx, fy, a, ni);
+        n[0] += ni[0];
+        n[1] += ni[1];
+        n[2] += ni[2];
+        if (gap) {
+            double X1[3], X2[3], X3[3], s2[3], s3[3], nd[3];
+            backproject((double)x, (double)y, d1, fx, fy, cx, cy, X1);
+            backproject((double)(x + i * alpha), (double)y, d2s[i - 1], fx, fy, cx, cy, X2);
+            backproject((double)x, (double)(y + i * alpha), d3s[i - 1], fx, fy, cx, cy, X3);
+            sub3(X2, X1, s2);
+            sub3(X3, X1, s3);
+            cross3(s2, s3, nd);
+            double l = norm3(ni), e = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                double dc = fabs(nd[c] - ni[c]);
+                if (dc > e) e = dc;
+            }
+            e = (l > 0.0) ? e / l : (e > 0.0 ? INFINITY : 0.0);
+            if (e > *gap) *gap = e;
+        }
+    }
+    n[0] /= scales;
+    n[1] /= scales;
+    n[2] /= scales;
+    double len = norm3(n);
+    out[0] = -n[0] / len;
+    out[1] = -n[1] / len;
+    out[2] = -n[2] / len;
+    *r = len;
+    *rho = len / (n[0] * u1 + n[1] * v1 + n[2]);
+}
+
+static int check_method(int method, int scales)
+{
+    if (method == ORC_FOUR_PAIR || method == ORC_PAIR_REMOVAL)
+        return (scales == 0 || scales == 1) ? ORC_OK : ORC_EARG;
+    if (method == ORC_MULTISCALE)
+        return scales >= 1 ? ORC_OK : ORC_EARG;
+    return ORC_EARG;
+}
+
+/*
+ * Any method, binary32 depth in, FP64 normals out, rows [row_begin, row_end)
+ * of the frame.  Arguments as bno_normals_f32_rows, plus:
+ *   method     0 FOUR_PAIR, 1 PAIR_REMOVAL, 2 MULTISCALE
+ *   scales     K for MULTISCALE (>= 1); 0 or 1 otherwise
+ *   keep_out   [rows][W] (nullable): PAIR_REMOVAL's passing pairs, bit p for
+ *              the p-th pair of Eq. 7 (n23, n34, n45, n52); 0 elsewhere
+ *   def_gap    (nullable) largest relative gap between each method's closed
+ *              form and its definition over the pixels it evaluates
+ * r_out and rho_out hold r and rho of the output vector of a VALID pixel
+ * (method 0: also of a BOUNDARY one), NaN otherwise.
+ */
+int bno_variant_f32_rows(int method, int scales, const float *depth, int H, int W,
+                         int64_t stride, float fx, float fy, float cx, float cy, int alpha,
+                         int mode, float tau, int row_begin, int row_end, double *normals,
+                         uint8_t *mask, uint64_t *counts, double *r_out, double *rho_out,
+                         uint8_t *keep_out, double *def_gap)
+{
+    if (check_method(method, scales) != ORC_OK)
+        return ORC_EARG;
+    if (check_common(H, W, stride, fx, fy, alpha, mode, tau) != ORC_OK)
+        return ORC_EARG;
+    if (row_begin < 0 || row_end > H || row_begin > row_end)
+        return ORC_EARG;
+    if ((H > 0 && W > 0) && (!depth || !normals || !mask))
+        return ORC_EARG;
+    if (keep_out)
+        memset(keep_out, 0, (size_t)(row_end - row_begin) * (size_t)W);
+    if (method == ORC_FOUR_PAIR)
+        return bno_normals_f32_rows(depth, H, W, stride, fx, fy, cx, cy, alpha, mode, tau,
+                                    row_begin, row_end, normals, mask, counts, r_out, rho_out,
+                                    def_gap);
+    const int K = (method == ORC_MULTISCALE) ? scales : 1;
+    const int reach = K * alpha;
+    float kabs = 0.0f;
+    if (mode == ORC_ABS)
+        kabs = (method == ORC_PAIR_REMOVAL) ? pair_abs_threshold_f32(fx, fy, tau, alpha)
+                                            : multiscale_abs_threshold_f32(fx, fy, tau, K);
+    uint64_t cnt[3] = {0, 0, 0};
+    double gap = 0.0;
+    float f2[64], f3[64];
+    double g2[64], g3[64];
+    if (K > 64)
+        return ORC_EARG;
+    for (int y = row_begin; y < row_end; ++y) {
+        for (int x = 0; x < W; ++x) {
+            int64_t i = (int64_t)(y - row_begin) * W + x;
+            int code = ORC_INVALID, keep = 0;
+            double nrm[3] = {0.0, 0.0, 0.0};
+            double r = NAN, rho = NAN;
+            const float *row = depth + (int64_t)y * stride;
+            if (method == ORC_PAIR_REMOVAL) {
+                int inside = (x - alpha >= 0) && (x + alpha <= W - 1) &&
+                             (y - alpha >= 0) && (y + alpha <= H - 1);
+                if (inside) {
+                    float d[6];
+                    int ok = 1;
+                    for (int t = 1; t <= 5; ++t) {
+                        d[t] = depth[(int64_t)(y + alpha * TAP_DY[t]) * stride +
+                                     (x + alpha * TAP_DX[t])];
+                        ok = ok && tap_ok_f32(d[t]);
+                    }
+                    if (ok) {
+                        code = fp32_pairs_code(d, x, y, fx, fy, cx, cy, alpha, mode, tau,
+                                               kabs, &keep);
+                        if (code == ORC_VALID) {
+                            double dd[6];
+                            for (int t = 1; t <= 5; ++t) dd[t] = (double)d[t];
+                            pairs_normal_f64(dd, x, y, fx, fy, cx, cy, alpha, keep, nrm, &r,
+                                             &rho, def_gap ? &gap : NULL);
+                        }
+                    }
+                }
+            } else {
+                int inside = (x + reach <= W - 1) && (y + reach <= H - 1);
+                if (inside) {
+                    float d1 = row[x];
+                    int ok = tap_ok_f32(d1);
+                    for (int s = 1; s <= K; ++s) {
+                        f2[s - 1] = row[x + s * alpha];
+                        f3[s - 1] = depth[(int64_t)(y + s * alpha) * stride + x];
+                        ok = ok && tap_ok_f32(f2[s - 1]) && tap_ok_f32(f3[s - 1]);
+                    }
+                    if (ok) {
+                        code = fp32_multiscale_code(d1, f2, f3, K, x, y, fx, fy, cx, cy, alpha,
+                                                    mode, tau, kabs);
+                        if (code == ORC_VALID) {
+                            for (int s = 0; s < K; ++s) {
+                                g2[s] = (double)f2[s];
+                                g3[s] = (double)f3[s];
+                            }
+                            multiscale_normal_f64((double)d1, g2, g3, K, x, y, fx, fy, cx, cy,
+                                                  alpha, nrm, &r, &rho, def_gap ? &gap : NULL);
+                        }
+                    }
+                }
+            }
+            normals[3 * i + 0] = nrm[0];
+            normals[3 * i + 1] = nrm[1];
+            normals[3 * i + 2] = nrm[2];
+            mask[i] = (uint8_t)code;
+            if (keep_out) keep_out[i] = (uint8_t)keep;
+            if (r_out) r_out[i] = r;
+            if (rho_out) rho_out[i] = rho;
+            cnt[code] += 1;
+        }
+    }
+    if (counts) {
+        counts[0] = cnt[0];
+        counts[1] = cnt[1];
+        counts[2] = cnt[2];
+    }
+    if (def_gap) *def_gap = gap;
+    return ORC_OK;
+}
+
+/*
+ * Any method, FP64 depth in, everything in FP64 (closed-form tests on exact
+ * depth).  The tests of Section 3.2 are taken in FP64: a pair (method 1) or
+ * the average (methods 0 and 2) fires when rho > tau (REL) or r > tau (ABS).
+ * A pixel whose output vector has a length that is not finite and > 0 is
+ * INVALID.
+ */
+int bno_variant_f64(int method, int scales, const double *depth, int H, int W, int64_t stride,
+                    double fx, double fy, double cx, double cy, int alpha, int mode, double tau,
+                    double *normals, uint8_t *mask, uint64_t *counts, double *r_out,
+                    double *rho_out, uint8_t *keep_out, double *def_gap)
+{
+    if (check_method(method, scales) != ORC_OK)
+        return ORC_EARG;
+    if (check_common(H, W, stride, fx, fy, alpha, mode, tau) != ORC_OK)
+        return ORC_EARG;
+    if ((H > 0 && W > 0) && (!depth || !normals || !mask))
+        return ORC_EARG;
+    if (keep_out)
+        memset(keep_out, 0, (size_t)H * (size_t)W);
+    if (method == ORC_FOUR_PAIR)
+        return bno_normals_f64(depth, H, W, stride, fx, fy, cx, cy, alpha, mode, tau, normals,
+                               mask, counts, r_out, rho_out, def_gap);
+    const int K = (method == ORC_MULTISCALE) ? scales : 1;
+    if (K > 64)
+        return ORC_EARG;
+    const int reach = K * alpha;
+    uint64_t cnt[3] = {0, 0, 0};
+    double gap = 0.0;
+    double g2[64], g3[64];
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            int64_t i = (int64_t)y * W + x;
+            int code = ORC_INVALID, keep = 0;
+            double nrm[3] = {0.0, 0.0, 0.0};
+            double r = NAN, rho = NAN;
+            const double *row = depth + (int64_t)y * stride;
+            double u1 = ((double)x - cx) / fx;
+            double v1 = ((double)y - cy) / fy;
+            if (method == ORC_PAIR_REMOVAL) {
+                int inside = (x - alpha >= 0) && (x + alpha <= W - 1) &&
+                             (y - alpha >= 0) && (y + alpha <= H - 1);
+                double d[6];
+                int ok = inside;
+                for (int t = 1; ok && t <= 5; ++t) {
+                    d[t] = depth[(int64_t)(y + alpha * TAP_DY[t]) * stride +
+                                 (x + alpha * TAP_DX[t])];
+                    ok = tap_ok_f64(d[t]);
+                }
+                if (ok) {
+                    double np[4][3];
+                    pair_normals_definition(d, x, y, alpha, fx, fy, cx, cy, np);
+                    for (int p = 0; p < 4; ++p) {
+                        double rp = norm3(np[p]);
+                        double rhop = rp / (np[p][0] * u1 + np[p][1] * v1 + np[p][2]);
+                        int fire = 0;
+                        if (mode == ORC_ABS) fire = rp > tau;
+                        else if (mode == ORC_REL) fire = rhop > tau;
+                        if (!fire) keep |= 1 << p;
+                    }
+                    if (!keep) {
+                        code = ORC_BOUNDARY;
+                    } else {
+                        pairs_normal_f64(d, x, y, fx, fy, cx, cy, alpha, keep, nrm, &r, &rho,
+                                         def_gap ? &gap : NULL);
+                        code = (isfinite(r) && r > 0.0) ? ORC_VALID : ORC_INVALID;
+                    }
+                }
+            } else {
+                int inside = (x + reach <= W - 1) && (y + reach <= H - 1);
+                int ok = inside;
+                double d1 = ok ? row[x] : 0.0;
+                ok = ok && tap_ok_f64(d1);
+                for (int s = 1; ok && s <= K; ++s) {
+                    g2[s - 1] = row[x + s * alpha];
+                    g3[s - 1] = depth[(int64_t)(y + s * alpha) * stride + x];
+                    ok = tap_ok_f64(g2[s - 1]) && tap_ok_f64(g3[s - 1]);
+                }
+                if (ok) {
+                    multiscale_normal_f64(d1, g2, g3, K, x, y, fx, fy, cx, cy, alpha, nrm, &r,
+                                          &rho, def_gap ? &gap : NULL);
+                    if (!isfinite(r) || !(r > 0.0)) {
+                        code = ORC_INVALID;
+                    } else {
+                        int fire = 0;
+                        if (mode == ORC_ABS) fire = r > tau;
+                        else if (mode == ORC_REL) fire = rho > tau;
+                        code = fire ? ORC_BOUNDARY : ORC_VALID;
+                    }
+                }
+            }
+            if (code != ORC_VALID) {
+                nrm[0] = nrm[1] = nrm[2] = 0.0;
+                if (code == ORC_INVALID) r = rho = NAN;
+            }
+            normals[3 * i + 0] = nrm[0];
+            normals[3 * i + 1] = nrm[1];
+            normals[3 * i + 2] = nrm[2];
+            mask[i] = (uint8_t)code;
+            if (keep_out) keep_out[i] = (uint8_t)keep;
+            if (r_out) r_out[i] = r;
+            if (rho_out) rho_out[i] = rho;
+            cnt[code] += 1;
+        }
+    }
+    if (counts) {
+        counts[0] = cnt[0];
+        counts[1] = cnt[1];
+        counts[2] = cnt[2];
+    }
+    if (def_gap) *def_gap = gap;
+    return ORC_OK;
+}
+
+/* Binary32 ABS thresholds of methods 1 and 2, for the closed-form tests. */
+float bno_variant_abs_threshold_f32(int method, int scales, float fx, float fy, float tau,
+                                    int alpha)
+{
+    if (method == ORC_PAIR_REMOVAL)
+        return pair_abs_threshold_f32(fx, fy, tau, alpha);
+    if (method == ORC_MULTISCALE)
+        return multiscale_abs_threshold_f32(fx, fy, tau, scales);
+    return abs_threshold_f32(fx, fy, tau, alpha);
+}
+
 /* The binary32 threshold of ABS mode, exposed for the closed-form tests. */
 float bno_abs_threshold_f32(float fx, float fy, float tau, int alpha)
 {
@@ -517,5 +1107,5 @@ float bno_abs_threshold_f32(float fx, float fy, float tau, int alpha)
 
 int bno_version(void)
 {
-    return 1;
+    return 2;
 }

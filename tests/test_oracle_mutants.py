@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import pins
+import pins_variants
 
 MUTANTS = {
     "eq10_fx_for_fy": [("n[0] = -alpha / (4.0 * fy)", "n[0] = -alpha / (4.0 * fx)")],
@@ -35,6 +36,32 @@ MUTANTS = {
     "no_degenerate_rule": [("if (!isfinite(q) || q < FLT_MIN)", "if (!isfinite(q))")],
     "boundary_keeps_normal": [("if (code == ORC_VALID) {", "if (code != ORC_INVALID) {")],
     "q_missing_mz": [("float q = (mx2 + my2) + mz2;", "float q = (mx2 + my2);")],
+    # pair removal
+    "pair_34_wrong_direction": [("const int sh[4] = {1, -1, -1, 1};",
+                                 "const int sh[4] = {1, 1, -1, 1};")],
+    "pair_taps_regrouped": [("const int tv[4] = {3, 3, 5, 5};", "const int tv[4] = {3, 5, 3, 5};")],
+    "pair_keep_inverted": [("if (!fire) k |= 1 << p;", "if (fire) k |= 1 << p;")],
+    "pair_average_ignores_test": [("        if (!(keep & (1 << p)))\n            continue;\n"
+                                   "        n[0] += np[p][0];", "        n[0] += np[p][0];")],
+    "pair_abs_without_alpha": [("    k = k / (double)alpha;\n    k = k * k;\n    return (float)k;\n}\n\n"
+                                "static float multiscale_abs",
+                                "    k = k * k;\n    return (float)k;\n}\n\nstatic float multiscale_abs")],
+    "pair_definition_wrong_order": [("static const int PAIR_K[4] = {3, 4, 5, 2};",
+                                     "static const int PAIR_K[4] = {3, 2, 5, 4};")],
+    # multi-scale
+    "ms_same_offset_every_scale": [("float a = (float)(i * alpha);", "float a = (float)alpha;")],
+    "ms_unweighted_scales": [("float ax = a * mx;", "float ax = mx;"),
+                             ("float ay = a * my;", "float ay = my;"),
+                             ("float az = a * mz;", "float az = mz;"),
+                             ("float aw = a * w;", "float aw = w;")],
+    "ms_abs_without_K": [("    double k = (double)scales;\n    k = k * (double)fx;",
+                          "    double k = 1.0;\n    k = k * (double)fx;")],
+    "ms_border_both_sides": [("int inside = (x + reach <= W - 1) && (y + reach <= H - 1);",
+                              "int inside = (x + reach <= W - 1) && (y + reach <= H - 1) && "
+                              "(x - reach >= 0);")],
+    "ms_sum_not_averaged": [("    n[0] /= scales;\n    n[1] /= scales;\n    n[2] /= scales;\n", "")],
+    "ms_eq2_fx_for_fy": [("n[1] = -a / fx * d2 * (d3 - d1);", "n[1] = -a / fy * d2 * (d3 - d1);")],
+    "ms_eq3_sign_u1": [("+ a / fy * u1 * d3 * (d2 - d1)", "- a / fy * u1 * d3 * (d2 - d1)")],
 }
 
 
@@ -56,7 +83,7 @@ def test_mutant_is_caught(name, tmp_path):
     subprocess.check_call(["gcc", *oracle.GCC_FLAGS, str(c), "-o", str(so), "-lm"])
     o = oracle.Oracle(str(so))
     failed = []
-    for pin in pins.ALL_PINS:
+    for pin in pins.ALL_PINS + pins_variants.VARIANT_PINS:
         try:
             pin(o)
         except (AssertionError, ValueError, FloatingPointError):
