@@ -18,11 +18,28 @@
  * that is the camera-facing unit vector -n/|n| when the code is BN_VALID and
  * (0, 0, 0) otherwise.
  *
+ * Methods (bn_params.method):
+ *   BN_METHOD_FOUR_PAIR (default) the paper's estimator as above: the
+ *       four-pair average, the whole pixel removed by the test.
+ *   BN_METHOD_PAIR_REMOVAL each of the four perpendicular-pair normals that
+ *       Eq. 7 averages, n23 = s12 x s13, n34, n45, n52, is tested on its
+ *       own; the normal is the average of the pairs that pass, and the pixel
+ *       is BOUNDARY only when none passes.  Only the tangent pairs that
+ *       cross a depth discontinuity are dropped.  With all four passing, the
+ *       result is the four-pair one.
+ *   BN_METHOD_MULTISCALE the authors' earlier single-pair estimator
+ *       (Section 2, Eqs. 1-3: the pair (2, 3) only) at offsets alpha_i =
+ *       i*alpha, i = 1..scales, averaged over i as in Eqs. 4-6, with the
+ *       test on the average.  Reads (x + alpha_i, y) and (x, y + alpha_i).
+ *
  * Codes:
- *   BN_INVALID  the stencil leaves the image; or one of the five taps is not
- *               a finite depth > 0 (holes are 0); or the binary32 squared
- *               length below is not a finite number >= FLT_MIN.
- *   BN_BOUNDARY otherwise, when the threshold test fires;
+ *   BN_INVALID  the stencil leaves the image (four-pair and pair removal:
+ *               a border of alpha on every side; multi-scale: scales*alpha
+ *               on the right and bottom); or a tap read is not a finite
+ *               depth > 0 (holes are 0); or a binary32 squared length below
+ *               is not a finite number >= FLT_MIN.
+ *   BN_BOUNDARY otherwise, when the threshold test fires (pair removal:
+ *               for all four pairs);
  *   BN_VALID    otherwise.
  *
  * The threshold test is decided in IEEE binary32, with this exact order of
@@ -40,6 +57,26 @@
  * of the same sequence.  The normal itself is (mx, my, -mz)/sqrt(q) in
  * binary32 (within 1e-5 per component of the FP64 value for intrinsics of
  * ordinary cameras, |x - cx|/fx and |y - cy|/fy up to about 2).
+ *
+ * Pair removal, per pair p in Eq. 7's order (h, v) = (2,3), (4,3), (4,5),
+ * (2,5), with directions (sh, sv) = (+,+), (-,+), (-,-), (+,-):
+ *     eh=dh-d1  ev=dv-d1  A=eh*dv  B=dh*ev  (negated where sh, sv is -)
+ *     C=dh*dv   then mx, my, t3, w, mz, q as above with a=A, b=B, c=C
+ *   (m_p = -(fx fy / alpha) n_p).  Any pair's q not a finite number >=
+ *   FLT_MIN: INVALID.  REL fires for the pair iff q > (tau*tau)*(w*w); ABS
+ *   iff q > (float)(((fx*fy)*tau)/alpha)^2 (double), i.e. |n_p| > tau.  The
+ *   passing pairs' mx, my, mz are summed in pair order from +0 (sx, sy,
+ *   sz); Q=((sx*sx)+(sy*sy))+(sz*sz) not a finite number >= FLT_MIN:
+ *   INVALID.  Normal (sx, sy, -sz)/sqrt(Q).  When all four pairs pass, the
+ *   sum is the four-pair m (Eq. 7) and is taken in its closed form instead:
+ *   (sx, sy, sz, Q) = (mx, my, mz, q) of the four-pair sequence, in which
+ *   d1 cancels exactly rather than through rounded sums.
+ * Multi-scale: for i = 1..K, a=(float)(i*alpha), taps d2 = (x+i*alpha, y),
+ *   d3 = (x, y+i*alpha): e2=d2-d1 e3=d3-d1 A=e2*d3 B=d2*e3 C=d2*d3, then
+ *   mx, my, t3, mz as above with w=a*C; Mx+=a*mx  My+=a*my  Mz+=a*mz
+ *   Wt+=a*w (from +0, in scale order); q=((Mx*Mx)+(My*My))+(Mz*Mz).  REL
+ *   fires iff q > (tau*tau)*(Wt*Wt); ABS iff q > (float)((((K*fx)*fy)*tau)^2)
+ *   (double), i.e. |average of Eqs. 4-6| > tau.  Normal (Mx, My, -Mz)/sqrt(q).
  *
  * Conventions
  *   - Every array argument is a DEVICE pointer (HBM of the current HIP
@@ -63,7 +100,7 @@
 extern "C" {
 #endif
 
-#define BN_VERSION 1
+#define BN_VERSION 2
 
 /* status codes */
 #define BN_OK 0
@@ -83,8 +120,17 @@ extern "C" {
 #define BN_BOUNDARY 1
 #define BN_INVALID 2
 
+/* methods */
+#define BN_METHOD_FOUR_PAIR 0
+#define BN_METHOD_PAIR_REMOVAL 1
+#define BN_METHOD_MULTISCALE 2
+
+/* flags */
+#define BN_FLAG_COUNTS_OVERWRITE 1u /* counts replace n_valid/n_boundary/n_invalid */
+
 /* limits */
 #define BN_MAX_ALPHA 8
+#define BN_MAX_SCALES 8
 #define BN_MAX_WIDTH 65536
 #define BN_MAX_PIXELS (1LL << 28)
 
@@ -95,16 +141,21 @@ typedef struct bn_params {
     uint32_t variant;  /* 0 = library's choice; else a kernel variant id
                           (bn_variant_count / bn_variant_name), for tests and
                           tuning: every variant writes identical output */
-} bn_params;
+    int32_t method;    /* BN_METHOD_*; 0 = the paper's four-pair estimator */
+    int32_t scales;    /* BN_METHOD_MULTISCALE: K, 1..BN_MAX_SCALES; others: 0 or 1 */
+    uint32_t flags;    /* 0 or BN_FLAG_COUNTS_OVERWRITE */
+    uint32_t reserved; /* 0 */
+} bn_params;          /* 32 bytes; a zeroed structure plus alpha, mode and tau
+                         selects the paper's method */
 
 /* Per-frame pixel counts by code, plus the device workspace the library uses
  * to reduce them inside the launch that produces them.
  *
- * The counts are ADDED to n_valid / n_boundary / n_invalid.  Before the
- * first use the caller zeroes the whole structure (e.g. hipMemset of
- * sizeof(bn_frame_stats) bytes); every call leaves `work` zero again, so a
- * structure can be reused indefinitely, re-zeroing only the counts when a
- * fresh total is wanted.  Two calls that overlap in time must not share one
+ * The counts are ADDED to n_valid / n_boundary / n_invalid, or, with
+ * BN_FLAG_COUNTS_OVERWRITE in params->flags, REPLACE them (no zeroing
+ * needed between calls).  Before the first use the caller zeroes the whole
+ * structure (e.g. hipMemset of sizeof(bn_frame_stats) bytes); every call
+ * leaves `work` zero again, so a structure can be reused indefinitely.  Two calls that overlap in time must not share one
  * structure.  Place it at a 128-byte aligned address (the workspace is one
  * 128-byte cache line per reduction slot). */
 #define BN_STATS_SLOTS 32
@@ -134,15 +185,17 @@ typedef struct bn_frame {
  * One frame: normals, mask and (if stats != NULL) counts.
  *   depth     [height][depth_stride] binary32 depth (z, > 0; 0 = hole)
  *   fx, fy    focal lengths in pixels (finite, > 0); cx, cy principal point
- *   params    alpha, mode, tau, variant (host pointer, read during the call)
+ *   params    alpha, mode, tau, variant, method, scales, flags (host
+ *             pointer, read during the call)
  *   normals   [height][width][3] binary32 out
  *   mask      [height][width] uint8 out (BN_VALID / BN_BOUNDARY / BN_INVALID)
  *   stats     one bn_frame_stats (zeroed before first use), counts added
  *             (nullable)
  * height or width 0: nothing to do, BN_OK.  Limits: width <= BN_MAX_WIDTH,
  * height*width <= BN_MAX_PIXELS.  Returns BN_OK, BN_ERR_INVALID_ARG,
- * BN_ERR_UNSUPPORTED (alpha > BN_MAX_ALPHA, or a forced variant whose
- * layout requirement the buffers do not meet) or BN_ERR_DEVICE.
+ * BN_ERR_UNSUPPORTED (alpha > BN_MAX_ALPHA, scales > BN_MAX_SCALES, or a
+ * forced variant that the method or the buffers' layout does not allow:
+ * the multi-scale method has the scalar variant only) or BN_ERR_DEVICE.
  */
 int bn_estimate_normals(const float *depth, int32_t height, int32_t width,
                         int64_t depth_stride, float fx, float fy, float cx, float cy,
@@ -159,7 +212,8 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width,
  * gradient only through its four neighbours' normals.
  *   grad_normals [height][width][3] binary32, dense
  *   grad_depth   [height][width] binary32 out, dense, overwritten
- * Same argument rules and errors as bn_estimate_normals (params->variant 0).
+ * Same argument rules and errors as bn_estimate_normals (params->variant 0);
+ * BN_ERR_UNSUPPORTED for a method other than BN_METHOD_FOUR_PAIR.
  */
 int bn_normals_vjp(const float *depth, int32_t height, int32_t width, int64_t depth_stride,
                    float fx, float fy, float cx, float cy, const bn_params *params,
@@ -172,7 +226,8 @@ int bn_normals_vjp(const float *depth, int32_t height, int32_t width, int64_t de
  * single kernel node that processes every tile of every frame; running the
  * plan replays the graph.  Frames are described by bn_frame (device
  * pointers, owned by the caller, which must stay valid while the plan runs).
- * All frames share `params` (alpha, mode, tau; params->variant must be 0);
+ * All frames share `params` (alpha, mode, tau, method, scales, flags;
+ * params->variant must be 0);
  * each frame has its own size, stride, intrinsics and outputs, and its
  * counts go to its own bn_frame_stats (zeroed before first use) or nowhere
  * (stats = NULL).  Each frame's outputs are identical to those of
@@ -235,8 +290,9 @@ int bn_autotune_entries(void);
  * Requests are queued first come, first served.  A request is admitted when
  * its slot - normals (12 B/px), mask (1 B/px), a bn_frame_stats and, for a
  * depth in host memory, a copy of the depth (4 B/px) - fits in the HBM
- * budget; admission zeroes its counts and starts the host-to-device copy on
- * a copy stream.  Whenever fewer than max_batches_in_flight launches are
+ * budget; admission starts the host-to-device copy of a host depth on a
+ * copy stream (a device depth is used in place).  Launches store each
+ * request's counts (BN_FLAG_COUNTS_OVERWRITE is implied).  Whenever fewer than max_batches_in_flight launches are
  * queued on the GPU, all admitted requests whose input is on the device (up
  * to max_batch) form one batched launch (bn_batch_plan) on a compute
  * stream.  New requests are therefore admitted and copied while earlier

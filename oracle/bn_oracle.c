@@ -685,6 +685,12 @@ static int fp32_pairs_code(const float d[6], int x, int y, float fx, float fy, f
     *keep = k;
     if (!k)
         return ORC_BOUNDARY;
+    /* All four pass: their average is Eq. 7's n, taken in its closed form
+     * (Eqs. 10-12, the four-pair sequence above), in which d1 cancels
+     * exactly instead of through rounded sums. */
+    if (k == 15)
+        return fp32_code(d[2], d[3], d[4], d[5], x, y, fx, fy, cx, cy, alpha, ORC_NONE, tau,
+                         0.0f);
     int first = 1;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     for (int p = 0; p < 4; ++p) {

@@ -31,7 +31,13 @@ class BnError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_int32), ("mask_mode", ctypes.c_int32),
-                ("tau", ctypes.c_float), ("variant", ctypes.c_uint32)]
+                ("tau", ctypes.c_float), ("variant", ctypes.c_uint32),
+                ("method", ctypes.c_int32), ("scales", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+METHODS = {"four_pair": 0, "pair_removal": 1, "multiscale": 2}
+FLAG_COUNTS_OVERWRITE = 1
 
 
 STATS_SLOTS = 32
@@ -139,9 +145,14 @@ def variants() -> Sequence[Tuple[int, str]]:
     return [(i, L.bn_variant_name(i).decode()) for i in range(1, L.bn_variant_count() + 1)]
 
 
-def make_params(alpha: int = 2, mode="rel", tau: float = 4.0, variant: int = 0) -> Params:
+def make_params(alpha: int = 2, mode="rel", tau: float = 4.0, variant: int = 0,
+                method="four_pair", scales: int = 0, overwrite_counts: bool = False) -> Params:
+    """bn_params: method is "four_pair" (the paper's estimator), "pair_removal"
+    or "multiscale" (with `scales` = K offsets alpha, 2 alpha, .., K alpha)."""
     m = MODES[mode] if isinstance(mode, str) else int(mode)
-    return Params(int(alpha), m, float(tau), int(variant))
+    me = METHODS[method] if isinstance(method, str) else int(method)
+    return Params(int(alpha), m, float(tau), int(variant), me, int(scales),
+                  FLAG_COUNTS_OVERWRITE if overwrite_counts else 0, 0)
 
 
 def _stream_handle(stream) -> int:
@@ -162,15 +173,17 @@ def _check_depth(depth):
 
 
 def estimate_normals(depth, fx: float, fy: float, cx: float, cy: float, alpha: int = 2,
-                     mode="rel", tau: float = 4.0, *, variant: int = 0,
+                     mode="rel", tau: float = 4.0, *, variant: int = 0, method="four_pair",
+                     scales: int = 0, overwrite_counts: bool = False,
                      normals=None, mask=None, stats=None, want_stats: bool = True,
                      stream=None):
     """Normals [H,W,3] float32, codes [H,W] uint8 and counts for one frame.
 
     `stats` (an int32 tensor of STATS_WORDS holding a zero-initialised
     bn_frame_stats; words 0..2 are the VALID / BOUNDARY / INVALID counts) is
-    accumulated into when given; otherwise a zeroed one is allocated when
-    want_stats.  Returns (normals, mask, stats_or_None).
+    accumulated into when given (replaced with overwrite_counts); otherwise
+    a zeroed one is allocated when want_stats.  Returns (normals, mask,
+    stats_or_None).
     """
     import torch
     _check_depth(depth)
@@ -191,7 +204,7 @@ def estimate_normals(depth, fx: float, fy: float, cx: float, cy: float, alpha: i
                               or not stats.is_contiguous() or stats.data_ptr() % 128):
         raise ValueError(f"stats must be a contiguous, 128-byte aligned int32 tensor of "
                          f"{STATS_WORDS} elements (bn_frame_stats)")
-    p = make_params(alpha, mode, tau, variant)
+    p = make_params(alpha, mode, tau, variant, method, scales, overwrite_counts)
     stride = depth.stride(0) if H > 0 else W
     rc = lib().bn_estimate_normals(
         ctypes.c_void_p(depth.data_ptr()), H, W, stride, fx, fy, cx, cy, ctypes.byref(p),
@@ -247,11 +260,12 @@ class BatchFrame:
 class BatchPlan:
     """A bn_batch_plan: every frame of the list in one persistent launch."""
 
-    def __init__(self, frames, alpha: int = 2, mode="rel", tau: float = 4.0):
+    def __init__(self, frames, alpha: int = 2, mode="rel", tau: float = 4.0, *,
+                 method="four_pair", scales: int = 0, overwrite_counts: bool = False):
         L = lib()
         self._frames = list(frames)
         arr = (Frame * len(self._frames))(*[f._c() for f in self._frames])
-        self.params = make_params(alpha, mode, tau, 0)
+        self.params = make_params(alpha, mode, tau, 0, method, scales, overwrite_counts)
         h = ctypes.c_void_p()
         rc = L.bn_batch_plan_create(arr, len(self._frames), ctypes.byref(self.params),
                                     ctypes.byref(h))
@@ -313,9 +327,10 @@ class BatchPlan:
 # autotuning table
 # ---------------------------------------------------------------------------
 
-def autotune_plain(height: int, width: int, alpha: int = 2, mode="rel", tau: float = 4.0):
+def autotune_plain(height: int, width: int, alpha: int = 2, mode="rel", tau: float = 4.0, *,
+                   method="four_pair", scales: int = 0):
     """Time every plain variant on frames of this size; returns (variant, us)."""
-    p = make_params(alpha, mode, tau, 0)
+    p = make_params(alpha, mode, tau, 0, method, scales)
     best, us = ctypes.c_int32(), ctypes.c_float()
     rc = lib().bn_autotune_plain(int(height), int(width), ctypes.byref(p), ctypes.byref(best),
                                  ctypes.byref(us))
@@ -487,11 +502,11 @@ class Server:
     def __init__(self, budget_bytes: int, max_batch: int = 64, max_batches_in_flight: int = 2,
                  alpha: int = 2, mode="rel", tau: float = 4.0, backend: str = "hip",
                  fake_ns_per_pixel: float = 0.004, fake_launch_ns: float = 5000.0,
-                 fake_copy_gbs: float = 25.0):
+                 fake_copy_gbs: float = 25.0, *, method="four_pair", scales: int = 0):
         L = lib()
         _bind_server(L)
         cfg = ServerConfig(int(budget_bytes), int(max_batch), int(max_batches_in_flight),
-                           make_params(alpha, mode, tau, 0),
+                           make_params(alpha, mode, tau, 0, method, scales),
                            BACKEND_FAKE if backend == "fake" else BACKEND_HIP, 0,
                            float(fake_ns_per_pixel), float(fake_launch_ns), float(fake_copy_gbs))
         h = ctypes.c_void_p()

@@ -124,7 +124,8 @@ extern "C" int bn_normals_vjp(const float *depth, int32_t height, int32_t width,
                               float *grad_depth, void *stream) {
     int rc = check_params_args(params);
     if (rc != BN_OK) return rc;
-    if (params->variant != VAR_AUTO) return BN_ERR_UNSUPPORTED;
+    if (params->variant != VAR_AUTO || params->method != BN_METHOD_FOUR_PAIR)
+        return BN_ERR_UNSUPPORTED;
     // the frame checks of the forward entry point; the gradients stand in
     // for its outputs
     rc = check_frame_args(depth, height, width, depth_stride, fx, fy, cx, cy,

@@ -1,6 +1,6 @@
-// Autotuner: measured choice of the plain kernel variant per (alpha, frame
-// size class) and of the persistent grid (workgroups per compute unit) of
-// batch plans.  Choices live in a process-wide table keyed by the GPU
+// Autotuner: measured choice of the plain kernel variant per (method, alpha,
+// frame size class) and of the grid shape (flat, or persistent workgroups
+// per compute unit) of batch plans.  Choices live in a process-wide table keyed by the GPU
 // architecture name; the table can be saved to and loaded from a small JSON
 // file, and is loaded from $BN_AUTOTUNE_CACHE on first use when that is set.
 #include <cstdio>
@@ -20,6 +20,7 @@ namespace {
 struct Entry {
     std::string arch;
     int kind;   // 0 plain, 1 batch
+    int method;
     int alpha;
     int cls;    // bit length of the pixel count
     int value;  // variant id or workgroups per CU
@@ -60,7 +61,8 @@ void ensure_env_loaded_locked() {
 
 void put_locked(const Entry &e) {
     for (auto &x : g_table) {
-        if (x.arch == e.arch && x.kind == e.kind && x.alpha == e.alpha && x.cls == e.cls) {
+        if (x.arch == e.arch && x.kind == e.kind && x.method == e.method && x.alpha == e.alpha &&
+            x.cls == e.cls) {
             x = e;
             return;
         }
@@ -68,9 +70,11 @@ void put_locked(const Entry &e) {
     g_table.push_back(e);
 }
 
-const Entry *find_locked(const std::string &arch, int kind, int alpha, int cls) {
+const Entry *find_locked(const std::string &arch, int kind, int method, int alpha, int cls) {
     for (const auto &x : g_table)
-        if (x.arch == arch && x.kind == kind && x.alpha == alpha && x.cls == cls) return &x;
+        if (x.arch == arch && x.kind == kind && x.method == method && x.alpha == alpha &&
+            x.cls == cls)
+            return &x;
     return nullptr;
 }
 
@@ -82,13 +86,13 @@ int load_locked(const char *path) {
     char line[512];
     while (std::fgets(line, sizeof(line), fh)) {
         char arch[64], kind[16];
-        int alpha, cls, value;
+        int method, alpha, cls, value;
         float us;
         if (std::sscanf(line,
-                        " {\"arch\": \"%63[^\"]\", \"kind\": \"%15[^\"]\", \"alpha\": %d, "
-                        "\"class\": %d, \"value\": %d, \"us\": %f}",
-                        arch, kind, &alpha, &cls, &value, &us) == 6) {
-            Entry e{arch, std::strcmp(kind, "batch") == 0 ? 1 : 0, alpha, cls, value, us};
+                        " {\"arch\": \"%63[^\"]\", \"kind\": \"%15[^\"]\", \"method\": %d, "
+                        "\"alpha\": %d, \"class\": %d, \"value\": %d, \"us\": %f}",
+                        arch, kind, &method, &alpha, &cls, &value, &us) == 7) {
+            Entry e{arch, std::strcmp(kind, "batch") == 0 ? 1 : 0, method, alpha, cls, value, us};
             put_locked(e);
         }
     }
@@ -104,9 +108,10 @@ int save_locked(const char *path) {
     for (size_t i = 0; i < g_table.size(); ++i) {
         const Entry &e = g_table[i];
         std::fprintf(fh,
-                     " {\"arch\": \"%s\", \"kind\": \"%s\", \"alpha\": %d, \"class\": %d, "
-                     "\"value\": %d, \"us\": %.3f}%s\n",
-                     e.arch.c_str(), e.kind ? "batch" : "plain", e.alpha, e.cls, e.value, e.us,
+                     " {\"arch\": \"%s\", \"kind\": \"%s\", \"method\": %d, \"alpha\": %d, "
+                     "\"class\": %d, \"value\": %d, \"us\": %.3f}%s\n",
+                     e.arch.c_str(), e.kind ? "batch" : "plain", e.method, e.alpha, e.cls, e.value,
+                     e.us,
                      i + 1 < g_table.size() ? "," : "");
     }
     std::fprintf(fh, "]}\n");
@@ -116,26 +121,26 @@ int save_locked(const char *path) {
 
 }  // namespace
 
-int tuned_plain_variant(int alpha, uint64_t pixels) {
+int tuned_plain_variant(int method, int alpha, uint64_t pixels) {
     std::lock_guard<std::mutex> g(g_mu);
     ensure_env_loaded_locked();
     if (g_table.empty()) return 0;
-    const Entry *e = find_locked(current_arch(), 0, alpha, bit_length(pixels));
+    const Entry *e = find_locked(current_arch(), 0, method, alpha, bit_length(pixels));
     return e ? e->value : 0;
 }
 
-int tuned_batch_blocks_per_cu(int alpha, uint64_t pixels) {
+int tuned_batch_blocks_per_cu(int method, int alpha, uint64_t pixels) {
     std::lock_guard<std::mutex> g(g_mu);
     ensure_env_loaded_locked();
     if (g_table.empty()) return 0;
-    const Entry *e = find_locked(current_arch(), 1, alpha, bit_length(pixels));
+    const Entry *e = find_locked(current_arch(), 1, method, alpha, bit_length(pixels));
     return e ? e->value : 0;
 }
 
-void record_tuning(int kind, int alpha, uint64_t pixels, int value, float us) {
+void record_tuning(int kind, int method, int alpha, uint64_t pixels, int value, float us) {
     std::lock_guard<std::mutex> g(g_mu);
     ensure_env_loaded_locked();
-    put_locked(Entry{current_arch(), kind, alpha, bit_length(pixels), value, us});
+    put_locked(Entry{current_arch(), kind, method, alpha, bit_length(pixels), value, us});
     const char *p = std::getenv("BN_AUTOTUNE_CACHE");
     if (p && *p) (void)save_locked(p);
 }
@@ -233,7 +238,7 @@ int bn_autotune_plain(int32_t height, int32_t width, const bn_params *params, in
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (!best) return BN_ERR_UNSUPPORTED;
-    record_tuning(0, params->alpha, px, best, best_t);
+    record_tuning(0, params->method, params->alpha, px, best, best_t);
     if (best_variant) *best_variant = best;
     if (best_us) *best_us = best_t;
     return BN_OK;

@@ -53,7 +53,7 @@ struct BatchHeader {
 // of a tile (VALID | BOUNDARY << 16, at most 256 pixels each) into
 // wave_counts[4 t + w]; a second kernel of the same graph sums them per
 // frame.  The main kernel thus has neither atomics nor workgroup barriers.
-template <int A>
+template <int A, int M>
 __global__ __launch_bounds__(kBlock) void k_batch(const BatchFrame *__restrict__ frames,
                                                   const uint32_t *__restrict__ tile_frame,
                                                   uint32_t *__restrict__ wave_counts,
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchFrame *__restrict__
         const uint32_t seg_end = min(tend, tb + nt);
         for (; t < seg_end; ++t) {
             uint32_t cv = 0, cb = 0;
-            run_tile<A>(f, vec, t - tb, lds, cv, cb);
+            run_tile<A, M>(f, vec, t - tb, lds, cv, cb);
             if (f.stats && lane == 0) wave_counts[4 * (int64_t)t + wave] = cv | (cb << 16);
         }
         do {
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchFrame *__restrict__
 }
 
 // One workgroup per frame: sum the frame's wavefront counts and add the
-// totals to its bn_frame_stats.
+// totals to its bn_frame_stats (or store them, BN_FLAG_COUNTS_OVERWRITE).
 __global__ __launch_bounds__(kBlock) void k_batch_counts(const BatchFrame *__restrict__ frames,
                                                          const uint32_t *__restrict__ wave_counts,
                                                          uint32_t nframes) {
@@ -118,26 +118,32 @@ __global__ __launch_bounds__(kBlock) void k_batch_counts(const BatchFrame *__res
             vt += s_sum[w][0];
             bt += s_sum[w][1];
         }
-        atomicAdd(&st->n_valid, vt);
-        atomicAdd(&st->n_boundary, bt);
-        atomicAdd(&st->n_invalid, frames[fi].a.npix - vt - bt);
+        put_counts(st, vt, bt, frames[fi].a.npix, frames[fi].a.overwrite);
     }
 }
 
 typedef void (*BatchKernelFn)(const BatchFrame *, const uint32_t *, uint32_t *, uint32_t,
                               uint32_t, uint32_t);
 
-static BatchKernelFn batch_kernel(int alpha) {
+template <int M>
+static BatchKernelFn batch_kernel_m(int alpha) {
     switch (alpha) {
-        case 1: return k_batch<1>;
-        case 2: return k_batch<2>;
-        case 3: return k_batch<3>;
-        case 4: return k_batch<4>;
-        case 5: return k_batch<5>;
-        case 6: return k_batch<6>;
-        case 7: return k_batch<7>;
-        case 8: return k_batch<8>;
+        case 1: return k_batch<1, M>;
+        case 2: return k_batch<2, M>;
+        case 3: return k_batch<3, M>;
+        case 4: return k_batch<4, M>;
+        case 5: return k_batch<5, M>;
+        case 6: return k_batch<6, M>;
+        case 7: return k_batch<7, M>;
+        case 8: return k_batch<8, M>;
     }
+    return nullptr;
+}
+
+static BatchKernelFn batch_kernel(int method, int alpha) {
+    if (method == kFourPair) return batch_kernel_m<kFourPair>(alpha);
+    if (method == kPairRemoval) return batch_kernel_m<kPairRemoval>(alpha);
+    if (method == kMultiScale) return k_batch<1, kMultiScale>;  // runtime offsets
     return nullptr;
 }
 
@@ -183,8 +189,15 @@ size_t buffer_bytes(int32_t capacity, uint64_t tile_capacity) {
     return table_offset(capacity) + sizeof(uint32_t) * (size_t)tile_capacity;
 }
 
+// Vector tiles for this frame under the method?
+bool frame_vec(const bn_frame &s, int method) {
+    return method_has_vec4(method) &&
+           vec4_layout(s.depth, s.width, s.depth_stride, s.normals, s.mask);
+}
+
 // Validate the frames; total tiles and pixels.
-int count_frames(const bn_frame *frames, int32_t n, uint64_t *tiles, uint64_t *pixels) {
+int count_frames(const bn_frame *frames, int32_t n, int method, uint64_t *tiles,
+                 uint64_t *pixels) {
     uint64_t t = 0, px = 0;
     for (int32_t k = 0; k < n; ++k) {
         const bn_frame &s = frames[k];
@@ -192,7 +205,7 @@ int count_frames(const bn_frame *frames, int32_t n, uint64_t *tiles, uint64_t *p
                                   s.cy, s.normals, s.mask);
         if (rc != BN_OK) return rc;
         if (s.height > 0 && s.width > 0) {
-            const bool vec = vec4_layout(s.depth, s.width, s.depth_stride, s.normals, s.mask);
+            const bool vec = frame_vec(s, method);
             const uint64_t items = (uint64_t)s.height * (uint64_t)(vec ? s.width / 4 : s.width);
             t += (items + kBlock - 1) / kBlock;
             px += (uint64_t)s.height * (uint64_t)s.width;
@@ -218,7 +231,7 @@ int build_table(const bn_frame *frames, int32_t n, const bn_params *p, int32_t c
     uint64_t tiles = 0;
     for (int32_t k = 0; k < n; ++k) {
         const bn_frame &s = frames[k];
-        const bool vec = vec4_layout(s.depth, s.width, s.depth_stride, s.normals, s.mask);
+        const bool vec = frame_vec(s, p->method);
         BatchFrame b;
         std::memset(&b, 0, sizeof(b));
         uint64_t nt = 0;
@@ -348,10 +361,10 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
     int rc = check_params_args(params);
     if (rc != BN_OK) return rc;
     if (params->variant != VAR_AUTO) return BN_ERR_UNSUPPORTED;
-    BatchKernelFn fn = batch_kernel(params->alpha);
+    BatchKernelFn fn = batch_kernel(params->method, params->alpha);
     if (!fn) return BN_ERR_UNSUPPORTED;
     uint64_t tiles = 0, pixels = 0;
-    rc = count_frames(frames_host, n_frames, &tiles, &pixels);
+    rc = count_frames(frames_host, n_frames, params->method, &tiles, &pixels);
     if (rc != BN_OK) return rc;
 
     bn_batch_plan *pl = new (std::nothrow) bn_batch_plan();
@@ -371,7 +384,7 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
     pl->cus = cus;
     // the grid shape tuned for this alpha and batch size class, if recorded
     // (the table stores the flat shape as -1)
-    const int tuned = tuned_batch_blocks_per_cu(params->alpha, pixels);
+    const int tuned = tuned_batch_blocks_per_cu(params->method, params->alpha, pixels);
     pl->blocks_per_cu = tuned > 0 ? (uint32_t)tuned : kFlat;
     pl->grid = grid_for(tiles, cus, pl->blocks_per_cu);
     pl->total_tiles = tiles;
@@ -405,7 +418,7 @@ int bn_batch_plan_update(bn_batch_plan *plan, const bn_frame *frames_host, int32
     if (n_frames > plan->capacity) return BN_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     uint64_t tiles = 0, pixels = 0;
-    int rc = count_frames(frames_host, n_frames, &tiles, &pixels);
+    int rc = count_frames(frames_host, n_frames, plan->params.method, &tiles, &pixels);
     if (rc != BN_OK) return rc;
     const uint32_t grid = grid_for(tiles, plan->cus, plan->blocks_per_cu);
     if (tiles > 0 && (tiles + grid - 1) / grid > 4096) return BN_ERR_UNSUPPORTED;
@@ -522,8 +535,8 @@ int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_bloc
     rc = set_grid(plan, best, s);
     if (rc != BN_OK) return rc;
     // the table stores the flat shape as -1 (0 means "nothing recorded")
-    record_tuning(1, plan->params.alpha, plan->total_pixels, best == kFlat ? -1 : (int)best,
-                  best_t);
+    record_tuning(1, plan->params.method, plan->params.alpha, plan->total_pixels,
+                  best == kFlat ? -1 : (int)best, best_t);
     if (best_blocks_per_cu) *best_blocks_per_cu = (int32_t)best;
     if (best_us) *best_us = best_t;
     return BN_OK;

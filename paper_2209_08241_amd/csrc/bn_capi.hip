@@ -26,8 +26,20 @@ int check_params_args(const bn_params *p) {
     if (p->mask_mode != BN_MASK_NONE && !(finite(p->tau) && p->tau > 0.0f))
         return BN_ERR_INVALID_ARG;
     if (p->variant > (uint32_t)VAR_COUNT) return BN_ERR_INVALID_ARG;
+    if (p->method == BN_METHOD_FOUR_PAIR || p->method == BN_METHOD_PAIR_REMOVAL) {
+        if (p->scales != 0 && p->scales != 1) return BN_ERR_INVALID_ARG;
+    } else if (p->method == BN_METHOD_MULTISCALE) {
+        if (p->scales < 1) return BN_ERR_INVALID_ARG;
+        if (p->scales > BN_MAX_SCALES) return BN_ERR_UNSUPPORTED;
+    } else {
+        return BN_ERR_INVALID_ARG;
+    }
+    if ((p->flags & ~BN_FLAG_COUNTS_OVERWRITE) != 0u || p->reserved != 0u)
+        return BN_ERR_INVALID_ARG;
     return BN_OK;
 }
+
+bool method_has_vec4(int method) { return method != BN_METHOD_MULTISCALE; }
 
 int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, float fx,
                      float fy, float cx, float cy, const float *normals, const uint8_t *mask) {
@@ -59,21 +71,47 @@ static bool variant_ok(int v, const float *depth, int32_t W, int64_t stride,
     return true;
 }
 
-// r = |n| > tau on the scale of q = |m|^2: |m| = (4 fx fy / alpha) r.
-static float abs_threshold(float fx, float fy, float tau, int alpha) {
-    double k = 4.0 * (double)fx;
-    k = k * (double)fy;
-    k = k * (double)tau;
-    k = k / (double)alpha;
+static bool method_variant_ok(int method, int v, const float *depth, int32_t W, int64_t stride,
+                              const float *normals, const uint8_t *mask) {
+    const VariantInfo *vi = variant_info(v);
+    if (!vi) return false;
+    if (vi->px_per_item == 4 && !method_has_vec4(method)) return false;
+    return variant_ok(v, depth, W, stride, normals, mask);
+}
+
+// The ABS test on the method's binary32 |m|^2 scale, computed in double in
+// this order and rounded once:
+//   four-pair    r = |n|   = alpha |m| / (4 fx fy)  ->  ((((4 fx) fy) tau) / alpha)^2
+//   pair removal r = |n_p| = alpha |m_p| / (fx fy)  ->  (((fx fy) tau) / alpha)^2
+//   multi-scale  r = |avg| = |M| / (K fx fy)        ->  (((K fx) fy) tau)^2
+static float abs_threshold(int method, int scales, float fx, float fy, float tau, int alpha) {
+    double k;
+    if (method == BN_METHOD_PAIR_REMOVAL) {
+        k = (double)fx;
+        k = k * (double)fy;
+        k = k * (double)tau;
+        k = k / (double)alpha;
+    } else if (method == BN_METHOD_MULTISCALE) {
+        k = (double)scales;
+        k = k * (double)fx;
+        k = k * (double)fy;
+        k = k * (double)tau;
+    } else {
+        k = 4.0 * (double)fx;
+        k = k * (double)fy;
+        k = k * (double)tau;
+        k = k / (double)alpha;
+    }
     k = k * k;
     return (float)k;
 }
 
 static int pick_variant(const float *depth, int32_t H, int32_t W, int64_t stride,
-                        const float *normals, const uint8_t *mask, int alpha) {
-    const int tuned = tuned_plain_variant(alpha, (uint64_t)H * (uint64_t)W);
-    if (tuned > 0 && variant_ok(tuned, depth, W, stride, normals, mask)) return tuned;
-    if (vec4_layout(depth, W, stride, normals, mask)) return VAR_VEC4;
+                        const float *normals, const uint8_t *mask, int method, int alpha) {
+    const int tuned = tuned_plain_variant(method, alpha, (uint64_t)H * (uint64_t)W);
+    if (tuned > 0 && method_variant_ok(method, tuned, depth, W, stride, normals, mask))
+        return tuned;
+    if (method_has_vec4(method) && vec4_layout(depth, W, stride, normals, mask)) return VAR_VEC4;
     return VAR_SCALAR;
 }
 
@@ -94,10 +132,15 @@ void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int
     f.af = (float)p->alpha;
     f.rel = p->mask_mode == BN_MASK_REL ? 1 : 0;
     f.tt = p->tau * p->tau;
-    f.hconst = p->mask_mode == BN_MASK_ABS ? abs_threshold(fx, fy, p->tau, p->alpha) : INFINITY;
+    f.hconst = p->mask_mode == BN_MASK_ABS
+                   ? abs_threshold(p->method, p->scales, fx, fy, p->tau, p->alpha)
+                   : INFINITY;
     f.gpr = (uint32_t)(W / px_per_item);
     f.nitems = f.gpr * (uint32_t)H;
     f.npix = (uint32_t)H * (uint32_t)W;
+    f.alpha = p->alpha;
+    f.scales = p->method == BN_METHOD_MULTISCALE ? p->scales : 1;
+    f.overwrite = (p->flags & BN_FLAG_COUNTS_OVERWRITE) ? 1u : 0u;
     f.inv_gpr = 1.0 / (double)f.gpr;
 }
 
@@ -115,14 +158,15 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width, int64
     if (height == 0 || width == 0) return BN_OK;
     int v = (int)params->variant;
     if (v == VAR_AUTO) {
-        v = pick_variant(depth, height, width, depth_stride, normals, mask, params->alpha);
-    } else if (!variant_ok(v, depth, width, depth_stride, normals, mask)) {
+        v = pick_variant(depth, height, width, depth_stride, normals, mask, params->method,
+                         params->alpha);
+    } else if (!method_variant_ok(params->method, v, depth, width, depth_stride, normals, mask)) {
         return BN_ERR_UNSUPPORTED;
     }
     FrameArgs f;
     fill_frame_args(f, depth, height, width, depth_stride, fx, fy, cx, cy, params, normals, mask,
                     stats, variant_info(v)->px_per_item);
-    hipError_t e = launch_plain(v, f, (hipStream_t)stream);
+    hipError_t e = launch_plain(v, params->method, f, (hipStream_t)stream);
     return e == hipSuccess ? BN_OK : BN_ERR_DEVICE;
 }
 

@@ -1,8 +1,9 @@
 // Device-side pieces shared by every kernel of the library: the per-pixel
 // evaluation (stencil validity, the reformulated normal of Eqs. 10-12 in the
 // scaled form m = -(4 fx fy / alpha) n, the binary32 boundary decision of
-// Section 3.2), wavefront lane shifts, and the in-launch reduction of the
-// per-frame counts.
+// Section 3.2, and the two variants: per-pair removal and the multi-scale
+// single pair of Eqs. 1-6), wavefront lane shifts, and the in-launch
+// reduction of the per-frame counts.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,13 +32,21 @@ struct FrameArgs {
     float fx, fy, cx, cy;
     float af;         // (float)alpha
     float tt;         // tau*tau (REL)
-    float hconst;     // K (ABS) or +inf (NONE)
+    float hconst;     // K (ABS) or +inf (NONE), on the method's |m|^2 scale
     int32_t rel;      // 1 for REL
     uint32_t gpr;     // work items per row (W/4 for vector kernels, W for scalar)
     uint32_t nitems;  // gpr * H
     uint32_t npix;    // H * W
+    int32_t alpha;    // integer alpha (multi-scale offsets)
+    int32_t scales;   // K of the multi-scale method
+    uint32_t overwrite;  // 1: counts replace the stats counters, 0: added
     double inv_gpr;   // 1.0 / gpr
 };
+
+// Methods (bn_params.method).
+constexpr int kFourPair = BN_METHOD_FOUR_PAIR;
+constexpr int kPairRemoval = BN_METHOD_PAIR_REMOVAL;
+constexpr int kMultiScale = BN_METHOD_MULTISCALE;
 
 // A finite depth > 0: bit patterns 0x00000001 .. 0x7f7fffff.  Integer test,
 // so it does not depend on the denormal mode.
@@ -121,6 +130,163 @@ __device__ __forceinline__ PixelOut eval_pixel(bool inside, float d1, float d2, 
 }
 
 // ---------------------------------------------------------------------------
+// Pair removal.  The four perpendicular pairs of Eq. 7, n23, n34, n45, n52,
+// each as m_p = -(fx fy / alpha) n_p = (fx A, fy B, -(xc A + yc B + alpha C))
+// with, for horizontal tap h, vertical tap v and their directions sh, sv:
+//   A = sh (d_h - d1) d_v,  B = sv d_h (d_v - d1),  C = d_h d_v
+// (Eqs. 1-3 scaled for the pair (2, 3)).  Each pair is tested like the
+// four-pair vector, with w_p = alpha C; the passing pairs are summed in pair
+// order, each sum starting from +0 (adding +0 for a failing pair changes no
+// bit of the squared length).  When all four pass, the sum is the
+// four-pair m, taken in its closed form (d1 cancels exactly there, while the
+// rounded sum of the pairs can lose it to cancellation).
+// ---------------------------------------------------------------------------
+struct PairVec {
+    float mx, my, mz;  // mz: negated third component
+    float q;
+    uint32_t keep;     // 1 when the pair passes the test
+    uint32_t ok;       // 1 when q is a finite number >= FLT_MIN
+};
+
+__device__ __forceinline__ PairVec pair_vec(float A, float B, float C, float xc, float yc,
+                                            const FrameArgs &f) {
+    PairVec r;
+    r.mx = f.fx * A;
+    r.my = f.fy * B;
+    const float xa = xc * A;
+    const float yb = yc * B;
+    const float t3 = xa + yb;
+    const float w = f.af * C;
+    r.mz = t3 + w;
+    const float mx2 = r.mx * r.mx;
+    const float my2 = r.my * r.my;
+    const float mz2 = r.mz * r.mz;
+    r.q = (mx2 + my2) + mz2;
+    const float ww = w * w;
+    const float hrel = f.tt * ww;
+    const float h = f.rel ? hrel : f.hconst;
+    r.keep = r.q > h ? 0u : 1u;
+    r.ok = q_ok(r.q);
+    return r;
+}
+
+__device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, float d2, float d3,
+                                                     float d4, float d5, float xc, float yc,
+                                                     const FrameArgs &f) {
+    const float e2 = d2 - d1;
+    const float e3 = d3 - d1;
+    const float e4 = d4 - d1;
+    const float e5 = d5 - d1;
+    // (h, v) = (2, 3), (4, 3), (4, 5), (2, 5); sh, sv = ++, -+, --, +-
+    const PairVec p0 = pair_vec(e2 * d3, d2 * e3, d2 * d3, xc, yc, f);
+    const PairVec p1 = pair_vec(-(e4 * d3), d4 * e3, d4 * d3, xc, yc, f);
+    const PairVec p2 = pair_vec(-(e4 * d5), -(d4 * e5), d4 * d5, xc, yc, f);
+    const PairVec p3 = pair_vec(e2 * d5, -(d2 * e5), d2 * d5, xc, yc, f);
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    sx = sx + (p0.keep ? p0.mx : 0.0f);
+    sy = sy + (p0.keep ? p0.my : 0.0f);
+    sz = sz + (p0.keep ? p0.mz : 0.0f);
+    sx = sx + (p1.keep ? p1.mx : 0.0f);
+    sy = sy + (p1.keep ? p1.my : 0.0f);
+    sz = sz + (p1.keep ? p1.mz : 0.0f);
+    sx = sx + (p2.keep ? p2.mx : 0.0f);
+    sy = sy + (p2.keep ? p2.my : 0.0f);
+    sz = sz + (p2.keep ? p2.mz : 0.0f);
+    sx = sx + (p3.keep ? p3.mx : 0.0f);
+    sy = sy + (p3.keep ? p3.my : 0.0f);
+    sz = sz + (p3.keep ? p3.mz : 0.0f);
+    const float sx2 = sx * sx;
+    const float sy2 = sy * sy;
+    const float sz2 = sz * sz;
+    const float Qs = (sx2 + sy2) + sz2;
+    // all four pass: the four-pair closed form, in which d1 cancels exactly
+    const PixelTerms t = eval_terms(inside, d1, d2, d3, d4, d5, xc, yc, f);
+    const bool all = (p0.keep & p1.keep & p2.keep & p3.keep) != 0u;
+    sx = all ? t.mx : sx;
+    sy = all ? t.my : sy;
+    sz = all ? t.mz : sz;
+    const float Q = all ? t.q : Qs;
+    const bool ok = ((inside ? 1u : 0u) & tap_ok(d1) & tap_ok(d2) & tap_ok(d3) & tap_ok(d4) &
+                     tap_ok(d5) & p0.ok & p1.ok & p2.ok & p3.ok) != 0u;
+    const bool any = (p0.keep | p1.keep | p2.keep | p3.keep) != 0u;
+    PixelOut o;
+    o.code = !ok ? (uint32_t)BN_INVALID
+                 : (!any ? (uint32_t)BN_BOUNDARY
+                         : (q_ok(Q) ? (uint32_t)BN_VALID : (uint32_t)BN_INVALID));
+    const bool valid = o.code == BN_VALID;
+    const float inv = __builtin_amdgcn_rsqf(Q);
+    o.nx = valid ? sx * inv : 0.0f;
+    o.ny = valid ? sy * inv : 0.0f;
+    o.nz = valid ? -(sz * inv) : 0.0f;
+    return o;
+}
+
+// The five-tap methods: four-pair average or pair removal.
+template <int M>
+__device__ __forceinline__ PixelOut eval_method(bool inside, float d1, float d2, float d3,
+                                                float d4, float d5, float xc, float yc,
+                                                const FrameArgs &f) {
+    if (M == kPairRemoval) return eval_pixel_pairs(inside, d1, d2, d3, d4, d5, xc, yc, f);
+    return eval_pixel(inside, d1, d2, d3, d4, d5, xc, yc, f);
+}
+
+// ---------------------------------------------------------------------------
+// Multi-scale single pair (Eqs. 1-6): at pixel (x, y), whose row starts at
+// p = depth + y * stride + x, the pair (2, 3) vector at offsets
+// a_i = i * alpha, i = 1..K, weighted by a_i and summed in scale order
+// (-K fx fy times the average of Eqs. 4-6); REL compares with
+// tau^2 (sum a_i w_i)^2.  Only the taps right of and below the pixel are
+// read: inside means x + K alpha < W and y + K alpha < H.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ PixelOut eval_pixel_multiscale(bool inside, const float *p, float xc,
+                                                          float yc, const FrameArgs &f) {
+    const float d1 = *p;
+    uint32_t ok = (inside ? 1u : 0u) & tap_ok(d1);
+    float Mx = 0.0f, My = 0.0f, Mz = 0.0f, Wt = 0.0f;
+    if (inside) {
+        for (int i = 1; i <= f.scales; ++i) {
+            const int off = i * f.alpha;
+            const float a = (float)off;
+            const float d2 = p[off];
+            const float d3 = p[(int64_t)off * f.stride];
+            ok &= tap_ok(d2) & tap_ok(d3);
+            const float e2 = d2 - d1;
+            const float e3 = d3 - d1;
+            const float A = e2 * d3;
+            const float B = d2 * e3;
+            const float C = d2 * d3;
+            const float mx = f.fx * A;
+            const float my = f.fy * B;
+            const float xa = xc * A;
+            const float yb = yc * B;
+            const float t3 = xa + yb;
+            const float w = a * C;
+            const float mz = t3 + w;
+            Mx = Mx + a * mx;
+            My = My + a * my;
+            Mz = Mz + a * mz;
+            Wt = Wt + a * w;
+        }
+    }
+    const float x2 = Mx * Mx;
+    const float y2 = My * My;
+    const float z2 = Mz * Mz;
+    const float q = (x2 + y2) + z2;
+    const float ww = Wt * Wt;
+    const float hrel = f.tt * ww;
+    const float h = f.rel ? hrel : f.hconst;
+    PixelOut o;
+    o.code = (ok & q_ok(q)) ? (q > h ? (uint32_t)BN_BOUNDARY : (uint32_t)BN_VALID)
+                            : (uint32_t)BN_INVALID;
+    const bool valid = o.code == BN_VALID;
+    const float inv = __builtin_amdgcn_rsqf(q);
+    o.nx = valid ? Mx * inv : 0.0f;
+    o.ny = valid ? My * inv : 0.0f;
+    o.nz = valid ? -(Mz * inv) : 0.0f;
+    return o;
+}
+
+// ---------------------------------------------------------------------------
 // Wavefront lane shifts (DPP wave_shr:1 / wave_shl:1).  Lane i receives the
 // value of lane i-1 (from_left) or i+1 (from_right); the lane without a
 // source receives 0.  Every lane of the wave must execute these.
@@ -178,13 +344,15 @@ struct CountTicket {
     unsigned long long *w1;
     unsigned long long mine1;
     unsigned long long old1;
-    uint32_t ns, nparts, npix;
+    uint32_t ns, nparts, npix, overwrite;
 };
 
 __device__ __forceinline__ CountTicket count_issue(bn_frame_stats *st, uint32_t part,
                                                    uint32_t nparts, uint32_t nvalid,
-                                                   uint32_t nboundary, uint32_t npix) {
+                                                   uint32_t nboundary, uint32_t npix,
+                                                   uint32_t overwrite) {
     CountTicket k;
+    k.overwrite = overwrite;
     const uint32_t s = part % BN_STATS_SLOTS;
     k.st = st;
     k.ns = nparts / BN_STATS_SLOTS + (s < nparts % BN_STATS_SLOTS ? 1u : 0u);
@@ -194,6 +362,20 @@ __device__ __forceinline__ CountTicket count_issue(bn_frame_stats *st, uint32_t 
     k.mine1 = (unsigned long long)nvalid | ((unsigned long long)nboundary << 24) | (1ull << 48);
     k.old1 = atomicAdd(k.w1, k.mine1);
     return k;
+}
+
+// Frame totals into the counters: added, or (overwrite) stored.
+__device__ __forceinline__ void put_counts(bn_frame_stats *st, uint32_t vt, uint32_t bt,
+                                           uint32_t npix, uint32_t overwrite) {
+    if (overwrite) {
+        st->n_valid = vt;
+        st->n_boundary = bt;
+        st->n_invalid = npix - vt - bt;
+    } else {
+        atomicAdd(&st->n_valid, vt);
+        atomicAdd(&st->n_boundary, bt);
+        atomicAdd(&st->n_invalid, npix - vt - bt);
+    }
 }
 
 __device__ __forceinline__ void count_finish(const CountTicket &k) {
@@ -213,15 +395,13 @@ __device__ __forceinline__ void count_finish(const CountTicket &k) {
     atomicExch(w2, 0ull);
     const uint32_t vt = (uint32_t)(tot2 & ((1ull << 29) - 1));
     const uint32_t bt = (uint32_t)((tot2 >> 29) & ((1ull << 29) - 1));
-    atomicAdd(&k.st->n_valid, vt);
-    atomicAdd(&k.st->n_boundary, bt);
-    atomicAdd(&k.st->n_invalid, k.npix - vt - bt);
+    put_counts(k.st, vt, bt, k.npix, k.overwrite);
 }
 
 __device__ __forceinline__ void reduce_counts(bn_frame_stats *st, uint32_t part, uint32_t nparts,
                                               uint32_t nvalid, uint32_t nboundary,
-                                              uint32_t npix) {
-    count_finish(count_issue(st, part, nparts, nvalid, nboundary, npix));
+                                              uint32_t npix, uint32_t overwrite) {
+    count_finish(count_issue(st, part, nparts, nvalid, nboundary, npix, overwrite));
 }
 
 // Block-wide sum of wave-uniform counts (one workgroup barrier): the totals,
@@ -248,10 +428,11 @@ __device__ __forceinline__ void block_sum(uint32_t cv, uint32_t cb, uint32_t &v,
 
 // Block-wide sum of wave-uniform counts; thread 0 then calls reduce_counts.
 __device__ __forceinline__ void block_counts(bn_frame_stats *st, uint32_t part, uint32_t nparts,
-                                             uint32_t cv, uint32_t cb, uint32_t npix) {
+                                             uint32_t cv, uint32_t cb, uint32_t npix,
+                                             uint32_t overwrite) {
     uint32_t v, b;
     block_sum(cv, cb, v, b);
-    if (threadIdx.x == 0) reduce_counts(st, part, nparts, v, b, npix);
+    if (threadIdx.x == 0) reduce_counts(st, part, nparts, v, b, npix, overwrite);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b%8).

@@ -32,18 +32,20 @@ int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, f
 // True when the frame can use the 4-pixel vector tiles.
 bool vec4_layout(const float *depth, int32_t W, int64_t stride, const float *normals,
                  const uint8_t *mask);
+// True when the method has vector tiles (the multi-scale one has not).
+bool method_has_vec4(int method);
 // Per-frame kernel arguments (derived constants included).
 void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t stride,
                      float fx, float fy, float cx, float cy, const bn_params *p, float *normals,
                      uint8_t *mask, bn_frame_stats *stats, int px_per_item);
 
 // Autotuning table (bn_autotune.hip): 0 when nothing is recorded.
-int tuned_plain_variant(int alpha, uint64_t pixels);
-int tuned_batch_blocks_per_cu(int alpha, uint64_t pixels);
-void record_tuning(int kind, int alpha, uint64_t pixels, int value, float us);
+int tuned_plain_variant(int method, int alpha, uint64_t pixels);
+int tuned_batch_blocks_per_cu(int method, int alpha, uint64_t pixels);
+void record_tuning(int kind, int method, int alpha, uint64_t pixels, int value, float us);
 
-// Launch one frame with the given variant.  FrameArgs.gpr / nitems /
-// inv_gpr must match the variant's pixels per work item.
-hipError_t launch_plain(int variant, const FrameArgs &f, hipStream_t stream);
+// Launch one frame with the given variant and method.  FrameArgs.gpr /
+// nitems / inv_gpr must match the variant's pixels per work item.
+hipError_t launch_plain(int variant, int method, const FrameArgs &f, hipStream_t stream);
 
 }  // namespace bn

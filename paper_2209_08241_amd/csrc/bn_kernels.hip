@@ -23,20 +23,20 @@
 namespace bn {
 
 // Scalar kernel: one pixel per thread, any row stride and alignment; one
-// tile per workgroup.
-template <int A>
+// tile per workgroup.  M: the method (the multi-scale one ignores A).
+template <int A, int M>
 __global__ __launch_bounds__(kBlock) void k_scalar(FrameArgs f) {
     __shared__ TileLds lds;
     const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
     uint32_t cv = 0, cb = 0;
-    run_tile<A>(f, false, blk, lds, cv, cb);
-    if (f.stats) block_counts(f.stats, blk, gridDim.x, cv, cb, f.npix);
+    run_tile<A, M>(f, false, blk, lds, cv, cb);
+    if (f.stats) block_counts(f.stats, blk, gridDim.x, cv, cb, f.npix, f.overwrite);
 }
 
 // Vector kernel: four consecutive pixels of a row per thread, G tiles of
 // 1024 pixels per workgroup.  Requires width % 4 == 0, stride % 4 == 0,
 // 16-byte aligned depth and normals, 4-byte aligned mask.
-template <int A, int G>
+template <int A, int G, int M>
 __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
     __shared__ TileLds lds;
     const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
@@ -45,9 +45,9 @@ __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
     for (int g = 0; g < G; ++g) {
         const uint32_t tile = blk * G + g;
         if (tile * kBlock >= f.nitems) break;  // uniform over the workgroup
-        run_tile<A>(f, true, tile, lds, cv, cb);
+        run_tile<A, M>(f, true, tile, lds, cv, cb);
     }
-    if (f.stats) block_counts(f.stats, blk, gridDim.x, cv, cb, f.npix);
+    if (f.stats) block_counts(f.stats, blk, gridDim.x, cv, cb, f.npix, f.overwrite);
 }
 
 // ---------------------------------------------------------------------------
@@ -55,27 +55,38 @@ __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
 // ---------------------------------------------------------------------------
 typedef void (*KernelFn)(FrameArgs);
 
-template <template <int> class K>
+template <template <int, int> class K, int M>
 struct AlphaTable {
     static KernelFn get(int a) {
         switch (a) {
-            case 1: return K<1>::fn;
-            case 2: return K<2>::fn;
-            case 3: return K<3>::fn;
-            case 4: return K<4>::fn;
-            case 5: return K<5>::fn;
-            case 6: return K<6>::fn;
-            case 7: return K<7>::fn;
-            case 8: return K<8>::fn;
+            case 1: return K<1, M>::fn;
+            case 2: return K<2, M>::fn;
+            case 3: return K<3, M>::fn;
+            case 4: return K<4, M>::fn;
+            case 5: return K<5, M>::fn;
+            case 6: return K<6, M>::fn;
+            case 7: return K<7, M>::fn;
+            case 8: return K<8, M>::fn;
         }
         return nullptr;
     }
 };
 
-template <int A> struct ScalarK { static constexpr KernelFn fn = k_scalar<A>; };
-template <int A> struct Vec4G1 { static constexpr KernelFn fn = k_vec4<A, 1>; };
-template <int A> struct Vec4G2 { static constexpr KernelFn fn = k_vec4<A, 2>; };
-template <int A> struct Vec4G4 { static constexpr KernelFn fn = k_vec4<A, 4>; };
+template <int A, int M> struct ScalarK { static constexpr KernelFn fn = k_scalar<A, M>; };
+template <int A, int M> struct Vec4G1 { static constexpr KernelFn fn = k_vec4<A, 1, M>; };
+template <int A, int M> struct Vec4G2 { static constexpr KernelFn fn = k_vec4<A, 2, M>; };
+template <int A, int M> struct Vec4G4 { static constexpr KernelFn fn = k_vec4<A, 4, M>; };
+
+template <int M>
+static KernelFn plain_kernel(int variant, int alpha) {
+    switch (variant) {
+        case VAR_SCALAR: return AlphaTable<ScalarK, M>::get(alpha);
+        case VAR_VEC4: return AlphaTable<Vec4G1, M>::get(alpha);
+        case VAR_VEC4_G2: return AlphaTable<Vec4G2, M>::get(alpha);
+        case VAR_VEC4_G4: return AlphaTable<Vec4G4, M>::get(alpha);
+    }
+    return nullptr;
+}
 
 const VariantInfo kVariants[] = {
     {VAR_SCALAR, "scalar", 1, 1},
@@ -90,15 +101,16 @@ const VariantInfo *variant_info(int v) {
     return nullptr;
 }
 
-hipError_t launch_plain(int variant, const FrameArgs &f, hipStream_t stream) {
+hipError_t launch_plain(int variant, int method, const FrameArgs &f, hipStream_t stream) {
     const VariantInfo *vi = variant_info(variant);
     if (!vi) return hipErrorInvalidValue;
     KernelFn fn = nullptr;
-    switch (variant) {
-        case VAR_SCALAR: fn = AlphaTable<ScalarK>::get((int)f.af); break;
-        case VAR_VEC4: fn = AlphaTable<Vec4G1>::get((int)f.af); break;
-        case VAR_VEC4_G2: fn = AlphaTable<Vec4G2>::get((int)f.af); break;
-        case VAR_VEC4_G4: fn = AlphaTable<Vec4G4>::get((int)f.af); break;
+    if (method == kFourPair) {
+        fn = plain_kernel<kFourPair>(variant, f.alpha);
+    } else if (method == kPairRemoval) {
+        fn = plain_kernel<kPairRemoval>(variant, f.alpha);
+    } else if (method == kMultiScale && variant == VAR_SCALAR) {
+        fn = k_scalar<1, kMultiScale>;  // runtime offsets
     }
     if (!fn) return hipErrorInvalidValue;
     const uint64_t per_block = (uint64_t)kBlock * vi->groups_per_thread;

@@ -3,7 +3,8 @@
 // Requests wait in a FIFO queue.  A request is admitted when its slot (its
 // outputs, plus its depth when it comes from host memory, plus its counts)
 // fits in the HBM budget; admission starts its host-to-device copy on a copy
-// stream.  Whenever fewer than `max_batches_in_flight` launches are queued on
+// stream, or makes it launchable at once when its depth is already in
+// device memory (the launch stores its counts, so nothing needs zeroing).  Whenever fewer than `max_batches_in_flight` launches are queued on
 // the GPU, every admitted request whose input is on the device (up to
 // `max_batch`) goes into one batch-plan launch on the compute stream.  So new
 // requests are admitted and copied while earlier batches run, and each
@@ -132,7 +133,7 @@ class Backend {
     virtual ~Backend() {}
     virtual double now() = 0;
     virtual char *base() = 0;  // arena base address
-    virtual int start_copy(Request &r) = 0;  // zero counts, copy host depth
+    virtual int start_copy(Request &r) = 0;  // copy a host depth to its slot
     virtual bool copy_done(Request &r) = 0;
     virtual int launch(const std::vector<Request *> &batch, uint64_t id) = 0;
     virtual bool batch_done(uint64_t id) = 0;
@@ -153,6 +154,8 @@ class HipBackend : public Backend {
     // waits for the upload, not for unrelated host-to-device depth copies.
     int init(size_t budget, int32_t max_batch, int32_t in_flight, const bn_params &params) {
         params_ = params;
+        // each request's counts are its own: the batch stores them
+        params_.flags |= BN_FLAG_COUNTS_OVERWRITE;
         max_batch_ = max_batch;
         plans_.assign((size_t)in_flight + 1, nullptr);
         if (hipMalloc(&arena_, budget ? budget : 1) != hipSuccess) return BN_ERR_OOM;
@@ -187,15 +190,11 @@ class HipBackend : public Backend {
     int start_copy(Request &r) override {
         r.copy_ev = take_event();
         if (!r.copy_ev) return BN_ERR_DEVICE;
-        if (hipMemsetAsync(r.stats, 0, sizeof(bn_frame_stats), copy_) != hipSuccess)
+        float *dst = const_cast<float *>(r.dev_depth);
+        if (hipMemcpy2DAsync(dst, (size_t)r.W * 4, r.host_depth, (size_t)r.stride * 4,
+                             (size_t)r.W * 4, (size_t)r.H, hipMemcpyHostToDevice,
+                             copy_) != hipSuccess)
             return BN_ERR_DEVICE;
-        if (r.host_depth) {
-            float *dst = const_cast<float *>(r.dev_depth);
-            if (hipMemcpy2DAsync(dst, (size_t)r.W * 4, r.host_depth, (size_t)r.stride * 4,
-                                 (size_t)r.W * 4, (size_t)r.H, hipMemcpyHostToDevice,
-                                 copy_) != hipSuccess)
-                return BN_ERR_DEVICE;
-        }
         if (hipEventRecord(r.copy_ev, copy_) != hipSuccess) return BN_ERR_DEVICE;
         return BN_OK;
     }
@@ -296,7 +295,7 @@ class FakeBackend : public Backend {
     char *base() override { return reinterpret_cast<char *>(uintptr_t(1) << 40); }
     bool threaded() override { return false; }
     int start_copy(Request &r) override {
-        const double bytes = r.host_depth ? 4.0 * r.H * (double)r.W : 0.0;
+        const double bytes = 4.0 * r.H * (double)r.W;
         copy_free_ = std::max(copy_free_, t_) + bytes / (copy_gbs_ * 1e9);
         r.copy_done_at = copy_free_;
         return BN_OK;
@@ -524,6 +523,13 @@ class Server {
             if (r->host_depth) r->dev_depth = reinterpret_cast<const float *>(b + l.depth);
             r->t_admit = now;
             pending_.pop_front();
+            if (!r->host_depth) {
+                // input already on the device: launchable at once
+                r->state = BN_REQ_READY;
+                ready_.push_back(r);
+                ++changes;
+                continue;
+            }
             const int rc = be_->start_copy(*r);
             if (rc != BN_OK) {
                 r->status = rc;

@@ -47,7 +47,7 @@ struct Vec4Out {
     bool live;
 };
 
-template <int A>
+template <int A, int M>
 __device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec4Out &o) {
     constexpr int R = Win<A>::R;
     const uint32_t t = threadIdx.x;
@@ -109,8 +109,8 @@ __device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec
         const bool inside = rows_in & (x >= (uint32_t)A) & (x + A < (uint32_t)f.W);
         const float xc = (float)x - f.cx;
         const int cI = 4 * R + j;
-        const PixelOut p = eval_pixel(inside, row[cI], row[cI + A], dnv[j], row[cI - A], upv[j],
-                                      xc, yc, f);
+        const PixelOut p = eval_method<M>(inside, row[cI], row[cI + A], dnv[j], row[cI - A],
+                                          upv[j], xc, yc, f);
         o.nv[3 * j + 0] = p.nx;
         o.nv[3 * j + 1] = p.ny;
         o.nv[3 * j + 2] = p.nz;
@@ -170,14 +170,25 @@ struct ScalarOut {
     bool live;
 };
 
-template <int A>
+template <int A, int M>
 __device__ __forceinline__ void scalar_eval(const FrameArgs &f, uint32_t tile, ScalarOut &r) {
     const uint32_t i = tile * kBlock + threadIdx.x;
     const bool live = i < f.nitems;
     r.live = live;
     uint32_t code = BN_INVALID;
     float nx = 0.f, ny = 0.f, nz = 0.f;
-    if (live) {
+    if (M == kMultiScale && live) {
+        const uint32_t y = row_of(i, f.inv_gpr);
+        const uint32_t x = i - y * f.gpr;
+        const uint32_t reach = (uint32_t)(f.scales * f.alpha);
+        const bool inside = (x + reach < (uint32_t)f.W) & (y + reach < (uint32_t)f.H);
+        const float *p = f.depth + (int64_t)y * f.stride + x;
+        const PixelOut o = eval_pixel_multiscale(inside, p, (float)x - f.cx, (float)y - f.cy, f);
+        nx = o.nx;
+        ny = o.ny;
+        nz = o.nz;
+        code = o.code;
+    } else if (M != kMultiScale && live) {
         const uint32_t y = row_of(i, f.inv_gpr);
         const uint32_t x = i - y * f.gpr;
         const bool inside = (x >= (uint32_t)A) & (x + A < (uint32_t)f.W) &
@@ -192,7 +203,7 @@ __device__ __forceinline__ void scalar_eval(const FrameArgs &f, uint32_t tile, S
         }
         const float xc = (float)x - f.cx;
         const float yc = (float)y - f.cy;
-        const PixelOut o = eval_pixel(inside, d1, d2, d3, d4, d5, xc, yc, f);
+        const PixelOut o = eval_method<M>(inside, d1, d2, d3, d4, d5, xc, yc, f);
         nx = o.nx;
         ny = o.ny;
         nz = o.nz;
@@ -236,19 +247,20 @@ __device__ __forceinline__ void scalar_count(const ScalarOut &r, uint32_t &cv, u
     cb += wave_count(r.live & (r.code == BN_BOUNDARY));
 }
 
-// One whole tile of either kind.  No workgroup barrier: consecutive tiles
-// of a workgroup may overlap freely.
-template <int A>
+// One whole tile of either kind, method M.  No workgroup barrier:
+// consecutive tiles of a workgroup may overlap freely.  The multi-scale
+// method has scalar tiles only.
+template <int A, int M>
 __device__ __forceinline__ void run_tile(const FrameArgs &f, bool vec, uint32_t tile, TileLds &lds,
                                          uint32_t &cv, uint32_t &cb) {
-    if (vec) {
+    if (M != kMultiScale && vec) {
         Vec4Out o;
-        vec4_eval<A>(f, tile, o);
+        vec4_eval<A, M>(f, tile, o);
         vec4_write(f, tile, lds, o);
         if (f.stats) vec4_count(o, cv, cb);
     } else {
         ScalarOut r;
-        scalar_eval<A>(f, tile, r);
+        scalar_eval<A, M>(f, tile, r);
         scalar_write(f, tile, lds, r);
         if (f.stats) scalar_count(r, cv, cb);
     }

@@ -34,14 +34,14 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(bn.Params) == 16
+    assert ctypes.sizeof(bn.Params) == 32
     assert ctypes.sizeof(bn.FrameStats) == bn.STATS_BYTES == 4224
     assert ctypes.sizeof(bn.Frame) == 64
 
 
 def test_version_and_status_strings():
     L = bn.lib()
-    assert L.bn_version() == 1
+    assert L.bn_version() == 2
     for s in range(5):
         assert L.bn_status_string(s)
     assert L.bn_status_string(99) == b"unknown status"
@@ -56,6 +56,16 @@ def test_version_and_status_strings():
     (dict(tau=float("inf")), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
     (dict(mode=3), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
     (dict(variant=17), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(method=3), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(method=-1), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(method="four_pair", scales=2), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(method="pair_removal", scales=3), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(method="multiscale", scales=0), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
+    (dict(method="multiscale", scales=9), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_UNSUPPORTED),
+    (dict(method="multiscale", scales=2, variant=2), (8, 8, 8, 500.0, 500.0),
+     bn.BN_ERR_UNSUPPORTED),
+    (dict(method="multiscale", scales=2, variant=4), (8, 8, 8, 500.0, 500.0),
+     bn.BN_ERR_UNSUPPORTED),
     (dict(), (8, 8, 7, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
     (dict(), (-1, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
     (dict(), (8, 8, 8, -5.0, 500.0), bn.BN_ERR_INVALID_ARG),
@@ -69,6 +79,29 @@ def test_argument_errors_before_launch(kw, dims, want):
     # fake, never-dereferenced addresses: validation fails before any HIP call
     rc = bn.raw_estimate_normals(0x10000, H, W, stride, fx, fy, 3.5, 3.5, p, 0x20000, 0x30000, 0)
     assert rc == want
+
+
+def test_flags_and_reserved_checked():
+    p = bn.make_params()
+    p.flags = 2
+    assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, p, 0x20000,
+                                   0x30000, 0) == bn.BN_ERR_INVALID_ARG
+    p = bn.make_params(overwrite_counts=True)
+    assert p.flags == bn.FLAG_COUNTS_OVERWRITE
+    p.reserved = 1
+    assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, p, 0x20000,
+                                   0x30000, 0) == bn.BN_ERR_INVALID_ARG
+
+
+def test_adjoint_only_for_the_four_pair_method():
+    L = bn.lib()
+    for method, scales in (("pair_removal", 0), ("multiscale", 2)):
+        p = bn.make_params(method=method, scales=scales)
+        rc = L.bn_normals_vjp(ctypes.c_void_p(0x10000), 8, 8, 8, ctypes.c_float(500.0),
+                              ctypes.c_float(500.0), ctypes.c_float(3.5), ctypes.c_float(3.5),
+                              ctypes.byref(p), ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000),
+                              None)
+        assert rc == bn.BN_ERR_UNSUPPORTED
 
 
 def test_null_pointers_rejected():

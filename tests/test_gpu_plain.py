@@ -28,7 +28,7 @@ def f1080():
 def test_library_is_native():
     import torch
     assert torch.cuda.is_available()
-    assert bn.lib().bn_version() == 1
+    assert bn.lib().bn_version() == 2
     names = dict(bn.variants())
     assert names[1] == "scalar" and names[2] == "vec4"
 

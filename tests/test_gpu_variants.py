@@ -1,0 +1,187 @@
+"""GPU parity of the pair-removal and multi-scale methods against the
+oracle (masks and counts bit-exact, normals within 1e-5 per component), the
+batched form of each against its plain form (bit for bit), and the
+overwrite flag of the counts."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2209_08241_amd as bn
+from gpu_util import NORMAL_TOL, assert_parity, log, to_gpu
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+PR, MS = "pair_removal", "multiscale"
+
+
+@pytest.fixture(scope="module")
+def f640():
+    return scenes.frame_640x480(seed=1)
+
+
+@pytest.fixture(scope="module")
+def f1080():
+    return scenes.frame_1920x1080(seed=2)
+
+
+def run(depth, fx, fy, cx, cy, alpha, mode, tau, method, scales=0, variant=0, stride_pad=0):
+    import torch
+    d = to_gpu(depth, stride_pad)
+    n, m, st = bn.estimate_normals(d, fx, fy, cx, cy, alpha, mode, tau, variant=variant,
+                                   method=method, scales=scales)
+    torch.cuda.synchronize()
+    return n.cpu().numpy(), m.cpu().numpy(), st.cpu().numpy()
+
+
+def check(depth, fx, fy, cx, cy, alpha, mode, tau, method, scales=0, variant=0, stride_pad=0,
+          what=""):
+    ref = oracle.variant_f32(depth, fx, fy, cx, cy, alpha, mode, tau, method=method,
+                             scales=scales)
+    n, m, st = run(depth, fx, fy, cx, cy, alpha, mode, tau, method, scales, variant, stride_pad)
+    return assert_parity(ref, n, m, st, what=what)
+
+
+@pytest.mark.parametrize("alpha", [1, 2, 3, 8])
+@pytest.mark.parametrize("mode,tau", [("rel", 4.0), ("rel", 1.5), ("abs", 1e-3), ("none", 1.0)])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+def test_pair_removal_640(f640, alpha, mode, tau, variant):
+    log(f"pair removal 640x480 alpha={alpha} {mode} {tau} variant={variant}")
+    s = f640
+    check(s.depth, *s.intrinsics, alpha, mode, tau, PR, 0, variant, what="pair removal")
+
+
+@pytest.mark.parametrize("alpha,K", [(1, 1), (1, 3), (2, 2), (2, 4), (3, 2), (4, 2), (8, 1),
+                                     (1, 8), (8, 8)])
+@pytest.mark.parametrize("mode,tau", [("rel", 4.0), ("abs", 5e-3), ("none", 1.0)])
+def test_multiscale_640(f640, alpha, K, mode, tau):
+    log(f"multiscale 640x480 alpha={alpha} K={K} {mode}")
+    s = f640
+    for variant in (0, 1):
+        check(s.depth, *s.intrinsics, alpha, mode, tau, MS, K, variant,
+              what=f"multiscale a={alpha} K={K} v={variant}")
+
+
+def test_multiscale_rejects_vector_variants(f640):
+    import torch
+    s = f640
+    d = to_gpu(s.depth)
+    for v in (2, 3, 4):
+        with pytest.raises(bn.BnError) as e:
+            bn.estimate_normals(d, *s.intrinsics, 1, method=MS, scales=2, variant=v)
+        assert e.value.status == bn.BN_ERR_UNSUPPORTED
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("method,alpha,K", [(PR, 2, 0), (PR, 1, 0), (MS, 1, 3), (MS, 2, 2)])
+def test_1920x1080_sampled_rows(f1080, method, alpha, K):
+    """Full frame on the GPU, row bands of it against the oracle's row entry."""
+    log(f"1080p {method} alpha={alpha} K={K}")
+    s = f1080
+    n, m, st = run(s.depth, *s.intrinsics, alpha, "rel", 4.0, method, K)
+    H = s.depth.shape[0]
+    full = oracle.variant_f32(s.depth, *s.intrinsics, alpha, "rel", 4.0, method=method, scales=K)
+    assert [int(c) for c in st[:3]] == [int(c) for c in full["counts"]]
+    for (rb, re) in ((0, 24), (H // 2 - 8, H // 2 + 8), (H - 24, H)):
+        ref = oracle.variant_f32(s.depth, *s.intrinsics, alpha, "rel", 4.0, method=method,
+                                 scales=K, rows=(rb, re))
+        assert_parity(ref, n[rb:re], m[rb:re], what=f"rows {rb}..{re}")
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (3, 5), (5, 3), (17, 33), (33, 17), (9, 1025),
+                                 (31, 129), (2, 2048), (64, 4)])
+def test_ragged_and_strided(H, W):
+    rng = np.random.default_rng(H * 7919 + W)
+    d = rng.uniform(0.8, 1.3, size=(H, W)).astype(np.float32)
+    d[rng.random((H, W)) < 0.04] = 0.0
+    fx, fy, cx, cy = 280.0, 300.0, (W - 1) / 2, (H - 1) / 2
+    for pad in (0, 3):
+        for alpha in (1, 2):
+            check(d, fx, fy, cx, cy, alpha, "rel", 1.05, PR, 0, 0, pad,
+                  what=f"pairs {H}x{W} a={alpha} pad={pad}")
+            check(d, fx, fy, cx, cy, alpha, "rel", 1.05, MS, 2, 0, pad,
+                  what=f"ms {H}x{W} a={alpha} pad={pad}")
+
+
+def test_special_values():
+    rng = np.random.default_rng(5)
+    H, W = 40, 64
+    d = rng.uniform(0.5, 3.0, size=(H, W)).astype(np.float32)
+    specials = [0.0, -0.0, -1.0, np.nan, np.inf, -np.inf, 1e-40, 1e30,
+                np.finfo(np.float32).max, 1e-20]
+    for k, v in enumerate(specials):
+        d[rng.integers(H), rng.integers(W)] = v
+        d[rng.integers(H), rng.integers(W)] = v
+    d[5, :] *= 1e6
+    d[9, :] *= 1e-6
+    for method, K in ((PR, 0), (MS, 1), (MS, 3)):
+        for mode, tau in (("rel", 4.0), ("abs", 1e-4), ("none", 1.0)):
+            check(d, 120.0, 125.0, 31.5, 19.5, 1, mode, tau, method, K,
+                  what=f"special {method} K={K} {mode}")
+
+
+def test_step_scene_pairs_keep_own_plane():
+    """Next to a step the pair-removal normal is the exact normal of the
+    pixel's own plane (to binary32 rounding), where the four-pair method
+    removes the pixel."""
+    import pins_variants as pv
+    H, W = 30, 34
+    fx, fy, cx, cy = 250.0, 270.0, 15.5, 13.0
+    d, lab, nrm = pv._step_scene(H, W, fx, fy, cx, cy)
+    f = d.astype(np.float32)
+    n, m, _ = run(f, fx, fy, cx, cy, 1, "rel", 4.0, PR)
+    n4, m4, _ = run(f, fx, fy, cx, cy, 1, "rel", 4.0, "four_pair")
+    v = m == 0
+    assert (v & (m4 == 1)).sum() > 30
+    err = np.abs(n[v].astype(np.float64) - nrm[lab[v]]).max()
+    assert err <= 4 * 2.0 ** -24 * max(fx, fy) + NORMAL_TOL
+
+
+@pytest.mark.parametrize("method,alpha,K", [(PR, 2, 0), (MS, 1, 3), ("four_pair", 2, 0)])
+def test_batch_equals_plain(method, alpha, K):
+    import torch
+    frames_h = [scenes.sized_frame(H, W, 40 + k) for k, (H, W) in
+                enumerate([(240, 320), (480, 640), (120, 160), (97, 131), (480, 640)])]
+    dev = torch.device("cuda")
+    frames = [bn.BatchFrame(torch.from_numpy(s.depth).to(dev), s.fx, s.fy, s.cx, s.cy)
+              for s in frames_h]
+    with bn.BatchPlan(frames, alpha, "rel", 4.0, method=method, scales=K) as plan:
+        plan.run()
+        torch.cuda.synchronize()
+        for s, fr in zip(frames_h, frames):
+            n, m, st = run(s.depth, s.fx, s.fy, s.cx, s.cy, alpha, "rel", 4.0, method, K)
+            assert np.array_equal(fr.mask.cpu().numpy(), m)
+            assert np.array_equal(fr.normals.cpu().numpy(), n)
+            assert fr.stats[:3].cpu().tolist() == st[:3].tolist()
+        ref = oracle.variant_f32(frames_h[1].depth, *frames_h[1].intrinsics, alpha, "rel", 4.0,
+                                 method=method, scales=K)
+        assert_parity(ref, frames[1].normals.cpu().numpy(), frames[1].mask.cpu().numpy(),
+                      frames[1].stats.cpu().numpy(), what="batch frame 1")
+
+
+@pytest.mark.parametrize("method,K", [("four_pair", 0), (PR, 0), (MS, 2)])
+def test_counts_overwrite_flag(f640, method, K):
+    """Added by default, replaced with BN_FLAG_COUNTS_OVERWRITE (plain and
+    batched)."""
+    import torch
+    s = f640
+    d = to_gpu(s.depth)
+    ref = oracle.variant_f32(s.depth, *s.intrinsics, 2, "rel", 4.0, method=method, scales=K)
+    want = [int(c) for c in ref["counts"]]
+    st = bn.new_stats(device="cuda")
+    for _ in range(3):
+        bn.estimate_normals(d, *s.intrinsics, 2, method=method, scales=K, stats=st)
+    torch.cuda.synchronize()
+    assert st[:3].cpu().tolist() == [3 * c for c in want]
+    for _ in range(3):
+        bn.estimate_normals(d, *s.intrinsics, 2, method=method, scales=K, stats=st,
+                            overwrite_counts=True)
+    torch.cuda.synchronize()
+    assert st[:3].cpu().tolist() == want
+    fr = bn.BatchFrame(d, *s.intrinsics)
+    with bn.BatchPlan([fr], 2, "rel", 4.0, method=method, scales=K,
+                      overwrite_counts=True) as plan:
+        for _ in range(3):
+            plan.run()
+        torch.cuda.synchronize()
+        assert fr.stats[:3].cpu().tolist() == want
