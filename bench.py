@@ -81,91 +81,200 @@ def cpu_baseline(frames, alpha, mode, tau, budget_s):
                       f"{el:.1f} s, single thread, FP64 normals + binary32 mask"}
 
 
-def run_plain(args, torch, bn, scenes):
-    H, W = 1080, 1920
-    ring = args.ring
-    ndistinct = min(args.distinct, ring)
-    log(f"generating {ndistinct} distinct 1920x1080 scenes (seeds 2..{1 + ndistinct})")
-    scs = [scenes.frame_1920x1080(seed=2 + i) for i in range(ndistinct)]
-    dev = torch.device("cuda:0")
-    depth = [torch.from_numpy(scs[i % ndistinct].depth).to(dev) for i in range(ring)]
-    normals = [torch.empty((H, W, 3), dtype=torch.float32, device=dev) for _ in range(ring)]
-    masks = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(ring)]
-    stats = bn.new_stats(ring, device=dev)
-    s0 = scs[0]
-    kw = dict(alpha=args.alpha, mode=args.mode, tau=args.tau, variant=args.variant)
-
-    def one(i, stream=None):
-        j = i % ring
-        bn.estimate_normals(depth[j], s0.fx, s0.fy, s0.cx, s0.cy, normals=normals[j],
-                            mask=masks[j], stats=stats[j], stream=stream, **kw)
-
-    # correctness of the benchmarked configuration against the oracle (frame 0)
-    one(0)
-    torch.cuda.synchronize()
+def cpu_threads(frames, alpha, mode, tau, budget_s):
+    """The same oracle on every host core: each frame's rows split into one
+    band per thread (ctypes releases the GIL during the call)."""
+    import concurrent.futures as cf
     import oracle
-    ref = oracle.normals_f32(s0.depth, s0.fx, s0.fy, s0.cx, s0.cy, args.alpha, args.mode, args.tau)
-    import numpy as np
-    ok_mask = bool(np.array_equal(masks[0].cpu().numpy(), ref["mask"]))
-    err = float(np.abs(normals[0].cpu().numpy().astype(np.float64) - ref["normals"]).max())
-    log(f"parity frame 0: mask equal={ok_mask}, max normal error={err:.2e}")
-    if not ok_mask or err > 1e-5:
-        raise SystemExit("benchmark configuration disagrees with the oracle")
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(int(cores or 1), 16))
+    o = oracle.default()
+    t0 = time.perf_counter()
+    px = n = 0
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        while True:
+            s = frames[n % len(frames)]
+            H = s.depth.shape[0]
+            bands = [(H * k // cores, H * (k + 1) // cores) for k in range(cores)]
+            list(ex.map(lambda b: o.normals_f32_rows(s.depth, s.fx, s.fy, s.cx, s.cy, alpha,
+                                                     mode, tau, b[0], b[1]), bands))
+            px += s.depth.size
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+    return {"value": px / el / 1e6, "unit": "Mpix/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} frames, {el:.1f} s, rows split over {cores} threads"}
 
-    stream = torch.cuda.Stream()
-    graph = None
-    if not args.eager:
-        # one pass over the ring, captured once, replayed per pass
-        with torch.cuda.stream(stream):
-            for i in range(ring):
-                one(i, stream)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=stream):
-            for i in range(ring):
-                one(i, torch.cuda.current_stream())
-        torch.cuda.synchronize()
 
-    steps = max(args.steps // ring, 1) * ring if graph is not None else args.steps
-    warm = max(args.warmup // ring, 1) * ring if graph is not None else args.warmup
+class Ring:
+    """A ring of distinct device frame buffers, one plain launch per step."""
 
-    def run(nsteps):
-        if graph is not None:
-            for _ in range(nsteps // ring):
-                graph.replay()
-        else:
+    def __init__(self, torch, bn, scs, ring):
+        dev = torch.device("cuda:0")
+        H, W = scs[0].depth.shape
+        self.torch, self.bn, self.scs, self.ring = torch, bn, scs, ring
+        self.H, self.W = H, W
+        self.depth = [torch.from_numpy(scs[i % len(scs)].depth).to(dev) for i in range(ring)]
+        self.normals = [torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+                        for _ in range(ring)]
+        self.masks = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(ring)]
+        self.stats = bn.new_stats(ring, device=dev)
+
+    def launch(self, i, kw, stream=None):
+        j = i % self.ring
+        s0 = self.scs[0]
+        self.bn.estimate_normals(self.depth[j], s0.fx, s0.fy, s0.cx, s0.cy,
+                                 normals=self.normals[j], mask=self.masks[j],
+                                 stats=self.stats[j], stream=stream, **kw)
+
+    def time(self, kw, steps, warmup, eager=False, hot=False):
+        """ms per launch over `steps` launches (graph replay of one pass over
+        the ring unless eager; hot: the same buffer every launch)."""
+        torch = self.torch
+        ring = 1 if hot else self.ring
+        stream = torch.cuda.Stream()
+        graph = None
+        if not eager:
             with torch.cuda.stream(stream):
-                for i in range(nsteps):
-                    one(i, stream)
+                for i in range(ring):
+                    self.launch(i, kw, stream)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=stream):
+                for i in range(ring):
+                    self.launch(i, kw, torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            steps = max(steps // ring, 1) * ring
+            warmup = max(warmup // ring, 1) * ring
 
-    with torch.cuda.stream(stream):
-        run(warm)
+        def run(n):
+            if graph is not None:
+                for _ in range(n // ring):
+                    graph.replay()
+            else:
+                for i in range(n):
+                    self.launch(i % ring, kw, stream)
+
+        with torch.cuda.stream(stream):
+            run(warmup)
+        torch.cuda.synchronize()
+        self.stats.zero_()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            start.record(stream)
+            run(steps)
+            end.record(stream)
+        end.synchronize()
+        torch.cuda.synchronize()
+        return start.elapsed_time(end) / steps, steps, warmup, graph is not None
+
+    def single_launch_us(self, kw, reps=30):
+        """Latency of one eager launch, synchronised, median of reps."""
+        import numpy as np
+        torch = self.torch
+        stream = torch.cuda.Stream()
+        out = []
+        for r in range(reps + 3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                self.launch(r, kw, stream)
+            stream.synchronize()
+            out.append(time.perf_counter() - t0)
+        return 1e6 * float(np.median(out[3:]))
+
+
+def parity_check(ring, kw, alpha, mode, tau, method="four_pair", scales=0):
+    """The benchmarked configuration against the oracle on frame 0."""
+    import numpy as np
+    import oracle
+    torch = ring.torch
+    ring.launch(0, kw)
     torch.cuda.synchronize()
-    stats.zero_()
+    s0 = ring.scs[0]
+    ref = oracle.variant_f32(s0.depth, s0.fx, s0.fy, s0.cx, s0.cy, alpha, mode, tau,
+                             method=method, scales=scales)
+    ok_mask = bool(np.array_equal(ring.masks[0].cpu().numpy(), ref["mask"]))
+    err = float(np.abs(ring.normals[0].cpu().numpy().astype(np.float64) - ref["normals"]).max())
+    log(f"parity frame 0 ({method}): mask equal={ok_mask}, max normal error={err:.2e}")
+    if not ok_mask or err > 1e-5:
+        raise SystemExit(f"benchmark configuration ({method}) disagrees with the oracle")
+    return ref
+
+
+def roofline(px, ms, traffic=None):
+    achieved = BYTES_PER_PIXEL * px / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+
+
+def device_copy_gbs(torch, mib=2048, reps=5):
+    """Read+write bandwidth of a device-to-device copy of `mib` MiB: the
+    achievable HBM rate on this GPU."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    with torch.cuda.stream(stream):
-        start.record(stream)
-        run(steps)
-        end.record(stream)
+    start.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    end.record()
     end.synchronize()
-    torch.cuda.synchronize()
-    ms_total = start.elapsed_time(end)
-    ms_step = ms_total / steps
+    ms = start.elapsed_time(end) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def run_plain(args, torch, bn, scenes):
+    ring_n = args.ring
+    ndistinct = min(args.distinct, ring_n)
+    log(f"generating {ndistinct} distinct 1920x1080 scenes (seeds 2..{1 + ndistinct})")
+    scs = [scenes.frame_1920x1080(seed=2 + i) for i in range(ndistinct)]
+    ring = Ring(torch, bn, scs, ring_n)
+    H, W = ring.H, ring.W
     px = H * W
-    st = stats.cpu().numpy()
-    passes = steps // ring
+    kw = dict(alpha=args.alpha, mode=args.mode, tau=args.tau, variant=args.variant)
+    ref = parity_check(ring, kw, args.alpha, args.mode, args.tau)
+    ms_step, steps, warm, graphed = ring.time(kw, args.steps, args.warmup, eager=args.eager)
+    st = ring.stats.cpu().numpy()
+    passes = steps // ring_n
     want = [passes * int(c) for c in ref["counts"]]
-    if st[0, :3].tolist() != want:
+    if graphed and st[0, :3].tolist() != want:
         raise SystemExit(f"per-frame counts wrong after timing: {st[0, :3].tolist()} != {want}")
-    achieved = BYTES_PER_PIXEL * px / (ms_step * 1e-3) / 1e9
     traffic = load_traffic("plain1080", px)
+    extra = {}
+    if not args.quick:
+        hot_ms, _, _, _ = ring.time(kw, args.steps // 4, args.warmup // 4, hot=True)
+        extra["hot_cache"] = {"value": px / (hot_ms * 1e-3) / 1e6, "unit": "Mpix/s",
+                              "note": "one frame buffer relaunched: the 256 MB last-level "
+                                      "cache holds it, not an HBM figure"}
+        extra["single_launch_us"] = ring.single_launch_us(kw)
+        methods = []
+        for name, alpha, K in (("pair_removal", args.alpha, 0), ("multiscale", 1, 3)):
+            mkw = dict(alpha=alpha, mode=args.mode, tau=args.tau, method=name, scales=K)
+            parity_check(ring, mkw, alpha, args.mode, args.tau, name, K)
+            mms, msteps, _, _ = ring.time(mkw, args.steps // 2, args.warmup // 2)
+            methods.append({"method": name, "alpha": alpha, "scales": K, "steps": msteps,
+                            "ms_per_step": mms, "value": px / (mms * 1e-3) / 1e6,
+                            "unit": "Mpix/s", "roofline": roofline(px, mms)})
+            log(f"{name}: {methods[-1]['value']:.0f} Mpix/s")
+        extra["methods"] = methods
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"timing the oracle for {args.cpu_seconds} s")
+        log(f"timing the oracle for {args.cpu_seconds} s (one thread)")
         cpu = cpu_baseline(scs, args.alpha, args.mode, args.tau, args.cpu_seconds)
-    return {
+        if not args.quick:
+            log(f"timing the oracle for {args.cpu_seconds} s (all host cores)")
+            extra["cpu_oracle_all_cores"] = cpu_threads(scs, args.alpha, args.mode, args.tau,
+                                                        args.cpu_seconds)
+    out = {
         "metric": "normals Mpix/s (plain single-frame launches)",
         "value": px / (ms_step * 1e-3) / 1e6,
         "unit": "Mpix/s",
@@ -173,15 +282,16 @@ def run_plain(args, torch, bn, scenes):
         "warmup": warm,
         "ms_per_step": ms_step,
         "config": {"workload": "plain 1920x1080, one launch per frame, ring of "
-                               f"{ring} frame buffers ({ndistinct} distinct scenes)",
+                               f"{ring_n} frame buffers ({ndistinct} distinct scenes)",
                    "frame": "1920x1080", "fx": 1050.0, "alpha": args.alpha,
-                   "mask": args.mode, "tau": args.tau,
-                   "launch": "hip graph replay" if graph is not None else "eager",
+                   "mask": args.mode, "tau": args.tau, "method": "four_pair",
+                   "launch": "hip graph replay" if graphed else "eager",
                    "variant": args.variant or "auto"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "roofline": roofline(px, ms_step, traffic),
         "cpu_baseline": cpu,
     }
+    out.update(extra)
+    return out
 
 
 def run_batch(args, torch, bn, scenes):
@@ -231,17 +341,64 @@ def run_batch(args, torch, bn, scenes):
     got0 = frames[0].stats[:3].cpu().tolist()
     if got0 != [steps * int(c) for c in ref0["counts"]]:
         raise SystemExit("batched counts wrong after timing")
-    achieved = BYTES_PER_PIXEL * px / (ms * 1e-3) / 1e9
     plan.close()
+    plain = None
+    if not args.quick:
+        plain = plain_launches(args, torch, bn, frames, stream, px)
     return {
         "workload": "256 frames: 64x 320x240, 96x 640x480, 64x 1280x720, 32x 1920x1080 "
                     "(seeds 1000..1255, fx=fy=525*W/640), one graph launch over all tiles",
         "pixels": px, "tiles": info["tiles"], "workgroups": info["workgroups"],
         "value": px / (ms * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_step": ms, "steps": steps,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": load_traffic("batch256", px)},
+        "roofline": roofline(px, ms, load_traffic("batch256", px)),
+        "same_frames_plain_launches": plain,
     }
+
+
+def plain_launches(args, torch, bn, frames, stream, px):
+    """The same 256 frames as 256 bn_estimate_normals launches on one stream:
+    eager (one host call per frame) and replayed from a HIP graph."""
+    kw = dict(alpha=args.alpha, mode=args.mode, tau=args.tau)
+
+    def one_pass(st):
+        for fr in frames:
+            bn.estimate_normals(fr.depth, fr.fx, fr.fy, fr.cx, fr.cy, normals=fr.normals,
+                                mask=fr.mask, stats=fr.stats, stream=st, **kw)
+
+    res = {}
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    reps = max(args.batch_steps // 10, 3)
+    with torch.cuda.stream(stream):
+        one_pass(stream)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(reps):
+            one_pass(stream)
+        end.record(stream)
+    end.synchronize()
+    ms = start.elapsed_time(end) / reps
+    res["eager"] = {"value": px / (ms * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_pass": ms,
+                    "roofline_frac": roofline(px, ms)["frac"]}
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        one_pass(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        graph.replay()
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(reps):
+            graph.replay()
+        end.record(stream)
+    end.synchronize()
+    ms = start.elapsed_time(end) / reps
+    res["graph"] = {"value": px / (ms * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_pass": ms,
+                    "roofline_frac": roofline(px, ms)["frac"]}
+    log(f"same frames as plain launches: eager {res['eager']['value']:.0f}, "
+        f"graph {res['graph']['value']:.0f} Mpix/s")
+    del graph
+    return res
 
 
 def run_serve(args, torch, bn, scenes, capacity_mpix_s):
@@ -306,6 +463,8 @@ def main():
     ap.add_argument("--serve-budget-gib", type=int, default=16)
     ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--serve-in-flight", type=int, default=3)
+    ap.add_argument("--quick", action="store_true",
+                    help="headline numbers only (no methods, latency, copy or multi-core oracle)")
     ap.add_argument("--calibration-mib", type=int, default=0,
                     help="first run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -349,7 +508,7 @@ def main():
             b = run_batch(args, torch, bn, scenes)
             out["batched"] = {k: b[k] for k in ("workload", "value", "unit", "ms_per_step",
                                                 "steps", "pixels", "tiles", "workgroups",
-                                                "roofline")}
+                                                "roofline", "same_frames_plain_launches")}
             if not args.no_serve:
                 out["serving"] = run_serve(args, torch, bn, scenes, b["value"])
     line = {
@@ -369,7 +528,13 @@ def main():
         "roofline": out["roofline"],
         "cpu_baseline": out["cpu_baseline"],
     }
-    for k in ("batched", "serving"):
+    if not args.quick and args.workload == "plain1080":
+        gbs = device_copy_gbs(torch)
+        line["achievable"] = {"device_copy_GBs": gbs, "what": "torch copy_ of 2 GiB, read + "
+                              "write bytes / time",
+                              "frac_of_copy": out["roofline"]["achieved"] / gbs}
+    for k in ("batched", "serving", "methods", "hot_cache", "single_launch_us",
+              "cpu_oracle_all_cores"):
         if k in out:
             line[k] = out[k]
     print(json.dumps(line), flush=True)
