@@ -380,6 +380,41 @@ int bn_server_run_poisson(bn_server *server, const bn_frame *pool, int32_t n_poo
                           double rate_hz, int32_t n_requests, uint64_t seed, double *latency_s,
                           double *wall_s, int64_t *pixels);
 
+/*
+ * Evaluation tools (Section 4).  All pointers are device pointers; nothing
+ * is allocated; asynchronous on `stream`.
+ *
+ * bn_normal_angles: the spherical angle images of a normal map [H][W][3]
+ *   binary32 (Eqs. 14-15, with the quadrant-aware arctangent):
+ *     phi   = atan2(ny, nx), taken into [0, 2 pi)
+ *     theta = atan2(sqrt(nx^2 + ny^2), nz), in [0, pi]
+ *   evaluated in FP64 and stored as binary32 [H][W]; a zero vector gives 0, 0.
+ * bn_angle_mse: mean squared error of the theta and of the phi images of
+ *   two normal maps over the pixels whose code is BN_VALID in both (a NULL
+ *   mask counts as all valid); result (device, 3 doubles): MSE theta, MSE
+ *   phi, pixel count.  workspace: BN_MSE_WORKSPACE_DOUBLES doubles of device
+ *   memory, owned by the caller, not shared by overlapping calls.  The sums
+ *   run in FP64 in a fixed order (deterministic).
+ * bn_plane_fit_normals: local plane fit over the (2 radius + 1)^2 window of
+ *   each pixel (radius 2: the 25-neighbour fit used as ground truth on real
+ *   depth, Section 4): the camera-facing eigenvector of the smallest
+ *   eigenvalue of the scatter matrix of the back-projected window points
+ *   (Eqs. 8-9), in FP64, stored as binary32 normals [H][W][3] and codes
+ *   [H][W] (BN_VALID; BN_INVALID when the window leaves the image, holds a
+ *   depth that is not finite and > 0, or has no unique smallest direction).
+ *   radius 1..BN_MAX_FIT_RADIUS.  Frame arguments as bn_estimate_normals.
+ */
+#define BN_MSE_WORKSPACE_DOUBLES (3 * 2048)
+#define BN_MAX_FIT_RADIUS 3
+int bn_normal_angles(const float *normals, int32_t height, int32_t width, float *theta,
+                     float *phi, void *stream);
+int bn_angle_mse(const float *normals_a, const uint8_t *mask_a, const float *normals_b,
+                 const uint8_t *mask_b, int32_t height, int32_t width, double *workspace,
+                 double *result, void *stream);
+int bn_plane_fit_normals(const float *depth, int32_t height, int32_t width, int64_t depth_stride,
+                         float fx, float fy, float cx, float cy, int32_t radius, float *normals,
+                         uint8_t *mask, void *stream);
+
 /* Number of kernel variants of the plain entry point, and a name for each
  * id 1..count (NULL for an unknown id). */
 int bn_variant_count(void);

@@ -97,8 +97,22 @@ def lib() -> ctypes.CDLL:
         L.bn_version.argtypes = []
         L.bn_version.restype = ctypes.c_int
         _bind_batch(L)
+        _bind_eval(L)
         _lib = L
     return _lib
+
+
+MSE_WORKSPACE_DOUBLES = 3 * 2048   # BN_MSE_WORKSPACE_DOUBLES
+
+
+def _bind_eval(L) -> None:
+    vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    L.bn_normal_angles.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.bn_normal_angles.restype = ctypes.c_int
+    L.bn_angle_mse.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
+    L.bn_angle_mse.restype = ctypes.c_int
+    L.bn_plane_fit_normals.argtypes = [vp, i32, i32, i64, f32, f32, f32, f32, i32, vp, vp, vp]
+    L.bn_plane_fit_normals.restype = ctypes.c_int
 
 
 def _bind_batch(L) -> None:
@@ -623,3 +637,79 @@ def device_to_host(ptr: int, nbytes: int):
         if rc != 0:
             raise RuntimeError(f"hipMemcpy failed: {rc}")
     return out
+
+
+# ---------------------------------------------------------------------------
+# evaluation tools (Section 4)
+# ---------------------------------------------------------------------------
+
+def _check_normals(n, what="normals"):
+    import torch
+    if not (isinstance(n, torch.Tensor) and n.is_cuda and n.dtype == torch.float32
+            and n.dim() == 3 and n.shape[2] == 3 and n.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous CUDA float32 [H, W, 3] tensor")
+
+
+def normal_angles(normals, stream=None):
+    """(theta, phi) images [H, W] float32 of a normal map (Eqs. 14-15):
+    phi = atan2(ny, nx) in [0, 2 pi), theta = atan2(|(nx, ny)|, nz)."""
+    import torch
+    _check_normals(normals)
+    H, W = normals.shape[:2]
+    theta = torch.empty((H, W), dtype=torch.float32, device=normals.device)
+    phi = torch.empty_like(theta)
+    rc = lib().bn_normal_angles(ctypes.c_void_p(normals.data_ptr()), H, W,
+                                ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(phi.data_ptr()),
+                                ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_normal_angles")
+    return theta, phi
+
+
+def angle_mse(normals_a, mask_a, normals_b, mask_b=None, stream=None, sync: bool = True):
+    """(MSE theta, MSE phi, pixel count) over the pixels VALID in both maps
+    (a None mask counts as all valid).  Returns a device tensor of 3 doubles
+    when sync is False."""
+    import torch
+    _check_normals(normals_a, "normals_a")
+    _check_normals(normals_b, "normals_b")
+    H, W = normals_a.shape[:2]
+    if normals_b.shape[:2] != (H, W):
+        raise ValueError("the two normal maps differ in size")
+    for m in (mask_a, mask_b):
+        if m is not None and not (m.is_cuda and m.dtype == torch.uint8 and m.shape == (H, W)
+                                  and m.is_contiguous()):
+            raise ValueError("masks must be contiguous CUDA uint8 [H, W] tensors")
+    dev = normals_a.device
+    ws = torch.empty(MSE_WORKSPACE_DOUBLES, dtype=torch.float64, device=dev)
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    rc = lib().bn_angle_mse(ctypes.c_void_p(normals_a.data_ptr()),
+                            ctypes.c_void_p(mask_a.data_ptr() if mask_a is not None else 0),
+                            ctypes.c_void_p(normals_b.data_ptr()),
+                            ctypes.c_void_p(mask_b.data_ptr() if mask_b is not None else 0),
+                            H, W, ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                            ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_angle_mse")
+    if not sync:
+        return out
+    t, p, k = out.cpu().tolist()
+    return t, p, int(k)
+
+
+def plane_fit_normals(depth, fx, fy, cx, cy, radius: int = 2, stream=None):
+    """Plane-fit normals [H, W, 3] float32 and codes [H, W] uint8 over the
+    (2 radius + 1)^2 window (radius 2: the 25-neighbour fit)."""
+    import torch
+    _check_depth(depth)
+    H, W = depth.shape
+    normals = torch.empty((H, W, 3), dtype=torch.float32, device=depth.device)
+    mask = torch.empty((H, W), dtype=torch.uint8, device=depth.device)
+    stride = depth.stride(0) if H > 0 else W
+    rc = lib().bn_plane_fit_normals(ctypes.c_void_p(depth.data_ptr()), H, W, stride, fx, fy, cx,
+                                    cy, int(radius), ctypes.c_void_p(normals.data_ptr()),
+                                    ctypes.c_void_p(mask.data_ptr()),
+                                    ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_plane_fit_normals")
+    return normals, mask

@@ -135,3 +135,15 @@ def test_batch_plan_argument_errors():
     assert L.bn_batch_plan_create(fr, 1, ctypes.byref(forced), ctypes.byref(h)) == bn.BN_ERR_UNSUPPORTED
     assert L.bn_batch_run(None, None) == bn.BN_ERR_INVALID_ARG
     L.bn_batch_plan_destroy(None)
+
+
+def test_eval_argument_errors():
+    L = bn.lib()
+    assert L.bn_plane_fit_normals(ctypes.c_void_p(0x10000), 8, 8, 8, 500.0, 500.0, 3.5, 3.5, 4,
+                                  ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000),
+                                  None) == bn.BN_ERR_UNSUPPORTED
+    assert L.bn_plane_fit_normals(ctypes.c_void_p(0x10000), 8, 8, 8, 500.0, 500.0, 3.5, 3.5, 0,
+                                  ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000),
+                                  None) == bn.BN_ERR_INVALID_ARG
+    assert L.bn_angle_mse(None, None, None, None, 4, 4, None, None, None) == bn.BN_ERR_INVALID_ARG
+    assert L.bn_normal_angles(None, 4, 4, None, None, None) == bn.BN_ERR_INVALID_ARG
