@@ -270,8 +270,9 @@ def make_scene(H: int, W: int, *, fx: float, fy: Optional[float] = None,
                cx: Optional[float] = None, cy: Optional[float] = None,
                n_planes: int = 2, n_spheres: int = 3, n_boxes: int = 1,
                seed: int = 1, noise: bool = True, hole_p: float = HOLE_P,
-               prims: Optional[Sequence[dict]] = None) -> Scene:
-    """One seeded frame: primitives in front of the wall, noise and holes."""
+               prims: Optional[Sequence[dict]] = None, noise_k: float = NOISE_K) -> Scene:
+    """One seeded frame: primitives in front of the wall, noise of standard
+    deviation noise_k * z^2 and holes."""
     fy = fx if fy is None else fy
     cx = (W - 1) / 2.0 if cx is None else cx
     cy = (H - 1) / 2.0 if cy is None else cy
@@ -284,7 +285,7 @@ def make_scene(H: int, W: int, *, fx: float, fy: Optional[float] = None,
     clean, labels, normals = render(H, W, fx, fy, cx, cy, prims)
     if noise:
         z = rng.standard_normal((H, W))
-        noisy = clean + z * (NOISE_K * clean * clean)
+        noisy = clean + z * (noise_k * clean * clean)
     else:
         noisy = clean.copy()
     depth = noisy.astype(np.float32)
