@@ -95,12 +95,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_counts(const BatchFrame *__res
     bn_frame_stats *st = frames[fi].a.stats;
     const uint32_t nt = frames[fi].ntiles;
     if (!st || nt == 0) return;  // uniform over the workgroup
-    const uint32_t *wc = wave_counts + 4 * (int64_t)frames[fi].tile_begin;
+    // the 4 wavefront counts of a tile are one 16-byte load; unrolled so that
+    // several loads are in flight per thread
+    const uint4 *wc = reinterpret_cast<const uint4 *>(wave_counts) + frames[fi].tile_begin;
     uint32_t v = 0, b = 0;
-    for (uint32_t k = threadIdx.x; k < 4 * nt; k += kBlock) {
-        const uint32_t c = wc[k];
-        v += c & 0xffffu;
-        b += c >> 16;
+#pragma unroll 8
+    for (uint32_t k = threadIdx.x; k < nt; k += kBlock) {
+        const uint4 c = wc[k];
+        v += (c.x & 0xffffu) + (c.y & 0xffffu) + (c.z & 0xffffu) + (c.w & 0xffffu);
+        b += (c.x >> 16) + (c.y >> 16) + (c.z >> 16) + (c.w >> 16);
     }
     // wavefront sums through DPP-free shuffles, then across the 4 wavefronts
     for (int off = 32; off > 0; off >>= 1) {
