@@ -436,12 +436,24 @@ __device__ __forceinline__ void block_counts(bn_frame_stats *st, uint32_t part, 
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b%8).
-// Give each XCD a contiguous run of tiles so that the rows a tile shares with
-// its neighbours (the stencil halo) are fetched into that XCD's L2 once.
+// Within each window of 8 * kXcdRun consecutive workgroups, give each XCD a
+// contiguous run of kXcdRun tiles, so that the rows a tile shares with its
+// neighbours (the stencil halo) are fetched into that XCD's L2 once, while
+// the 8 XCDs still stream through nearby addresses.  (One contiguous run per
+// XCD over the whole frame keeps the L2 benefit but sends the XCDs to 8
+// distant regions of HBM at once; measured 10-20% slower on frames of
+// 12-168 Mpixel.)  The last, partial window is split the same way into 8
+// runs of its size / 8, and its remainder keeps its own numbers.
+constexpr uint32_t kXcdRun = 64;
+
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
-    const uint32_t per = nblocks >> 3;
-    if (b >= (per << 3)) return b;
-    return (b & 7u) * per + (b >> 3);
+    constexpr uint32_t kWin = 8 * kXcdRun;
+    const uint32_t base = b / kWin * kWin;
+    const uint32_t lb = b - base;
+    if (base + kWin <= nblocks) return base + (lb & 7u) * kXcdRun + (lb >> 3);
+    const uint32_t per = (nblocks - base) >> 3;
+    if (lb >= (per << 3)) return b;
+    return base + (lb & 7u) * per + (lb >> 3);
 }
 
 }  // namespace bn
