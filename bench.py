@@ -211,25 +211,39 @@ def roofline(px, ms, traffic=None):
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
 
 
-def device_copy_gbs(torch, mib=2048, reps=5):
-    """Read+write bandwidth of a device-to-device copy of `mib` MiB: the
-    achievable HBM rate on this GPU."""
-    n = mib * (1 << 20) // 4
+def achievable_rates(torch, bn, reps=5):
+    """HBM rates of plain streaming kernels on this GPU: torch's device copy,
+    the library's 16-byte non-temporal copy (2 GiB moved each), and the
+    estimator's traffic shape without its arithmetic (168 Mpixel)."""
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            fn()
+        end.record()
+        end.synchronize()
+        return start.elapsed_time(end) / reps
+    n = (1 << 30) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    end.record()
-    end.synchronize()
-    ms = start.elapsed_time(end) / reps
+    out = {"torch_copy_GBs": 2 * n * 4 / (timed(lambda: dst.copy_(src)) * 1e-3) / 1e9,
+           "stream_copy_GBs": 2 * n * 4 / (timed(lambda: bn.stream_copy(dst, src)) * 1e-3) / 1e9}
     del src, dst
+    px = 160 << 20
+    depth = torch.ones(px, dtype=torch.float32, device="cuda")
+    normals = torch.empty(3 * px, dtype=torch.float32, device="cuda")
+    mask = torch.empty(px, dtype=torch.uint8, device="cuda")
+    ms = timed(lambda: bn.stream_pattern(depth, normals, mask))
+    out["pattern_GBs"] = BYTES_PER_PIXEL * px / (ms * 1e-3) / 1e9
+    out["what"] = ("GB/s of read + write bytes: torch copy_ and bn_stream_copy of 1 GiB; "
+                   "bn_stream_pattern = 4 B in + 13 B out per pixel through the kernels' LDS "
+                   "staging, no arithmetic, 168 Mpixel")
+    del depth, normals, mask
     torch.cuda.empty_cache()
-    return 2 * n * 4 / (ms * 1e-3) / 1e9
+    return out
 
 
 def run_plain(args, torch, bn, scenes):
@@ -529,10 +543,12 @@ def main():
         "cpu_baseline": out["cpu_baseline"],
     }
     if not args.quick and args.workload == "plain1080":
-        gbs = device_copy_gbs(torch)
-        line["achievable"] = {"device_copy_GBs": gbs, "what": "torch copy_ of 2 GiB, read + "
-                              "write bytes / time",
-                              "frac_of_copy": out["roofline"]["achieved"] / gbs}
+        ach = achievable_rates(torch, bn)
+        ach["plain_frac_of_pattern"] = out["roofline"]["achieved"] / ach["pattern_GBs"]
+        if "batched" in out:
+            ach["batched_frac_of_pattern"] = (out["batched"]["roofline"]["achieved"]
+                                              / ach["pattern_GBs"])
+        line["achievable"] = ach
     for k in ("batched", "serving", "methods", "hot_cache", "single_launch_us",
               "cpu_oracle_all_cores"):
         if k in out:

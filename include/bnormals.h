@@ -415,6 +415,21 @@ int bn_plane_fit_normals(const float *depth, int32_t height, int32_t width, int6
                          float fx, float fy, float cx, float cy, int32_t radius, float *normals,
                          uint8_t *mask, void *stream);
 
+/*
+ * Bandwidth probes: what this GPU's HBM delivers to plain streaming kernels,
+ * the achievable reference beside the published peak.  Device pointers,
+ * asynchronous on `stream`, nothing allocated.
+ * bn_stream_copy: bytes (a multiple of 16, 16-byte aligned buffers) from src
+ *   to dst with 16-byte non-temporal loads and stores.
+ * bn_stream_pattern: the estimator's traffic without its arithmetic: reads
+ *   4 B of depth and writes 12 B of normals and 1 B of code per pixel
+ *   through the same LDS staging; pixels a multiple of 1024, depth and
+ *   normals 16-byte and mask 4-byte aligned.  Output values are meaningless.
+ */
+int bn_stream_copy(void *dst, const void *src, uint64_t bytes, void *stream);
+int bn_stream_pattern(const float *depth, float *normals, uint8_t *mask, uint64_t pixels,
+                      void *stream);
+
 /* Number of kernel variants of the plain entry point, and a name for each
  * id 1..count (NULL for an unknown id). */
 int bn_variant_count(void);

@@ -113,6 +113,11 @@ def _bind_eval(L) -> None:
     L.bn_angle_mse.restype = ctypes.c_int
     L.bn_plane_fit_normals.argtypes = [vp, i32, i32, i64, f32, f32, f32, f32, i32, vp, vp, vp]
     L.bn_plane_fit_normals.restype = ctypes.c_int
+    u64 = ctypes.c_uint64
+    L.bn_stream_copy.argtypes = [vp, vp, u64, vp]
+    L.bn_stream_copy.restype = ctypes.c_int
+    L.bn_stream_pattern.argtypes = [vp, vp, vp, u64, vp]
+    L.bn_stream_pattern.restype = ctypes.c_int
 
 
 def _bind_batch(L) -> None:
@@ -713,3 +718,30 @@ def plane_fit_normals(depth, fx, fy, cx, cy, radius: int = 2, stream=None):
     if rc != BN_OK:
         raise BnError(rc, "bn_plane_fit_normals")
     return normals, mask
+
+
+# ---------------------------------------------------------------------------
+# bandwidth probes
+# ---------------------------------------------------------------------------
+
+def stream_copy(dst, src, stream=None) -> None:
+    """Copy src into dst (same byte size, a multiple of 16) with 16-byte
+    non-temporal loads and stores."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("dst and src differ in size")
+    rc = lib().bn_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n,
+                              ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_stream_copy")
+
+
+def stream_pattern(depth, normals, mask, stream=None) -> None:
+    """The estimator's traffic shape without its arithmetic (see the header)."""
+    n = depth.numel()
+    rc = lib().bn_stream_pattern(ctypes.c_void_p(depth.data_ptr()),
+                                 ctypes.c_void_p(normals.data_ptr()),
+                                 ctypes.c_void_p(mask.data_ptr()), n,
+                                 ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_stream_pattern")

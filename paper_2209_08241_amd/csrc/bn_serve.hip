@@ -426,6 +426,14 @@ class Server {
     }
 
     // Scheduling passes until nothing changes at the current time.
+    // Runs fn(backend) under the scheduler's lock (the fake backend's clock
+    // and failure set are read by every scheduling pass).
+    template <class F>
+    void locked(F fn) {
+        std::lock_guard<std::mutex> g(mu_);
+        fn(*be_);
+    }
+
     int progress() {
         std::lock_guard<std::mutex> g(mu_);
         int total = 0;
@@ -693,13 +701,15 @@ int bn_server_get_stats(bn_server *srv, bn_server_stats *stats) {
 
 int bn_server_fake_advance(bn_server *srv, double seconds) {
     if (!srv || !srv->fake || !(seconds >= 0)) return BN_ERR_INVALID_ARG;
-    srv->fake->advance(seconds);
+    FakeBackend *fb = srv->fake;
+    srv->s->locked([fb, seconds](Backend &) { fb->advance(seconds); });
     return BN_OK;
 }
 
 int bn_server_fake_fail(bn_server *srv, uint64_t request_id) {
     if (!srv || !srv->fake) return BN_ERR_INVALID_ARG;
-    srv->fake->fail(request_id);
+    FakeBackend *fb = srv->fake;
+    srv->s->locked([fb, request_id](Backend &) { fb->fail(request_id); });
     return BN_OK;
 }
 

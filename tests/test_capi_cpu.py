@@ -147,3 +147,12 @@ def test_eval_argument_errors():
                                   None) == bn.BN_ERR_INVALID_ARG
     assert L.bn_angle_mse(None, None, None, None, 4, 4, None, None, None) == bn.BN_ERR_INVALID_ARG
     assert L.bn_normal_angles(None, 4, 4, None, None, None) == bn.BN_ERR_INVALID_ARG
+
+
+def test_probe_argument_errors():
+    L = bn.lib()
+    assert L.bn_stream_copy(0x20000, 0x10000, 24, None) == bn.BN_ERR_INVALID_ARG
+    assert L.bn_stream_copy(0x20008, 0x10000, 32, None) == bn.BN_ERR_INVALID_ARG
+    assert L.bn_stream_copy(0x20000, 0x10000, 0, None) == bn.BN_OK
+    assert L.bn_stream_pattern(0x10000, 0x20000, 0x30000, 1000, None) == bn.BN_ERR_INVALID_ARG
+    assert L.bn_stream_pattern(0x10004, 0x20000, 0x30000, 1024, None) == bn.BN_ERR_INVALID_ARG
