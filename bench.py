@@ -433,7 +433,7 @@ def run_serve(args, torch, bn, scenes, capacity_mpix_s):
     with bn.Server(args.serve_budget_gib << 30, max_batch=args.serve_max_batch,
                    max_batches_in_flight=args.serve_in_flight, alpha=args.alpha, mode=args.mode,
                    tau=args.tau) as srv:
-        srv.run_poisson(pool, cap_hz * 0.3, 200, seed=2999)       # warm-up
+        srv.run_poisson(pool, cap_hz * 0.3, 2000, seed=2999)      # warm-up
         for load in (0.5, 0.9):
             rate = cap_hz * load
             r = srv.run_poisson(pool, rate, args.serve_requests, seed=3000)
@@ -473,10 +473,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-budget-gib", type=int, default=16)
     ap.add_argument("--serve-max-batch", type=int, default=64)
-    ap.add_argument("--serve-in-flight", type=int, default=3)
+    ap.add_argument("--serve-in-flight", type=int, default=2)
     ap.add_argument("--quick", action="store_true",
                     help="headline numbers only (no methods, latency, copy or multi-core oracle)")
     ap.add_argument("--calibration-mib", type=int, default=0,

@@ -103,3 +103,25 @@ def test_poisson_load_completes(serve_frames):
         log(f"poisson 20k req/s: p50 {1e6 * np.median(lat):.0f} us, p99 "
             f"{1e6 * np.quantile(lat, 0.99):.0f} us, {r['pixels'] / r['wall_s'] / 1e6:.0f} Mpix/s")
         assert srv.stats()["completed"] == 400
+
+
+@pytest.mark.parametrize("method,alpha,K", [("pair_removal", 2, 0), ("multiscale", 1, 3)])
+def test_methods_served_equal_alone(serve_frames, method, alpha, K):
+    import torch
+    frames = serve_frames[:4]
+    dev = [torch.from_numpy(s.depth).cuda() for s in frames]
+    refs = []
+    for s, d in zip(frames, dev):
+        n, m, st = bn.estimate_normals(d, s.fx, s.fy, s.cx, s.cy, alpha, "rel", 4.0,
+                                       method=method, scales=K)
+        torch.cuda.synchronize()
+        refs.append((n.cpu().numpy(), m.cpu().numpy(), st.cpu().numpy()[:3]))
+    with bn.Server(4 << 30, max_batch=8, max_batches_in_flight=2, alpha=alpha, method=method,
+                   scales=K) as srv:
+        reqs = [(srv.submit(dev[k % 4], frames[k % 4].fx, frames[k % 4].fy, frames[k % 4].cx,
+                            frames[k % 4].cy), k % 4) for k in range(12)]
+        for rid, k in reqs:
+            info = srv.wait(rid, timeout=30.0)
+            H, W = frames[k].depth.shape
+            check_same(served(info, H, W), refs[k], f"{method} request {rid}")
+            srv.release(rid)
