@@ -309,7 +309,7 @@ def run_plain(args, torch, bn, scenes):
 
 
 def run_batch(args, torch, bn, scenes):
-    """The 256-frame mixed batch, one persistent graph launch per step."""
+    """The 256-frame mixed batch, one graph launch over all tiles per step."""
     workers = min(16, os.cpu_count() or 1)
     log(f"generating the 256-frame mixed batch ({workers} workers)")
     t0 = time.perf_counter()
@@ -505,7 +505,7 @@ def main():
         del src, dst
     if args.workload == "batch":
         b = run_batch(args, torch, bn, scenes)
-        out = {"metric": "normals Mpix/s (batched persistent launch)", "value": b["value"],
+        out = {"metric": "normals Mpix/s (batched launch)", "value": b["value"],
                "unit": "Mpix/s", "steps": b["steps"], "warmup": args.batch_warmup,
                "ms_per_step": b["ms_per_step"],
                "config": {"workload": b["workload"], "alpha": args.alpha, "mask": args.mode,

@@ -220,11 +220,12 @@ int bn_normals_vjp(const float *depth, int32_t height, int32_t width, int64_t de
                    const float *grad_normals, float *grad_depth, void *stream);
 
 /*
- * Batches: many frames of any mix of sizes, one persistent launch.
+ * Batches: many frames of any mix of sizes, one launch.
  *
- * A plan holds the frame descriptors in device memory and a HIP graph with a
- * single kernel node that processes every tile of every frame; running the
- * plan replays the graph.  Frames are described by bn_frame (device
+ * A plan holds the frame descriptors in device memory and a HIP graph of two
+ * kernel nodes: one processes every tile of every frame (one workgroup per
+ * tile of 1024 pixels by default), the other sums each frame's counts;
+ * running the plan replays the graph.  Frames are described by bn_frame (device
  * pointers, owned by the caller, which must stay valid while the plan runs).
  * All frames share `params` (alpha, mode, tau, method, scales, flags;
  * params->variant must be 0);
@@ -235,13 +236,17 @@ int bn_normals_vjp(const float *depth, int32_t height, int32_t width, int64_t de
  *
  * bn_batch_plan_create: validates every frame (the checks of
  *   bn_estimate_normals), allocates the plan (device descriptor table of
- *   n_frames entries, two pinned staging copies) and instantiates the graph.
+ *   n_frames entries, a tile-to-frame table, a table of 4 counts per tile,
+ *   two pinned staging copies) and instantiates the graph.
  *   Capacity = n_frames.  Returns BN_OK, BN_ERR_INVALID_ARG,
  *   BN_ERR_UNSUPPORTED, BN_ERR_OOM or BN_ERR_DEVICE; *out_plan is NULL on
  *   error.  Synchronous.
  * bn_batch_plan_update: replaces the frame list (n_frames <= capacity) with
  *   an asynchronous copy on `stream`, ordered after earlier work and before
- *   later runs on that stream; the graph is reused unchanged.
+ *   later runs on that stream.  The instantiated graph is kept; its kernel
+ *   nodes' launch parameters (grid, table sizes) are updated in place.  A
+ *   list with more tiles than the plan's tables hold grows them, which first
+ *   synchronises `stream` (the plan's earlier runs must have finished).
  * bn_batch_run: one launch over the current frame list on `stream`.
  * bn_batch_plan_info: pixels, tiles and workgroups of the current list.
  * bn_batch_plan_destroy: frees the plan; the caller makes sure no run of it

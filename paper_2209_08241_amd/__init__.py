@@ -277,7 +277,7 @@ class BatchFrame:
 
 
 class BatchPlan:
-    """A bn_batch_plan: every frame of the list in one persistent launch."""
+    """A bn_batch_plan: every frame of the list in one graph launch."""
 
     def __init__(self, frames, alpha: int = 2, mode="rel", tau: float = 4.0, *,
                  method="four_pair", scales: int = 0, overwrite_counts: bool = False):
@@ -311,8 +311,9 @@ class BatchPlan:
         self._frames = frames
 
     def autotune(self, stream=None):
-        """Time 1/2/4/8 workgroups per CU, keep the fastest (runs the plan:
-        counts accumulate).  Returns (workgroups per CU, microseconds)."""
+        """Time the flat grid (one workgroup per tile) and 2/4/8 persistent
+        workgroups per CU, keep the fastest (runs the plan: counts
+        accumulate).  Returns (workgroups per CU or 0 for flat, microseconds)."""
         best, us = ctypes.c_int32(), ctypes.c_float()
         rc = lib().bn_batch_plan_autotune(self._h, ctypes.c_void_p(_stream_handle(stream)),
                                           ctypes.byref(best), ctypes.byref(us))

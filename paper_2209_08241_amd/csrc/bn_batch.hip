@@ -1,5 +1,5 @@
-// Batched execution: every tile of every frame of a batch in one launch of
-// a persistent kernel, instantiated once as a HIP graph.
+// Batched execution: every tile of every frame of a batch in one kernel
+// launch, instantiated once as a HIP graph.
 //
 // Frames of different sizes are cut into tiles of 256 work items (1024
 // pixels for vector frames).  Workgroup b owns the contiguous tile range
