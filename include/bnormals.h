@@ -155,9 +155,10 @@ typedef struct bn_params {
  * BN_FLAG_COUNTS_OVERWRITE in params->flags, REPLACE them (no zeroing
  * needed between calls).  Before the first use the caller zeroes the whole
  * structure (e.g. hipMemset of sizeof(bn_frame_stats) bytes); every call
- * leaves `work` zero again, so a structure can be reused indefinitely.  Two calls that overlap in time must not share one
- * structure.  Place it at a 128-byte aligned address (the workspace is one
- * 128-byte cache line per reduction slot). */
+ * leaves `work` zero again, so a structure can be reused indefinitely.  Two
+ * calls that overlap in time must not share one structure.  Place it at a
+ * 128-byte aligned address (else the calls return BN_ERR_INVALID_ARG): the
+ * workspace is one 128-byte cache line per reduction slot. */
 #define BN_STATS_SLOTS 32
 typedef struct bn_frame_stats {
     uint32_t n_valid;
@@ -168,8 +169,9 @@ typedef struct bn_frame_stats {
 } bn_frame_stats;                             /* 4224 bytes */
 
 /* One frame of a batch.  depth: [height][depth_stride] binary32, row-major,
- * depth_stride >= width (elements).  normals: [height][width][3] binary32,
- * dense.  mask: [height][width] uint8, dense.  stats: nullable. */
+ * depth_stride >= width (elements), 4-byte aligned.  normals:
+ * [height][width][3] binary32, dense, 4-byte aligned.  mask: [height][width]
+ * uint8, dense.  stats: nullable, 128-byte aligned. */
 typedef struct bn_frame {
     const float *depth;
     int32_t height;
@@ -183,7 +185,8 @@ typedef struct bn_frame {
 
 /*
  * One frame: normals, mask and (if stats != NULL) counts.
- *   depth     [height][depth_stride] binary32 depth (z, > 0; 0 = hole)
+ *   depth     [height][depth_stride] binary32 depth (z, > 0; 0 = hole),
+ *             4-byte aligned (as are normals)
  *   fx, fy    focal lengths in pixels (finite, > 0); cx, cy principal point
  *   params    alpha, mode, tau, variant, method, scales, flags (host
  *             pointer, read during the call)

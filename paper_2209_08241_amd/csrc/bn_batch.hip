@@ -206,6 +206,7 @@ int count_frames(const bn_frame *frames, int32_t n, int method, uint64_t *tiles,
         const bn_frame &s = frames[k];
         int rc = check_frame_args(s.depth, s.height, s.width, s.depth_stride, s.fx, s.fy, s.cx,
                                   s.cy, s.normals, s.mask);
+        if (rc == BN_OK) rc = check_stats_arg(s.stats);
         if (rc != BN_OK) return rc;
         if (s.height > 0 && s.width > 0) {
             const bool vec = frame_vec(s, method);

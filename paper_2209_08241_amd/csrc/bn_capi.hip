@@ -52,7 +52,13 @@ int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, f
     if (stride < W) return BN_ERR_INVALID_ARG;
     if (stride > (int64_t)1 << 40) return BN_ERR_UNSUPPORTED;
     if (!depth || !normals || !mask) return BN_ERR_INVALID_ARG;
+    if ((uintptr_t)depth % 4 || (uintptr_t)normals % 4) return BN_ERR_INVALID_ARG;
     return BN_OK;
+}
+
+int check_stats_arg(const bn_frame_stats *stats) {
+    // the in-launch reduction works on 128-byte lines of the structure
+    return ((uintptr_t)stats % 128) ? BN_ERR_INVALID_ARG : BN_OK;
 }
 
 static bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
@@ -154,6 +160,8 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width, int64
     int rc = check_params_args(params);
     if (rc != BN_OK) return rc;
     rc = check_frame_args(depth, height, width, depth_stride, fx, fy, cx, cy, normals, mask);
+    if (rc != BN_OK) return rc;
+    rc = check_stats_arg(stats);
     if (rc != BN_OK) return rc;
     if (height == 0 || width == 0) return BN_OK;
     int v = (int)params->variant;

@@ -29,6 +29,8 @@ const VariantInfo *variant_info(int v);
 int check_params_args(const bn_params *p);
 int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, float fx,
                      float fy, float cx, float cy, const float *normals, const uint8_t *mask);
+// A bn_frame_stats pointer: NULL or 128-byte aligned.
+int check_stats_arg(const bn_frame_stats *stats);
 // True when the frame can use the 4-pixel vector tiles.
 bool vec4_layout(const float *depth, int32_t W, int64_t stride, const float *normals,
                  const uint8_t *mask);

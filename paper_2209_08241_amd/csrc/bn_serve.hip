@@ -356,9 +356,10 @@ class Server {
 
     int submit(const float *depth, bool host, int32_t H, int32_t W, int64_t stride, float fx,
                float fy, float cx, float cy, uint64_t *out_id) {
+        // the outputs live in the server's slots: stand-in aligned pointers
         int rc = check_frame_args(depth, H, W, stride, fx, fy, cx, cy,
-                                  reinterpret_cast<const float *>(1),
-                                  reinterpret_cast<const uint8_t *>(1));
+                                  reinterpret_cast<const float *>(uintptr_t(256)),
+                                  reinterpret_cast<const uint8_t *>(uintptr_t(256)));
         if (rc != BN_OK) return rc;
         if (H == 0 || W == 0) return BN_ERR_INVALID_ARG;
         const SlotLayout l = slot_layout(H, W, host);

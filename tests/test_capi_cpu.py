@@ -156,3 +156,14 @@ def test_probe_argument_errors():
     assert L.bn_stream_copy(0x20000, 0x10000, 0, None) == bn.BN_OK
     assert L.bn_stream_pattern(0x10000, 0x20000, 0x30000, 1000, None) == bn.BN_ERR_INVALID_ARG
     assert L.bn_stream_pattern(0x10004, 0x20000, 0x30000, 1024, None) == bn.BN_ERR_INVALID_ARG
+
+
+def test_alignment_checked_before_launch():
+    p = bn.make_params()
+    # misaligned depth / normals / stats: rejected before any HIP call
+    assert bn.raw_estimate_normals(0x10002, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, p, 0x20000, 0x30000,
+                                   0) == bn.BN_ERR_INVALID_ARG
+    assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, p, 0x20001, 0x30000,
+                                   0) == bn.BN_ERR_INVALID_ARG
+    assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, p, 0x20000, 0x30000,
+                                   0x40040) == bn.BN_ERR_INVALID_ARG
