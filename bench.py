@@ -415,6 +415,94 @@ def plain_launches(args, torch, bn, frames, stream, px):
     return res
 
 
+def run_diff(args, torch, bn, scenes):
+    """Differentiation: 16 x 640x480 frames (seeds 2000..2015), the adjoint
+    kernel alone and one full step (forward, cosine loss against the normals
+    of the noise-free depth, backward through the adjoint)."""
+    import numpy as np
+    import oracle
+    log("generating the 16-frame differentiation batch (seeds 2000..2015)")
+    scs = [scenes.frame_640x480(seed=2000 + i) for i in range(16)]
+    dev = torch.device("cuda:0")
+    depth = [torch.from_numpy(s.depth).to(dev) for s in scs]
+    clean = [torch.from_numpy(s.depth_clean.astype(np.float32)).to(dev) for s in scs]
+    kw = dict(alpha=args.alpha, mode=args.mode, tau=args.tau)
+    targets = [bn.estimate_normals(c, s.fx, s.fy, s.cx, s.cy, want_stats=False, **kw)[:2]
+               for s, c in zip(scs, clean)]
+    gen = torch.Generator(device=dev).manual_seed(5)
+    grads = [torch.randn((480, 640, 3), device=dev, generator=gen) for _ in scs]
+    gd = [torch.empty((480, 640), device=dev) for _ in scs]
+    # the benchmarked adjoint against the oracle's on frame 0 (codes frozen)
+    s0 = scs[0]
+    bn.normals_vjp(depth[0], s0.fx, s0.fy, s0.cx, s0.cy, grads[0], grad_depth=gd[0], **kw)
+    torch.cuda.synchronize()
+    codes = oracle.normals_f32(s0.depth, s0.fx, s0.fy, s0.cx, s0.cy, args.alpha, args.mode,
+                               args.tau)["mask"]
+    ref = oracle.normals_vjp_f64(s0.depth.astype(np.float64), s0.fx, s0.fy, s0.cx, s0.cy,
+                                 args.alpha, codes, grads[0].cpu().numpy().astype(np.float64))
+    got = gd[0].cpu().numpy().astype(np.float64)
+    scale = np.abs(ref).max()
+    if not np.all(np.abs(got - ref) <= 1e-4 * scale + 1e-3 * np.abs(ref)):
+        raise SystemExit("benchmarked adjoint disagrees with the oracle")
+    log("adjoint parity frame 0 ok")
+    stream = torch.cuda.Stream()
+
+    def adjoints(st):
+        for k, s in enumerate(scs):
+            bn.normals_vjp(depth[k], s.fx, s.fy, s.cx, s.cy, grads[k], grad_depth=gd[k],
+                           stream=st, **kw)
+
+    with torch.cuda.stream(stream):
+        adjoints(stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        adjoints(torch.cuda.current_stream())
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    reps = 50
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        for _ in range(reps):
+            g.replay()
+        end.record(stream)
+    end.synchronize()
+    us_frame = start.elapsed_time(end) * 1e3 / (reps * len(scs))
+    px = 480 * 640
+    adj_bytes = 20                      # depth 4 B + cotangent 12 B in, gradient 4 B out
+    achieved = adj_bytes * px / (us_frame * 1e-6) / 1e9
+
+    def step():
+        loss = 0.0
+        for k, s in enumerate(scs):
+            d = depth[k].clone().requires_grad_(True)
+            n, m = bn.normals_with_grad(d, s.fx, s.fy, s.cx, s.cy, **kw)
+            l = bn.cosine_loss(n, targets[k][0], m, targets[k][1])
+            l.backward()
+            loss = loss + float(l.detach())
+        return loss
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nstep = 5
+    for _ in range(nstep):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / nstep
+    return {"workload": "16 x 640x480 (seeds 2000..2015): adjoint kernel per frame (graph replay); "
+                        "full step = forward + cosine loss vs the noise-free depth's normals + "
+                        "backward, eager",
+            "adjoint_us_per_frame": us_frame, "adjoint_mpix_s": px / us_frame,
+            "adjoint_roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                 "bytes_per_pixel": adj_bytes},
+            "step_ms": ms_step, "step_mpix_s": 16 * px / (ms_step * 1e3)}
+
+
 def run_serve(args, torch, bn, scenes, capacity_mpix_s):
     """Poisson request streams over the serving sizes at fractions of the
     batched capacity measured in the same run; device-resident inputs."""
@@ -525,6 +613,8 @@ def main():
                                                 "roofline", "same_frames_plain_launches")}
             if not args.no_serve:
                 out["serving"] = run_serve(args, torch, bn, scenes, b["value"])
+        if not args.quick:
+            out["differentiation"] = run_diff(args, torch, bn, scenes)
     line = {
         "metric": out["metric"],
         "value": out["value"],
@@ -549,8 +639,8 @@ def main():
             ach["batched_frac_of_pattern"] = (out["batched"]["roofline"]["achieved"]
                                               / ach["pattern_GBs"])
         line["achievable"] = ach
-    for k in ("batched", "serving", "methods", "hot_cache", "single_launch_us",
-              "cpu_oracle_all_cores"):
+    for k in ("batched", "serving", "differentiation", "methods", "hot_cache",
+              "single_launch_us", "cpu_oracle_all_cores"):
         if k in out:
             line[k] = out[k]
     print(json.dumps(line), flush=True)

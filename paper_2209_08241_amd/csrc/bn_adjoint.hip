@@ -11,8 +11,10 @@
 // and the taps receive  d2: dP + dS,  d4: -dP + dS,  d3: dQ + dT,
 // d5: -dQ + dT.
 //
-// Gather form: a workgroup owns a 64 x 16 tile of output depths.  It stages
-// the depth of the tile plus a 2-alpha ring in LDS, evaluates every pixel of
+// Gather form: a workgroup owns a TX x TY tile of output depths (64 x 16, or
+// 32 x 8 on frames under 2^20 pixels, which would otherwise leave most
+// compute units idle).  It stages the depth of the tile plus a 2-alpha ring
+// in LDS, evaluates every pixel of
 // the tile plus an alpha ring once (its code and its four tap gradients, in
 // LDS), and each output depth then sums the four contributions that land on
 // it, in a fixed order.  No atomics: the result is deterministic.
@@ -23,12 +25,10 @@
 
 namespace bn {
 
-constexpr int kAdjTX = 64;
-constexpr int kAdjTY = 16;
-
-template <int A>
+template <int A, int TX, int TY>
 __global__ __launch_bounds__(kBlock) void k_vjp(FrameArgs f, const float *__restrict__ gn,
                                                 float *__restrict__ gd, uint32_t tiles_x) {
+    constexpr int kAdjTX = TX, kAdjTY = TY;
     constexpr int DX = kAdjTX + 4 * A, DY = kAdjTY + 4 * A;  // depth tile
     constexpr int GX = kAdjTX + 2 * A, GY = kAdjTY + 2 * A;  // evaluated pixels
     __shared__ float s_d[DY * DX];
@@ -100,16 +100,17 @@ __global__ __launch_bounds__(kBlock) void k_vjp(FrameArgs f, const float *__rest
 
 typedef void (*VjpFn)(FrameArgs, const float *, float *, uint32_t);
 
-static VjpFn vjp_kernel(int a) {
+template <int TX, int TY>
+static VjpFn vjp_kernel_t(int a) {
     switch (a) {
-        case 1: return k_vjp<1>;
-        case 2: return k_vjp<2>;
-        case 3: return k_vjp<3>;
-        case 4: return k_vjp<4>;
-        case 5: return k_vjp<5>;
-        case 6: return k_vjp<6>;
-        case 7: return k_vjp<7>;
-        case 8: return k_vjp<8>;
+        case 1: return k_vjp<1, TX, TY>;
+        case 2: return k_vjp<2, TX, TY>;
+        case 3: return k_vjp<3, TX, TY>;
+        case 4: return k_vjp<4, TX, TY>;
+        case 5: return k_vjp<5, TX, TY>;
+        case 6: return k_vjp<6, TX, TY>;
+        case 7: return k_vjp<7, TX, TY>;
+        case 8: return k_vjp<8, TX, TY>;
     }
     return nullptr;
 }
@@ -133,13 +134,15 @@ extern "C" int bn_normals_vjp(const float *depth, int32_t height, int32_t width,
                           reinterpret_cast<const uint8_t *>(grad_depth));
     if (rc != BN_OK) return rc;
     if (height == 0 || width == 0) return BN_OK;
-    VjpFn fn = vjp_kernel(params->alpha);
+    const bool small = (int64_t)height * width < (1 << 20);
+    const uint32_t TX = small ? 32u : 64u, TY = small ? 8u : 16u;
+    VjpFn fn = small ? vjp_kernel_t<32, 8>(params->alpha) : vjp_kernel_t<64, 16>(params->alpha);
     if (!fn) return BN_ERR_UNSUPPORTED;
     FrameArgs f;
     fill_frame_args(f, depth, height, width, depth_stride, fx, fy, cx, cy, params, nullptr,
                     nullptr, nullptr, 1);
-    const uint32_t tx = ((uint32_t)width + kAdjTX - 1) / kAdjTX;
-    const uint32_t ty = ((uint32_t)height + kAdjTY - 1) / kAdjTY;
+    const uint32_t tx = ((uint32_t)width + TX - 1) / TX;
+    const uint32_t ty = ((uint32_t)height + TY - 1) / TY;
     hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(kBlock), 0, (hipStream_t)stream, f, grad_normals,
                        grad_depth, tx);
     return hipGetLastError() == hipSuccess ? BN_OK : BN_ERR_DEVICE;

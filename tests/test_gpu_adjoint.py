@@ -45,7 +45,17 @@ def test_vjp_random_cotangent(alpha):
     log(f"alpha={alpha}: max |gpu - oracle| / max|grad| = {e:.2e}")
 
 
-@pytest.mark.parametrize("H,W,pad", [(1, 1, 0), (5, 7, 0), (33, 65, 3), (17, 130, 0), (70, 90, 5)])
+@pytest.mark.parametrize("alpha", [1, 2, 5])
+def test_vjp_large_frame_tiles(alpha):
+    """Frames of 2^20 pixels and more take the 64 x 16 tiles."""
+    s = scenes.frame_1920x1080(seed=2100 + alpha)
+    rng = np.random.default_rng(100 + alpha)
+    g = rng.standard_normal((1080, 1920, 3))
+    check_vjp(s.depth, *s.intrinsics, alpha, g, what=f"1920x1080 alpha={alpha}")
+
+
+@pytest.mark.parametrize("H,W,pad", [(1, 1, 0), (5, 7, 0), (33, 65, 3), (17, 130, 0), (70, 90, 5),
+                                     (1024, 1024, 0), (1023, 1025, 2)])
 def test_vjp_shapes(H, W, pad):
     rng = np.random.default_rng(H * W)
     d = rng.uniform(1.0, 1.3, size=(H, W)).astype(np.float32)
