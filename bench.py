@@ -271,7 +271,8 @@ def run_plain(args, torch, bn, scenes):
                                       "cache holds it, not an HBM figure"}
         extra["single_launch_us"] = ring.single_launch_us(kw)
         methods = []
-        for name, alpha, K in (("pair_removal", args.alpha, 0), ("multiscale", 1, 3)):
+        for name, alpha, K in (("pair_removal", args.alpha, 0), ("multiscale", 1, 3),
+                               ("multiscale", 3, 3)):
             mkw = dict(alpha=alpha, mode=args.mode, tau=args.tau, method=name, scales=K)
             parity_check(ring, mkw, alpha, args.mode, args.tau, name, K)
             mms, msteps, _, _ = ring.time(mkw, args.steps // 2, args.warmup // 2)

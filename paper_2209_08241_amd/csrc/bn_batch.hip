@@ -146,7 +146,7 @@ static BatchKernelFn batch_kernel_m(int alpha) {
 static BatchKernelFn batch_kernel(int method, int alpha) {
     if (method == kFourPair) return batch_kernel_m<kFourPair>(alpha);
     if (method == kPairRemoval) return batch_kernel_m<kPairRemoval>(alpha);
-    if (method == kMultiScale) return k_batch<1, kMultiScale>;  // runtime offsets
+    if (method == kMultiScale) return batch_kernel_m<kMultiScale>(alpha);
     return nullptr;
 }
 
@@ -192,14 +192,13 @@ size_t buffer_bytes(int32_t capacity, uint64_t tile_capacity) {
     return table_offset(capacity) + sizeof(uint32_t) * (size_t)tile_capacity;
 }
 
-// Vector tiles for this frame under the method?
-bool frame_vec(const bn_frame &s, int method) {
-    return method_has_vec4(method) &&
-           vec4_layout(s.depth, s.width, s.depth_stride, s.normals, s.mask);
+// Vector tiles for this frame under these parameters?
+bool frame_vec(const bn_frame &s, const bn_params *p) {
+    return method_has_vec4(p) && vec4_layout(s.depth, s.width, s.depth_stride, s.normals, s.mask);
 }
 
 // Validate the frames; total tiles and pixels.
-int count_frames(const bn_frame *frames, int32_t n, int method, uint64_t *tiles,
+int count_frames(const bn_frame *frames, int32_t n, const bn_params *p, uint64_t *tiles,
                  uint64_t *pixels) {
     uint64_t t = 0, px = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -209,7 +208,7 @@ int count_frames(const bn_frame *frames, int32_t n, int method, uint64_t *tiles,
         if (rc == BN_OK) rc = check_stats_arg(s.stats);
         if (rc != BN_OK) return rc;
         if (s.height > 0 && s.width > 0) {
-            const bool vec = frame_vec(s, method);
+            const bool vec = frame_vec(s, p);
             const uint64_t items = (uint64_t)s.height * (uint64_t)(vec ? s.width / 4 : s.width);
             t += (items + kBlock - 1) / kBlock;
             px += (uint64_t)s.height * (uint64_t)s.width;
@@ -235,7 +234,7 @@ int build_table(const bn_frame *frames, int32_t n, const bn_params *p, int32_t c
     uint64_t tiles = 0;
     for (int32_t k = 0; k < n; ++k) {
         const bn_frame &s = frames[k];
-        const bool vec = frame_vec(s, p->method);
+        const bool vec = frame_vec(s, p);
         BatchFrame b;
         std::memset(&b, 0, sizeof(b));
         uint64_t nt = 0;
@@ -368,7 +367,7 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
     BatchKernelFn fn = batch_kernel(params->method, params->alpha);
     if (!fn) return BN_ERR_UNSUPPORTED;
     uint64_t tiles = 0, pixels = 0;
-    rc = count_frames(frames_host, n_frames, params->method, &tiles, &pixels);
+    rc = count_frames(frames_host, n_frames, params, &tiles, &pixels);
     if (rc != BN_OK) return rc;
 
     bn_batch_plan *pl = new (std::nothrow) bn_batch_plan();
@@ -422,7 +421,7 @@ int bn_batch_plan_update(bn_batch_plan *plan, const bn_frame *frames_host, int32
     if (n_frames > plan->capacity) return BN_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     uint64_t tiles = 0, pixels = 0;
-    int rc = count_frames(frames_host, n_frames, plan->params.method, &tiles, &pixels);
+    int rc = count_frames(frames_host, n_frames, &plan->params, &tiles, &pixels);
     if (rc != BN_OK) return rc;
     const uint32_t grid = grid_for(tiles, plan->cus, plan->blocks_per_cu);
     if (tiles > 0 && (tiles + grid - 1) / grid > 4096) return BN_ERR_UNSUPPORTED;

@@ -39,7 +39,9 @@ int check_params_args(const bn_params *p) {
     return BN_OK;
 }
 
-bool method_has_vec4(int method) { return method != BN_METHOD_MULTISCALE; }
+bool method_has_vec4(const bn_params *p) {
+    return p->method != BN_METHOD_MULTISCALE || p->alpha * p->scales <= BN_MAX_ALPHA;
+}
 
 int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, float fx,
                      float fy, float cx, float cy, const float *normals, const uint8_t *mask) {
@@ -77,11 +79,11 @@ static bool variant_ok(int v, const float *depth, int32_t W, int64_t stride,
     return true;
 }
 
-static bool method_variant_ok(int method, int v, const float *depth, int32_t W, int64_t stride,
-                              const float *normals, const uint8_t *mask) {
+static bool method_variant_ok(const bn_params *p, int v, const float *depth, int32_t W,
+                              int64_t stride, const float *normals, const uint8_t *mask) {
     const VariantInfo *vi = variant_info(v);
     if (!vi) return false;
-    if (vi->px_per_item == 4 && !method_has_vec4(method)) return false;
+    if (vi->px_per_item == 4 && !method_has_vec4(p)) return false;
     return variant_ok(v, depth, W, stride, normals, mask);
 }
 
@@ -113,11 +115,10 @@ static float abs_threshold(int method, int scales, float fx, float fy, float tau
 }
 
 static int pick_variant(const float *depth, int32_t H, int32_t W, int64_t stride,
-                        const float *normals, const uint8_t *mask, int method, int alpha) {
-    const int tuned = tuned_plain_variant(method, alpha, (uint64_t)H * (uint64_t)W);
-    if (tuned > 0 && method_variant_ok(method, tuned, depth, W, stride, normals, mask))
-        return tuned;
-    if (method_has_vec4(method) && vec4_layout(depth, W, stride, normals, mask)) return VAR_VEC4;
+                        const float *normals, const uint8_t *mask, const bn_params *p) {
+    const int tuned = tuned_plain_variant(p->method, p->alpha, (uint64_t)H * (uint64_t)W);
+    if (tuned > 0 && method_variant_ok(p, tuned, depth, W, stride, normals, mask)) return tuned;
+    if (method_has_vec4(p) && vec4_layout(depth, W, stride, normals, mask)) return VAR_VEC4;
     return VAR_SCALAR;
 }
 
@@ -166,9 +167,8 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width, int64
     if (height == 0 || width == 0) return BN_OK;
     int v = (int)params->variant;
     if (v == VAR_AUTO) {
-        v = pick_variant(depth, height, width, depth_stride, normals, mask, params->method,
-                         params->alpha);
-    } else if (!method_variant_ok(params->method, v, depth, width, depth_stride, normals, mask)) {
+        v = pick_variant(depth, height, width, depth_stride, normals, mask, params);
+    } else if (!method_variant_ok(params, v, depth, width, depth_stride, normals, mask)) {
         return BN_ERR_UNSUPPORTED;
     }
     FrameArgs f;

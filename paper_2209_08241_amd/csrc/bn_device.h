@@ -238,36 +238,31 @@ __device__ __forceinline__ PixelOut eval_method(bool inside, float d1, float d2,
 // tau^2 (sum a_i w_i)^2.  Only the taps right of and below the pixel are
 // read: inside means x + K alpha < W and y + K alpha < H.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ PixelOut eval_pixel_multiscale(bool inside, const float *p, float xc,
-                                                          float yc, const FrameArgs &f) {
-    const float d1 = *p;
-    uint32_t ok = (inside ? 1u : 0u) & tap_ok(d1);
-    float Mx = 0.0f, My = 0.0f, Mz = 0.0f, Wt = 0.0f;
-    if (inside) {
-        for (int i = 1; i <= f.scales; ++i) {
-            const int off = i * f.alpha;
-            const float a = (float)off;
-            const float d2 = p[off];
-            const float d3 = p[(int64_t)off * f.stride];
-            ok &= tap_ok(d2) & tap_ok(d3);
-            const float e2 = d2 - d1;
-            const float e3 = d3 - d1;
-            const float A = e2 * d3;
-            const float B = d2 * e3;
-            const float C = d2 * d3;
-            const float mx = f.fx * A;
-            const float my = f.fy * B;
-            const float xa = xc * A;
-            const float yb = yc * B;
-            const float t3 = xa + yb;
-            const float w = a * C;
-            const float mz = t3 + w;
-            Mx = Mx + a * mx;
-            My = My + a * my;
-            Mz = Mz + a * mz;
-            Wt = Wt + a * w;
-        }
-    }
+// One scale: the pair (2, 3) vector at offset a (taps d2 = (x+a, y),
+// d3 = (x, y+a)), weighted by a and added to the running sums.
+__device__ __forceinline__ void ms_accumulate(float d1, float d2, float d3, float a, float xc,
+                                              float yc, const FrameArgs &f, float &Mx, float &My,
+                                              float &Mz, float &Wt) {
+    const float e2 = d2 - d1;
+    const float e3 = d3 - d1;
+    const float A = e2 * d3;
+    const float B = d2 * e3;
+    const float C = d2 * d3;
+    const float mx = f.fx * A;
+    const float my = f.fy * B;
+    const float xa = xc * A;
+    const float yb = yc * B;
+    const float t3 = xa + yb;
+    const float w = a * C;
+    const float mz = t3 + w;
+    Mx = Mx + a * mx;
+    My = My + a * my;
+    Mz = Mz + a * mz;
+    Wt = Wt + a * w;
+}
+
+__device__ __forceinline__ PixelOut ms_finish(uint32_t ok, float Mx, float My, float Mz, float Wt,
+                                              const FrameArgs &f) {
     const float x2 = Mx * Mx;
     const float y2 = My * My;
     const float z2 = Mz * Mz;
@@ -284,6 +279,23 @@ __device__ __forceinline__ PixelOut eval_pixel_multiscale(bool inside, const flo
     o.ny = valid ? My * inv : 0.0f;
     o.nz = valid ? -(Mz * inv) : 0.0f;
     return o;
+}
+
+__device__ __forceinline__ PixelOut eval_pixel_multiscale(bool inside, const float *p, float xc,
+                                                          float yc, const FrameArgs &f) {
+    const float d1 = *p;
+    uint32_t ok = (inside ? 1u : 0u) & tap_ok(d1);
+    float Mx = 0.0f, My = 0.0f, Mz = 0.0f, Wt = 0.0f;
+    if (inside) {
+        for (int i = 1; i <= f.scales; ++i) {
+            const int off = i * f.alpha;
+            const float d2 = p[off];
+            const float d3 = p[(int64_t)off * f.stride];
+            ok &= tap_ok(d2) & tap_ok(d3);
+            ms_accumulate(d1, d2, d3, (float)off, xc, yc, f, Mx, My, Mz, Wt);
+        }
+    }
+    return ms_finish(ok, Mx, My, Mz, Wt, f);
 }
 
 // ---------------------------------------------------------------------------

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
         // one tile: the counts are known before the stores, so the count
         // atomic goes out first and its round trip overlaps the stores
         Vec4Out o;
-        vec4_eval<A, M>(f, blk, o);
+        vec4_eval_method<A, M>(f, blk, o);
         CountTicket tk;
         bool have = false;
         if (f.stats) {
@@ -129,8 +129,11 @@ hipError_t launch_plain(int variant, int method, const FrameArgs &f, hipStream_t
         fn = plain_kernel<kFourPair>(variant, f.alpha);
     } else if (method == kPairRemoval) {
         fn = plain_kernel<kPairRemoval>(variant, f.alpha);
-    } else if (method == kMultiScale && variant == VAR_SCALAR) {
-        fn = k_scalar<1, kMultiScale>;  // runtime offsets
+    } else if (method == kMultiScale) {
+        // scalar tiles take any offsets at run time; vector tiles serve
+        // alpha * scales <= 8
+        fn = variant == VAR_SCALAR ? k_scalar<1, kMultiScale>
+                                   : plain_kernel<kMultiScale>(variant, f.alpha);
     }
     if (!fn) return hipErrorInvalidValue;
     const uint64_t per_block = (uint64_t)kBlock * vi->groups_per_thread;

@@ -119,6 +119,94 @@ __device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec
     o.codes = codes;
 }
 
+// Multi-scale vector tile (alpha * scales <= 8): the taps lie right of and
+// below each pixel, so the row window extends to the right only and the
+// vertical taps are the float4s of rows y + i alpha.  Same arithmetic per
+// scale as the scalar tile.
+template <int A>
+__device__ __forceinline__ void vec4_eval_ms(const FrameArgs &f, uint32_t tile, Vec4Out &o) {
+    constexpr int KMAX = 8 / A;
+    constexpr int RR = (A * KMAX + 3) / 4;  // float4s needed on the right
+    const uint32_t t = threadIdx.x;
+    const uint32_t lane = t & 63u;
+    const uint32_t i = tile * kBlock + t;
+    const bool live = i < f.nitems;
+    o.live = live;
+    uint32_t y = 0, x0 = 0;
+    if (live) {
+        y = row_of(i, f.inv_gpr);
+        x0 = (i - y * f.gpr) * 4u;
+    }
+    const int K = f.scales;
+    const uint32_t reach = (uint32_t)(K * A);
+    const float *rp = f.depth + (int64_t)y * f.stride;
+    const bool rows_in = live & (y + reach < (uint32_t)f.H);
+    f4 c = {0.f, 0.f, 0.f, 0.f};
+    if (live) c = *reinterpret_cast<const f4 *>(rp + x0);
+    f4 dn[KMAX];
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s) {
+        dn[s] = f4{0.f, 0.f, 0.f, 0.f};
+        if (s < K && rows_in)
+            dn[s] = *reinterpret_cast<const f4 *>(rp + (int64_t)((s + 1) * A) * f.stride + x0);
+    }
+    float row[4 * (RR + 1)];
+    row[0] = c.x;
+    row[1] = c.y;
+    row[2] = c.z;
+    row[3] = c.w;
+    f4 rk = c;
+#pragma unroll
+    for (int k = 1; k <= RR; ++k) {
+        rk = from_right(rk);
+        if (lane == 63) {
+            const int xs = (int)x0 + 4 * k;
+            rk = (live && xs < f.W) ? *reinterpret_cast<const f4 *>(rp + xs) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+        row[4 * k + 0] = rk.x;
+        row[4 * k + 1] = rk.y;
+        row[4 * k + 2] = rk.z;
+        row[4 * k + 3] = rk.w;
+    }
+    const float yc = (float)y - f.cy;
+    uint32_t codes = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t x = x0 + j;
+        const bool inside = rows_in & (x + reach < (uint32_t)f.W);
+        const float xc = (float)x - f.cx;
+        const float d1 = row[j];
+        uint32_t ok = (inside ? 1u : 0u) & tap_ok(d1);
+        float Mx = 0.0f, My = 0.0f, Mz = 0.0f, Wt = 0.0f;
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s) {
+            if (s < K) {
+                const float d2 = row[j + (s + 1) * A];
+                const float dv[4] = {dn[s].x, dn[s].y, dn[s].z, dn[s].w};
+                const float d3 = dv[j];
+                ok &= tap_ok(d2) & tap_ok(d3);
+                ms_accumulate(d1, d2, d3, (float)((s + 1) * A), xc, yc, f, Mx, My, Mz, Wt);
+            }
+        }
+        const PixelOut p = ms_finish(ok, Mx, My, Mz, Wt, f);
+        o.nv[3 * j + 0] = p.nx;
+        o.nv[3 * j + 1] = p.ny;
+        o.nv[3 * j + 2] = p.nz;
+        codes |= p.code << (8 * j);
+    }
+    o.codes = codes;
+}
+
+// The vector tile of method M.
+template <int A, int M>
+__device__ __forceinline__ void vec4_eval_method(const FrameArgs &f, uint32_t tile, Vec4Out &o) {
+    if constexpr (M == kMultiScale) {
+        vec4_eval_ms<A>(f, tile, o);
+    } else {
+        vec4_eval<A, M>(f, tile, o);
+    }
+}
+
 // Vector tile, second half: the four codes with one 32-bit store, the 12
 // normal floats through the wavefront's LDS slice with contiguous 16-byte
 // stores (lane l holds groups 3l..3l+2 of the slice; store k writes
@@ -249,13 +337,14 @@ __device__ __forceinline__ void scalar_count(const ScalarOut &r, uint32_t &cv, u
 
 // One whole tile of either kind, method M.  No workgroup barrier:
 // consecutive tiles of a workgroup may overlap freely.  The multi-scale
-// method has scalar tiles only.
+// method takes vector tiles only when alpha * scales <= 8 (the host's
+// choice).
 template <int A, int M>
 __device__ __forceinline__ void run_tile(const FrameArgs &f, bool vec, uint32_t tile, TileLds &lds,
                                          uint32_t &cv, uint32_t &cb) {
-    if (M != kMultiScale && vec) {
+    if (vec) {
         Vec4Out o;
-        vec4_eval<A, M>(f, tile, o);
+        vec4_eval_method<A, M>(f, tile, o);
         vec4_write(f, tile, lds, o);
         if (f.stats) vec4_count(o, cv, cb);
     } else {

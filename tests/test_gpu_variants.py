@@ -55,20 +55,33 @@ def test_pair_removal_640(f640, alpha, mode, tau, variant):
                                      (1, 8), (8, 8)])
 @pytest.mark.parametrize("mode,tau", [("rel", 4.0), ("abs", 5e-3), ("none", 1.0)])
 def test_multiscale_640(f640, alpha, K, mode, tau):
+    """Every variant the offsets allow against the oracle, and the vector
+    tiles against the scalar tiles bit for bit."""
     log(f"multiscale 640x480 alpha={alpha} K={K} {mode}")
     s = f640
-    for variant in (0, 1):
+    variants = (0, 1, 2, 3, 4) if alpha * K <= 8 else (0, 1)
+    scalar = run(s.depth, *s.intrinsics, alpha, mode, tau, MS, K, 1)
+    for variant in variants:
         check(s.depth, *s.intrinsics, alpha, mode, tau, MS, K, variant,
               what=f"multiscale a={alpha} K={K} v={variant}")
+        got = run(s.depth, *s.intrinsics, alpha, mode, tau, MS, K, variant)
+        for a, b in zip(got, scalar):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), f"v={variant}"
 
 
-def test_multiscale_rejects_vector_variants(f640):
+@pytest.mark.parametrize("alpha,K", [(3, 3), (2, 5), (8, 2), (1, 8)])
+def test_multiscale_vector_variants_need_short_reach(f640, alpha, K):
+    """Vector tiles serve alpha * K <= 8 only; beyond it the request for one
+    is refused and the automatic choice is the scalar tile."""
     import torch
     s = f640
     d = to_gpu(s.depth)
     for v in (2, 3, 4):
+        if alpha * K <= 8:
+            bn.estimate_normals(d, *s.intrinsics, alpha, method=MS, scales=K, variant=v)
+            continue
         with pytest.raises(bn.BnError) as e:
-            bn.estimate_normals(d, *s.intrinsics, 1, method=MS, scales=2, variant=v)
+            bn.estimate_normals(d, *s.intrinsics, alpha, method=MS, scales=K, variant=v)
         assert e.value.status == bn.BN_ERR_UNSUPPORTED
     torch.cuda.synchronize()
 
@@ -89,7 +102,7 @@ def test_1920x1080_sampled_rows(f1080, method, alpha, K):
 
 
 @pytest.mark.parametrize("H,W", [(1, 1), (3, 5), (5, 3), (17, 33), (33, 17), (9, 1025),
-                                 (31, 129), (2, 2048), (64, 4)])
+                                 (31, 129), (2, 2048), (64, 4), (11, 12), (19, 260), (7, 1028)])
 def test_ragged_and_strided(H, W):
     rng = np.random.default_rng(H * 7919 + W)
     d = rng.uniform(0.8, 1.3, size=(H, W)).astype(np.float32)
@@ -137,7 +150,7 @@ def test_step_scene_pairs_keep_own_plane():
     assert err <= 4 * 2.0 ** -24 * max(fx, fy) + NORMAL_TOL
 
 
-@pytest.mark.parametrize("method,alpha,K", [(PR, 2, 0), (MS, 1, 3), ("four_pair", 2, 0)])
+@pytest.mark.parametrize("method,alpha,K", [(PR, 2, 0), (MS, 1, 3), (MS, 3, 3), ("four_pair", 2, 0)])
 def test_batch_equals_plain(method, alpha, K):
     import torch
     frames_h = [scenes.sized_frame(H, W, 40 + k) for k, (H, W) in
