@@ -248,10 +248,17 @@ int bn_normals_vjp(const float *depth, int32_t height, int32_t width, int64_t de
  * bn_batch_plan_update: replaces the frame list (n_frames <= capacity) with
  *   an asynchronous copy on `stream`, ordered after earlier work and before
  *   later runs on that stream.  The instantiated graph is kept; its kernel
- *   nodes' launch parameters (grid, table sizes) are updated in place.  A
- *   list with more tiles than the plan's tables hold grows them, which first
- *   synchronises `stream` (the plan's earlier runs must have finished).
- * bn_batch_run: one launch over the current frame list on `stream`.
+ *   nodes' launch parameters (grid, table sizes) are updated in place by the
+ *   next bn_batch_run.  A list with more tiles than the plan's tables hold
+ *   grows them, which first synchronises `stream` (the plan's earlier runs
+ *   must have finished).
+ * bn_batch_run: one replay of the plan's graph over the current frame list
+ *   on `stream`.
+ * bn_batch_launch: the same two kernels, with the same output, as two
+ *   ordinary launches on `stream` instead of a graph replay.  Costs less host
+ *   time per call (a graph replay costs tens of microseconds), so it suits
+ *   small, latency-bound batches such as a server's; a long batch is the
+ *   same either way.
  * bn_batch_plan_info: pixels, tiles and workgroups of the current list.
  * bn_batch_plan_destroy: frees the plan; the caller makes sure no run of it
  *   is still in flight.
@@ -262,6 +269,7 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
 int bn_batch_plan_update(bn_batch_plan *plan, const bn_frame *frames_host, int32_t n_frames,
                          void *stream);
 int bn_batch_run(bn_batch_plan *plan, void *stream);
+int bn_batch_launch(bn_batch_plan *plan, void *stream);
 int bn_batch_plan_info(const bn_batch_plan *plan, int64_t *n_pixels, int64_t *n_tiles,
                        int32_t *n_workgroups);
 void bn_batch_plan_destroy(bn_batch_plan *plan);

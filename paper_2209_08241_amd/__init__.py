@@ -134,6 +134,8 @@ def _bind_batch(L) -> None:
     L.bn_batch_plan_info.restype = ctypes.c_int
     L.bn_batch_run.argtypes = [vp, vp]
     L.bn_batch_run.restype = ctypes.c_int
+    L.bn_batch_launch.argtypes = [vp, vp]
+    L.bn_batch_launch.restype = ctypes.c_int
     L.bn_batch_plan_destroy.argtypes = [vp]
     L.bn_batch_plan_destroy.restype = None
     L.bn_batch_plan_autotune.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
@@ -297,9 +299,16 @@ class BatchPlan:
         return self._frames
 
     def run(self, stream=None) -> None:
+        """Replay the plan's graph on `stream`."""
         rc = lib().bn_batch_run(self._h, ctypes.c_void_p(_stream_handle(stream)))
         if rc != BN_OK:
             raise BnError(rc, "bn_batch_run")
+
+    def launch(self, stream=None) -> None:
+        """The same kernels as two plain launches (less host time per call)."""
+        rc = lib().bn_batch_launch(self._h, ctypes.c_void_p(_stream_handle(stream)))
+        if rc != BN_OK:
+            raise BnError(rc, "bn_batch_launch")
 
     def update(self, frames, stream=None) -> None:
         frames = list(frames)

@@ -176,6 +176,7 @@ struct bn_batch_plan {
     hipGraphNode_t count_node = nullptr;   // the per-frame count sums
     BatchKernelFn fn = nullptr;
     BatchHeader hdr{};                     // current header (kernel arguments)
+    bool graph_stale = false;              // node parameters behind the frame list
     uint64_t total_tiles = 0;
     uint64_t total_pixels = 0;
 };
@@ -270,22 +271,41 @@ hipKernelNodeParams kernel_params(void *func, uint32_t grid, void **args) {
     return kp;
 }
 
+// The two kernels' arguments for the plan's current buffers and header.
+struct BatchArgs {
+    const BatchFrame *frames;
+    const uint32_t *tile_frame;
+    uint32_t *wave_counts;
+    const uint32_t *wave_counts_c;
+    uint32_t ntiles, chunk, nframes;
+    void *main[6];
+    void *counts[3];
+    explicit BatchArgs(const bn_batch_plan *pl)
+        : frames(reinterpret_cast<const BatchFrame *>(static_cast<const char *>(pl->dbuf) +
+                                                      sizeof(BatchHeader))),
+          tile_frame(reinterpret_cast<const uint32_t *>(static_cast<const char *>(pl->dbuf) +
+                                                        table_offset(pl->capacity))),
+          wave_counts(pl->dcounts),
+          wave_counts_c(pl->dcounts),
+          ntiles(pl->hdr.ntiles),
+          chunk(pl->hdr.chunk),
+          nframes(pl->hdr.nframes),
+          main{(void *)&frames, (void *)&tile_frame, (void *)&wave_counts,
+               (void *)&ntiles, (void *)&chunk,      (void *)&nframes},
+          counts{(void *)&frames, (void *)&wave_counts_c, (void *)&nframes} {}
+    BatchArgs(const BatchArgs &) = delete;
+    BatchArgs &operator=(const BatchArgs &) = delete;
+    uint32_t count_grid() const { return nframes ? nframes : 1u; }
+};
+
 // Kernel node parameters (buffer pointers, header values, grids) into the
 // graph, or a fresh graph [tile kernel] -> [count sums] when none exists.
 int refresh_node(bn_batch_plan *pl) {
-    const BatchFrame *d_frames = reinterpret_cast<const BatchFrame *>(
-        static_cast<const char *>(pl->dbuf) + sizeof(BatchHeader));
-    const uint32_t *d_tf = reinterpret_cast<const uint32_t *>(
-        static_cast<const char *>(pl->dbuf) + table_offset(pl->capacity));
-    uint32_t *d_wc = pl->dcounts;
-    uint32_t ntiles = pl->hdr.ntiles, chunk = pl->hdr.chunk, nframes = pl->hdr.nframes;
-    void *args[6] = {(void *)&d_frames, (void *)&d_tf, (void *)&d_wc,
-                     (void *)&ntiles,   (void *)&chunk, (void *)&nframes};
-    hipKernelNodeParams kp = kernel_params(reinterpret_cast<void *>(pl->fn), pl->grid, args);
-    const uint32_t *d_wc_c = pl->dcounts;
-    void *cargs[3] = {(void *)&d_frames, (void *)&d_wc_c, (void *)&nframes};
+    BatchArgs a(pl);
+    hipKernelNodeParams kp = kernel_params(reinterpret_cast<void *>(pl->fn), pl->grid, a.main);
     hipKernelNodeParams cp = kernel_params(reinterpret_cast<void *>(k_batch_counts),
-                                           nframes ? nframes : 1u, cargs);
+                                           a.count_grid(), a.counts);
+    pl->graph_stale = false;
     if (!pl->exec) {
         if (hipGraphCreate(&pl->graph, 0) != hipSuccess ||
             hipGraphAddKernelNode(&pl->node, pl->graph, nullptr, 0, &kp) != hipSuccess ||
@@ -461,12 +481,30 @@ int bn_batch_plan_update(bn_batch_plan *plan, const bn_frame *frames_host, int32
     plan->next = 1 - k;
     plan->total_tiles = tiles;
     plan->total_pixels = pixels;
-    return refresh_node(plan);  // new header values, grids and pointers
+    // new header values, grids and pointers reach the graph at its next run
+    plan->graph_stale = true;
+    return BN_OK;
 }
 
 int bn_batch_run(bn_batch_plan *plan, void *stream) {
     if (!plan || !plan->exec) return BN_ERR_INVALID_ARG;
+    if (plan->graph_stale) {
+        const int rc = refresh_node(plan);
+        if (rc != BN_OK) return rc;
+    }
     return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? BN_OK : BN_ERR_DEVICE;
+}
+
+int bn_batch_launch(bn_batch_plan *plan, void *stream) {
+    if (!plan || !plan->exec) return BN_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    BatchArgs a(plan);
+    if (hipLaunchKernel(reinterpret_cast<const void *>(plan->fn), dim3(plan->grid),
+                        dim3(kBlock), a.main, 0, s) != hipSuccess ||
+        hipLaunchKernel(reinterpret_cast<const void *>(k_batch_counts), dim3(a.count_grid()),
+                        dim3(kBlock), a.counts, 0, s) != hipSuccess)
+        return BN_ERR_DEVICE;
+    return BN_OK;
 }
 
 int bn_batch_plan_info(const bn_batch_plan *plan, int64_t *n_pixels, int64_t *n_tiles,

@@ -230,7 +230,9 @@ class HipBackend : public Backend {
             hipStreamWaitEvent(compute_, up, 0) != hipSuccess)
             return BN_ERR_DEVICE;
         uploads_.push_back(up);
-        rc = bn_batch_run(plan, compute_);
+        // plain launches: a graph replay costs more host time than the
+        // kernels of a typical batch of requests take on the GPU
+        rc = bn_batch_launch(plan, compute_);
         if (rc != BN_OK) return rc;
         hipEvent_t e = take_event();
         if (!e || hipEventRecord(e, compute_) != hipSuccess) return BN_ERR_DEVICE;

@@ -23,7 +23,7 @@ def declared_functions():
 def test_header_declares_the_api():
     names = declared_functions()
     for want in ("bn_estimate_normals", "bn_batch_plan_create", "bn_batch_plan_update",
-                 "bn_batch_run", "bn_batch_plan_destroy", "bn_status_string", "bn_version"):
+                 "bn_batch_run", "bn_batch_launch", "bn_batch_plan_destroy", "bn_status_string", "bn_version"):
         assert want in names
 
 
@@ -134,6 +134,7 @@ def test_batch_plan_argument_errors():
     forced = bn.make_params(variant=2)
     assert L.bn_batch_plan_create(fr, 1, ctypes.byref(forced), ctypes.byref(h)) == bn.BN_ERR_UNSUPPORTED
     assert L.bn_batch_run(None, None) == bn.BN_ERR_INVALID_ARG
+    assert L.bn_batch_launch(None, None) == bn.BN_ERR_INVALID_ARG
     L.bn_batch_plan_destroy(None)
 
 

@@ -169,3 +169,37 @@ def test_graph_replay_deterministic(mixed_batch):
                 assert torch.equal(n0.view(torch.int32), f.normals.view(torch.int32))
                 assert torch.equal(m0, f.mask)
                 assert torch.equal(s0, f.stats[:3])
+
+
+def test_direct_launch_equals_graph_replay():
+    """bn_batch_launch writes what bn_batch_run writes, across updates that
+    change the frame list in between (the graph picks its new parameters up
+    at its next replay, whichever call came before)."""
+    import torch
+    lists = [[scenes.sized_frame(240, 320, seed=90), scenes.sized_frame(97, 131, seed=91)],
+             [scenes.sized_frame(480, 640, seed=92)],
+             [scenes.sized_frame(120, 160, seed=93), scenes.sized_frame(720, 1280, seed=94),
+              scenes.sized_frame(33, 65, seed=95)]]
+    first = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in lists[0]]
+    with bn.BatchPlan(first + first[:1], alpha=2) as plan:
+        for k, lst in enumerate(lists):
+            frames = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in lst]
+            plan.update(frames)
+            order = ("launch", "run") if k % 2 == 0 else ("run", "launch")
+            got = {}
+            for how in order:
+                for f in frames:
+                    f.normals.fill_(7.0)
+                    f.mask.fill_(9)
+                    f.stats.zero_()
+                getattr(plan, how)()
+                torch.cuda.synchronize()
+                got[how] = [(f.normals.clone(), f.mask.clone(), f.stats.clone()) for f in frames]
+            for (n0, m0, s0), (n1, m1, s1) in zip(got["run"], got["launch"]):
+                assert torch.equal(n0.view(torch.int32), n1.view(torch.int32))
+                assert torch.equal(m0, m1)
+                assert torch.equal(s0, s1)
+            for s, (n, m, st) in zip(lst, got["launch"]):
+                ref = oracle.normals_f32(s.depth, s.fx, s.fy, s.cx, s.cy, 2, "rel", 4.0)
+                assert_parity(ref, n.cpu().numpy(), m.cpu().numpy(), st.cpu().numpy(),
+                              what=f"list {k} {s.depth.shape}")
