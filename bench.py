@@ -417,25 +417,29 @@ def plain_launches(args, torch, bn, frames, stream, px):
 
 
 def run_diff(args, torch, bn, scenes):
-    """Differentiation: 16 x 640x480 frames (seeds 2000..2015), the adjoint
-    kernel alone and one full step (forward, cosine loss against the normals
-    of the noise-free depth, backward through the adjoint)."""
+    """Differentiation: 16 x 640x480 frames (seeds 2000..2015) as one stack.
+    The adjoint kernel over the stack (one launch), the forward over the
+    stack, the adjoint as 16 single-frame launches for comparison, and one
+    full step (forward, cosine loss against the normals of the noise-free
+    depth, backward through the adjoint)."""
     import numpy as np
     import oracle
     log("generating the 16-frame differentiation batch (seeds 2000..2015)")
     scs = [scenes.frame_640x480(seed=2000 + i) for i in range(16)]
     dev = torch.device("cuda:0")
-    depth = [torch.from_numpy(s.depth).to(dev) for s in scs]
-    clean = [torch.from_numpy(s.depth_clean.astype(np.float32)).to(dev) for s in scs]
+    n, H, W = len(scs), 480, 640
+    px = H * W
+    intr = [(s.fx, s.fy, s.cx, s.cy) for s in scs]
+    depth = torch.from_numpy(np.stack([s.depth for s in scs])).to(dev)
+    clean = torch.from_numpy(np.stack([s.depth_clean for s in scs]).astype(np.float32)).to(dev)
     kw = dict(alpha=args.alpha, mode=args.mode, tau=args.tau)
-    targets = [bn.estimate_normals(c, s.fx, s.fy, s.cx, s.cy, want_stats=False, **kw)[:2]
-               for s, c in zip(scs, clean)]
+    t_n, t_m, _ = bn.estimate_normals_stack(clean, intr, want_stats=False, **kw)
     gen = torch.Generator(device=dev).manual_seed(5)
-    grads = [torch.randn((480, 640, 3), device=dev, generator=gen) for _ in scs]
-    gd = [torch.empty((480, 640), device=dev) for _ in scs]
+    grads = torch.randn((n, H, W, 3), device=dev, generator=gen)
+    gd = torch.empty((n, H, W), device=dev)
     # the benchmarked adjoint against the oracle's on frame 0 (codes frozen)
     s0 = scs[0]
-    bn.normals_vjp(depth[0], s0.fx, s0.fy, s0.cx, s0.cy, grads[0], grad_depth=gd[0], **kw)
+    bn.normals_vjp_stack(depth, intr, grads, grad_depth=gd, **kw)
     torch.cuda.synchronize()
     codes = oracle.normals_f32(s0.depth, s0.fx, s0.fy, s0.cx, s0.cy, args.alpha, args.mode,
                                args.tau)["mask"]
@@ -448,60 +452,76 @@ def run_diff(args, torch, bn, scenes):
     log("adjoint parity frame 0 ok")
     stream = torch.cuda.Stream()
 
-    def adjoints(st):
+    def timed_graph(fn, reps=50):
+        """us per call of fn(stream), captured once and replayed."""
+        with torch.cuda.stream(stream):
+            fn(stream)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            fn(torch.cuda.current_stream())
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            start.record(stream)
+            for _ in range(reps):
+                g.replay()
+            end.record(stream)
+        end.synchronize()
+        return start.elapsed_time(end) * 1e3 / reps
+
+    adj_bytes = 20                      # depth 4 B + cotangent 12 B in, gradient 4 B out
+    fwd_bytes = 17                      # depth 4 B in, normal 12 B + code 1 B out
+    nrm = torch.empty((n, H, W, 3), device=dev)
+    msk = torch.empty((n, H, W), dtype=torch.uint8, device=dev)
+    us_adj = timed_graph(lambda st: bn.normals_vjp_stack(depth, intr, grads, grad_depth=gd,
+                                                         stream=st, **kw))
+    us_fwd = timed_graph(lambda st: bn.estimate_normals_stack(depth, intr, normals=nrm, mask=msk,
+                                                              want_stats=False, stream=st, **kw))
+
+    def per_frame(st):
         for k, s in enumerate(scs):
             bn.normals_vjp(depth[k], s.fx, s.fy, s.cx, s.cy, grads[k], grad_depth=gd[k],
                            stream=st, **kw)
 
-    with torch.cuda.stream(stream):
-        adjoints(stream)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=stream):
-        adjoints(torch.cuda.current_stream())
-    for _ in range(3):
-        g.replay()
-    torch.cuda.synchronize()
-    reps = 50
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        start.record(stream)
-        for _ in range(reps):
-            g.replay()
-        end.record(stream)
-    end.synchronize()
-    us_frame = start.elapsed_time(end) * 1e3 / (reps * len(scs))
-    px = 480 * 640
-    adj_bytes = 20                      # depth 4 B + cotangent 12 B in, gradient 4 B out
-    achieved = adj_bytes * px / (us_frame * 1e-6) / 1e9
+    us_adj_frames = timed_graph(per_frame)
+
+    def rl(bpp, us):
+        a = bpp * n * px / (us * 1e-6) / 1e9
+        return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": a / HBM_PEAK_GBS, "bytes_per_pixel": bpp}
 
     def step():
-        loss = 0.0
-        for k, s in enumerate(scs):
-            d = depth[k].clone().requires_grad_(True)
-            n, m = bn.normals_with_grad(d, s.fx, s.fy, s.cx, s.cy, **kw)
-            l = bn.cosine_loss(n, targets[k][0], m, targets[k][1])
-            l.backward()
-            loss = loss + float(l.detach())
-        return loss
+        x = depth.clone().requires_grad_(True)
+        nn_, mm = bn.normals_with_grad_stack(x, intr, **kw)
+        loss = bn.cosine_loss(nn_, t_n, mm, t_m)
+        loss.backward()
+        return loss.detach()
 
     step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    nstep = 5
+    nstep = 20
     for _ in range(nstep):
-        step()
+        last = step()
+    float(last)
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1e3 / nstep
-    return {"workload": "16 x 640x480 (seeds 2000..2015): adjoint kernel per frame (graph replay); "
-                        "full step = forward + cosine loss vs the noise-free depth's normals + "
-                        "backward, eager",
-            "adjoint_us_per_frame": us_frame, "adjoint_mpix_s": px / us_frame,
-            "adjoint_roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                                 "bytes_per_pixel": adj_bytes},
-            "step_ms": ms_step, "step_mpix_s": 16 * px / (ms_step * 1e3)}
+    log(f"stack of 16: adjoint {us_adj:.1f} us, forward {us_fwd:.1f} us, 16 single-frame "
+        f"adjoints {us_adj_frames:.1f} us; step {ms_step:.3f} ms")
+    return {"workload": "16 x 640x480 (seeds 2000..2015) as one stack [16, 480, 640] with "
+                        "per-frame intrinsics; kernels graph-replayed; full step = stacked "
+                        "forward + cosine loss vs the noise-free depth's normals + stacked "
+                        "backward, eager, one host synchronisation per step",
+            "adjoint_us_per_stack": us_adj, "adjoint_us_per_frame": us_adj / n,
+            "adjoint_mpix_s": n * px / us_adj, "adjoint_roofline": rl(adj_bytes, us_adj),
+            "forward_us_per_stack": us_fwd, "forward_mpix_s": n * px / us_fwd,
+            "forward_roofline": rl(fwd_bytes, us_fwd),
+            "adjoint_single_frame_launches_us": us_adj_frames,
+            "step_ms": ms_step, "step_mpix_s": n * px / (ms_step * 1e3)}
 
 
 def run_serve(args, torch, bn, scenes, capacity_mpix_s):

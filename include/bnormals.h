@@ -131,6 +131,7 @@ extern "C" {
 /* limits */
 #define BN_MAX_ALPHA 8
 #define BN_MAX_SCALES 8
+#define BN_MAX_STACK 64
 #define BN_MAX_WIDTH 65536
 #define BN_MAX_PIXELS (1LL << 28)
 
@@ -222,6 +223,40 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width,
 int bn_normals_vjp(const float *depth, int32_t height, int32_t width, int64_t depth_stride,
                    float fx, float fy, float cx, float cy, const bn_params *params,
                    const float *grad_normals, float *grad_depth, void *stream);
+
+/*
+ * Stacks: n frames of one size in one launch, each with its own intrinsics
+ * (a training or evaluation batch).  Frame k is what bn_estimate_normals /
+ * bn_normals_vjp compute for it, bit for bit.
+ *   depth        frame k at depth + k * depth_frame_stride (elements), rows
+ *                of depth_stride elements; depth_frame_stride >=
+ *                height * depth_stride
+ *   intrinsics   host array of n bn_intrinsics, read during the call
+ *   normals      [n][height][width][3] out;  mask [n][height][width] out
+ *   stats        [n] bn_frame_stats (each zeroed before first use;
+ *                nullable), counts added or (BN_FLAG_COUNTS_OVERWRITE)
+ *                stored per frame
+ *   grad_normals [n][height][width][3];  grad_depth [n][height][width] out
+ * 1 <= n <= BN_MAX_STACK (n = 0, height 0 or width 0: nothing to do).
+ * params->variant: 0 (vector tiles when the layout allows them, which
+ * needs depth_frame_stride % 4 == 0 besides the single-frame rules), 1
+ * ("scalar") or 2 ("vec4") for the forward; 0 for the adjoint.
+ * Errors as for the single-frame calls; BN_ERR_UNSUPPORTED for n >
+ * BN_MAX_STACK.  Nothing is allocated; the arguments travel in the launch.
+ */
+typedef struct bn_intrinsics {
+    float fx, fy, cx, cy;
+} bn_intrinsics;
+
+int bn_estimate_normals_stack(const float *depth, int32_t n, int32_t height, int32_t width,
+                              int64_t depth_stride, int64_t depth_frame_stride,
+                              const bn_intrinsics *intrinsics, const bn_params *params,
+                              float *normals, uint8_t *mask, bn_frame_stats *stats,
+                              void *stream);
+int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t height, int32_t width,
+                         int64_t depth_stride, int64_t depth_frame_stride,
+                         const bn_intrinsics *intrinsics, const bn_params *params,
+                         const float *grad_normals, float *grad_depth, void *stream);
 
 /*
  * Batches: many frames of any mix of sizes, one launch.

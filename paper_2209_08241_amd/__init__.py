@@ -68,6 +68,14 @@ class Frame(ctypes.Structure):
                 ("stats", ctypes.c_void_p)]
 
 
+class Intrinsics(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+MAX_STACK = 64
+
+
 _lib = None
 
 
@@ -96,6 +104,14 @@ def lib() -> ctypes.CDLL:
         L.bn_normals_vjp.restype = ctypes.c_int
         L.bn_version.argtypes = []
         L.bn_version.restype = ctypes.c_int
+        L.bn_estimate_normals_stack.argtypes = [vp, i32, i32, i32, i64, i64,
+                                                ctypes.POINTER(Intrinsics),
+                                                ctypes.POINTER(Params), vp, vp, vp, vp]
+        L.bn_estimate_normals_stack.restype = ctypes.c_int
+        L.bn_normals_vjp_stack.argtypes = [vp, i32, i32, i32, i64, i64,
+                                           ctypes.POINTER(Intrinsics), ctypes.POINTER(Params),
+                                           vp, vp, vp]
+        L.bn_normals_vjp_stack.restype = ctypes.c_int
         _bind_batch(L)
         _bind_eval(L)
         _lib = L
@@ -234,6 +250,76 @@ def estimate_normals(depth, fx: float, fy: float, cx: float, cy: float, alpha: i
         ctypes.c_void_p(_stream_handle(stream)))
     if rc != BN_OK:
         raise BnError(rc, "bn_estimate_normals")
+    return normals, mask, stats
+
+
+def _check_stack(depth):
+    import torch
+    if not isinstance(depth, torch.Tensor) or not depth.is_cuda:
+        raise TypeError("depth must be a CUDA (HIP) torch tensor")
+    if depth.dtype != torch.float32 or depth.dim() != 3:
+        raise TypeError("a stack's depth must be a 3-D float32 tensor [n, H, W]")
+    if depth.numel() > 0 and depth.shape[2] > 1 and depth.stride(2) != 1:
+        raise ValueError("depth rows must be contiguous (stride(2) == 1)")
+
+
+def _intrinsics_array(intrinsics, n: int):
+    """bn_intrinsics[n] from one (fx, fy, cx, cy) for every frame or from a
+    sequence of n of them."""
+    vals = list(intrinsics)
+    if len(vals) == 4 and all(isinstance(v, (int, float)) for v in vals):
+        vals = [tuple(vals)] * n
+    if len(vals) != n:
+        raise ValueError(f"{len(vals)} intrinsics for {n} frames")
+    return (Intrinsics * max(n, 1))(*[Intrinsics(*map(float, v)) for v in vals])
+
+
+def _stack_strides(depth):
+    n, H, W = depth.shape
+    row = depth.stride(1) if H > 0 else W
+    frame = depth.stride(0) if n > 1 else H * row
+    return row, frame
+
+
+def estimate_normals_stack(depth, intrinsics, alpha: int = 2, mode="rel", tau: float = 4.0, *,
+                           variant: int = 0, method="four_pair", scales: int = 0,
+                           overwrite_counts: bool = False, normals=None, mask=None, stats=None,
+                           want_stats: bool = True, stream=None):
+    """n frames of one size in one launch (bn_estimate_normals_stack).
+
+    `depth` is [n, H, W] float32 on the device; `intrinsics` one (fx, fy, cx,
+    cy) for all frames or n of them.  Returns normals [n, H, W, 3], mask
+    [n, H, W] and stats [n, STATS_WORDS] (or None); frame k equals
+    estimate_normals on depth[k] bit for bit."""
+    import torch
+    _check_stack(depth)
+    n, H, W = depth.shape
+    dev = depth.device
+    arr = _intrinsics_array(intrinsics, n)
+    if normals is None:
+        normals = torch.empty((n, H, W, 3), dtype=torch.float32, device=dev)
+    if mask is None:
+        mask = torch.empty((n, H, W), dtype=torch.uint8, device=dev)
+    if stats is None and want_stats:
+        stats = new_stats(n, device=dev)
+    if not (normals.is_contiguous() and normals.shape == (n, H, W, 3)
+            and normals.dtype == torch.float32):
+        raise ValueError("normals must be a contiguous float32 [n, H, W, 3] tensor")
+    if not (mask.is_contiguous() and mask.shape == (n, H, W) and mask.dtype == torch.uint8):
+        raise ValueError("mask must be a contiguous uint8 [n, H, W] tensor")
+    if stats is not None and (stats.shape != (n, STATS_WORDS) or stats.dtype != torch.int32
+                              or not stats.is_contiguous() or stats.data_ptr() % 128):
+        raise ValueError("stats must be a contiguous, 128-byte aligned int32 tensor "
+                         f"[n, {STATS_WORDS}]")
+    p = make_params(alpha, mode, tau, variant, method, scales, overwrite_counts)
+    row, frame = _stack_strides(depth)
+    rc = lib().bn_estimate_normals_stack(
+        ctypes.c_void_p(depth.data_ptr()), n, H, W, row, frame, arr, ctypes.byref(p),
+        ctypes.c_void_p(normals.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
+        ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
+        ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_estimate_normals_stack")
     return normals, mask, stats
 
 
@@ -416,6 +502,34 @@ def normals_vjp(depth, fx, fy, cx, cy, grad_normals, alpha: int = 2, mode="rel",
     return grad_depth
 
 
+def normals_vjp_stack(depth, intrinsics, grad_normals, alpha: int = 2, mode="rel",
+                      tau: float = 4.0, grad_depth=None, stream=None):
+    """The adjoint of estimate_normals_stack (bn_normals_vjp_stack): grad
+    [n, H, W] from the cotangent [n, H, W, 3], every frame in one launch."""
+    import torch
+    _check_stack(depth)
+    n, H, W = depth.shape
+    g = grad_normals
+    if not (g.is_cuda and g.dtype == torch.float32 and g.shape == (n, H, W, 3)):
+        raise ValueError("grad_normals must be a float32 [n, H, W, 3] device tensor")
+    g = g.contiguous()
+    if grad_depth is None:
+        grad_depth = torch.empty((n, H, W), dtype=torch.float32, device=depth.device)
+    if not (grad_depth.is_contiguous() and grad_depth.shape == (n, H, W)
+            and grad_depth.dtype == torch.float32):
+        raise ValueError("grad_depth must be a contiguous float32 [n, H, W] tensor")
+    arr = _intrinsics_array(intrinsics, n)
+    p = make_params(alpha, mode, tau, 0)
+    row, frame = _stack_strides(depth)
+    rc = lib().bn_normals_vjp_stack(ctypes.c_void_p(depth.data_ptr()), n, H, W, row, frame, arr,
+                                    ctypes.byref(p), ctypes.c_void_p(g.data_ptr()),
+                                    ctypes.c_void_p(grad_depth.data_ptr()),
+                                    ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_normals_vjp_stack")
+    return grad_depth
+
+
 def _normals_function():
     import torch
 
@@ -440,27 +554,63 @@ def _normals_function():
                 gd = normals_vjp(depth, fx, fy, cx, cy, grad_n.float(), alpha, mode, tau)
             return gd, None, None, None, None, None, None, None
 
-    return NormalsFunction
+    class StackFunction(torch.autograd.Function):
+        """The same over a stack [n, H, W]: one launch each way."""
+
+        @staticmethod
+        def forward(ctx, depth, intrinsics, alpha, mode, tau):
+            n, m, _ = estimate_normals_stack(depth, intrinsics, alpha, mode, tau,
+                                             want_stats=False)
+            ctx.save_for_backward(depth)
+            ctx.args = (intrinsics, alpha, mode, tau)
+            ctx.mark_non_differentiable(m)
+            return n, m
+
+        @staticmethod
+        def backward(ctx, grad_n, grad_m):
+            (depth,) = ctx.saved_tensors
+            intrinsics, alpha, mode, tau = ctx.args
+            gd = None
+            if ctx.needs_input_grad[0]:
+                gd = normals_vjp_stack(depth, intrinsics, grad_n.float(), alpha, mode, tau)
+            return gd, None, None, None, None
+
+    return NormalsFunction, StackFunction
 
 
 _NormalsFunction = None
+_StackFunction = None
 
 
 def normals_with_grad(depth, fx, fy, cx, cy, alpha: int = 2, mode="rel", tau: float = 4.0):
     """Differentiable estimate_normals: returns (normals, mask); gradients
     flow to `depth` through bn_normals_vjp."""
-    global _NormalsFunction
+    global _NormalsFunction, _StackFunction
     if _NormalsFunction is None:
-        _NormalsFunction = _normals_function()
+        _NormalsFunction, _StackFunction = _normals_function()
     return _NormalsFunction.apply(depth, float(fx), float(fy), float(cx), float(cy), int(alpha),
                                   mode, float(tau))
 
 
+def normals_with_grad_stack(depth, intrinsics, alpha: int = 2, mode="rel", tau: float = 4.0):
+    """Differentiable estimate_normals_stack over depth [n, H, W]: returns
+    (normals, mask); gradients flow through bn_normals_vjp_stack."""
+    global _NormalsFunction, _StackFunction
+    if _StackFunction is None:
+        _NormalsFunction, _StackFunction = _normals_function()
+    n = depth.shape[0]
+    arr = _intrinsics_array(intrinsics, n)
+    key = tuple((c.fx, c.fy, c.cx, c.cy) for c in arr[:n])
+    return _StackFunction.apply(depth, key, int(alpha), mode, float(tau))
+
+
 def cosine_loss(normals, target, mask, target_mask):
-    """mean over pixels valid in both of (1 - normals . target)."""
+    """mean over pixels valid in both of (1 - normals . target); any leading
+    shape (one frame or a stack).  No host synchronisation."""
+    import torch
     U = (mask == VALID) & (target_mask == VALID)
     cos = (normals * target).sum(-1)
-    return (1.0 - cos)[U].sum() / U.sum().clamp(min=1)
+    return torch.where(U, 1.0 - cos, torch.zeros_like(cos)).sum() / U.sum().clamp(min=1)
 
 
 # ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbnormals.so")
 
-SOURCES = ["bn_kernels.hip", "bn_batch.hip", "bn_adjoint.hip", "bn_autotune.hip", "bn_serve.hip", "bn_eval.hip", "bn_probe.hip", "bn_capi.hip"]
+SOURCES = ["bn_kernels.hip", "bn_batch.hip", "bn_adjoint.hip", "bn_autotune.hip", "bn_serve.hip", "bn_eval.hip", "bn_probe.hip", "bn_stack.hip", "bn_capi.hip"]
 ARCH = os.environ.get("BN_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -25,17 +25,36 @@
 
 namespace bn {
 
+// One TX x TY tile of the gradient of one frame.
 template <int A, int TX, int TY>
-__global__ __launch_bounds__(kBlock) void k_vjp(FrameArgs f, const float *__restrict__ gn,
-                                                float *__restrict__ gd, uint32_t tiles_x) {
+__device__ __forceinline__ void vjp_tile(const FrameArgs &f, const float *__restrict__ gn,
+                                         float *__restrict__ gd, uint32_t tile,
+                                         uint32_t tiles_x) {
     constexpr int kAdjTX = TX, kAdjTY = TY;
     constexpr int DX = kAdjTX + 4 * A, DY = kAdjTY + 4 * A;  // depth tile
     constexpr int GX = kAdjTX + 2 * A, GY = kAdjTY + 2 * A;  // evaluated pixels
     __shared__ float s_d[DY * DX];
     __shared__ float s_g[4][GY * GX];  // tap gradients: to d2, d3, d4, d5
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    constexpr int NE = (GY * GX + kBlock - 1) / kBlock;  // evaluated pixels per thread
     const int x0 = (int)(tile % tiles_x) * kAdjTX;
     const int y0 = (int)(tile / tiles_x) * kAdjTY;
+    // The cotangents of this thread's pixels are loaded first, all at once:
+    // a load behind each pixel's code would expose one memory latency per
+    // pixel.  (Masked pixels' cotangents are read and then ignored.)
+    float cg[NE][3];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        const int k = (int)threadIdx.x + i * kBlock;
+        const int X = x0 - A + k % GX;
+        const int Y = y0 - A + k / GX;
+        cg[i][0] = cg[i][1] = cg[i][2] = 0.f;
+        if (k < GY * GX && X >= 0 && X < f.W && Y >= 0 && Y < f.H) {
+            const float *g = gn + 3 * ((int64_t)Y * f.W + X);
+            cg[i][0] = g[0];
+            cg[i][1] = g[1];
+            cg[i][2] = g[2];
+        }
+    }
     for (int k = threadIdx.x; k < DY * DX; k += kBlock) {
         const int X = x0 - 2 * A + k % DX;
         const int Y = y0 - 2 * A + k / DX;
@@ -44,7 +63,10 @@ __global__ __launch_bounds__(kBlock) void k_vjp(FrameArgs f, const float *__rest
         s_d[k] = v;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < GY * GX; k += kBlock) {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        const int k = (int)threadIdx.x + i * kBlock;
+        if (k >= GY * GX) break;
         const int c = k % GX, r = k / GX;
         const int X = x0 - A + c;
         const int Y = y0 - A + r;
@@ -61,10 +83,9 @@ __global__ __launch_bounds__(kBlock) void k_vjp(FrameArgs f, const float *__rest
             const float yc = (float)Y - f.cy;
             const PixelTerms t = eval_terms(inside, d1, d2, d3, d4, d5, xc, yc, f);
             if (t.code == BN_VALID) {
-                const float *g = gn + 3 * ((int64_t)Y * f.W + X);
                 const float inv = __builtin_amdgcn_rsqf(t.q);
                 const float nx = t.mx * inv, ny = t.my * inv, nz = -(t.mz * inv);
-                const float gx = g[0], gy = g[1], gz = g[2];
+                const float gx = cg[i][0], gy = cg[i][1], gz = cg[i][2];
                 const float dot = (nx * gx + ny * gy) + nz * gz;
                 const float ox = (gx - dot * nx) * inv;
                 const float oy = (gy - dot * ny) * inv;
@@ -98,7 +119,25 @@ __global__ __launch_bounds__(kBlock) void k_vjp(FrameArgs f, const float *__rest
     }
 }
 
+template <int A, int TX, int TY>
+__global__ __launch_bounds__(kBlock) void k_vjp(FrameArgs f, const float *__restrict__ gn,
+                                                float *__restrict__ gd, uint32_t tiles_x) {
+    vjp_tile<A, TX, TY>(f, gn, gd, xcd_tile(blockIdx.x, gridDim.x), tiles_x);
+}
+
+// A stack: workgroup b takes tile b % T of frame b / T.
+template <int A, int TX, int TY>
+__global__ __launch_bounds__(kBlock) void k_vjp_stack(const StackArgs s) {
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t k = b / s.tiles_per_frame;
+    const uint32_t tile = b - k * s.tiles_per_frame;
+    const int64_t npix = (int64_t)s.f.npix;
+    vjp_tile<A, TX, TY>(stack_frame(s, k), s.gn + (int64_t)k * npix * 3, s.gd + (int64_t)k * npix,
+                        tile, s.tiles_x);
+}
+
 typedef void (*VjpFn)(FrameArgs, const float *, float *, uint32_t);
+typedef void (*VjpStackFn)(const StackArgs);
 
 template <int TX, int TY>
 static VjpFn vjp_kernel_t(int a) {
@@ -111,6 +150,21 @@ static VjpFn vjp_kernel_t(int a) {
         case 6: return k_vjp<6, TX, TY>;
         case 7: return k_vjp<7, TX, TY>;
         case 8: return k_vjp<8, TX, TY>;
+    }
+    return nullptr;
+}
+
+template <int TX, int TY>
+static VjpStackFn vjp_stack_kernel_t(int a) {
+    switch (a) {
+        case 1: return k_vjp_stack<1, TX, TY>;
+        case 2: return k_vjp_stack<2, TX, TY>;
+        case 3: return k_vjp_stack<3, TX, TY>;
+        case 4: return k_vjp_stack<4, TX, TY>;
+        case 5: return k_vjp_stack<5, TX, TY>;
+        case 6: return k_vjp_stack<6, TX, TY>;
+        case 7: return k_vjp_stack<7, TX, TY>;
+        case 8: return k_vjp_stack<8, TX, TY>;
     }
     return nullptr;
 }
@@ -145,5 +199,38 @@ extern "C" int bn_normals_vjp(const float *depth, int32_t height, int32_t width,
     const uint32_t ty = ((uint32_t)height + TY - 1) / TY;
     hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(kBlock), 0, (hipStream_t)stream, f, grad_normals,
                        grad_depth, tx);
+    return hipGetLastError() == hipSuccess ? BN_OK : BN_ERR_DEVICE;
+}
+
+extern "C" int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t height, int32_t width,
+                                    int64_t depth_stride, int64_t depth_frame_stride,
+                                    const bn_intrinsics *intrinsics, const bn_params *params,
+                                    const float *grad_normals, float *grad_depth, void *stream) {
+    int rc = check_params_args(params);
+    if (rc != BN_OK) return rc;
+    if (params->variant != VAR_AUTO || params->method != BN_METHOD_FOUR_PAIR)
+        return BN_ERR_UNSUPPORTED;
+    StackArgs s;
+    // the gradients stand in for the forward's outputs in the checks
+    rc = stack_args(s, depth, n, height, width, depth_stride, depth_frame_stride, intrinsics,
+                    params, const_cast<float *>(grad_normals),
+                    reinterpret_cast<uint8_t *>(grad_depth), nullptr, 1);
+    if (rc == BN_OK && s.n > 0 && (uintptr_t)grad_depth % 4) rc = BN_ERR_INVALID_ARG;
+    if (rc != BN_OK || s.n == 0) return rc;
+    s.f.normals = nullptr;  // the gradients travel in gn / gd
+    s.f.mask = nullptr;
+    // each frame is small when the stack as a whole would not fill the chip
+    // with the larger tiles
+    const bool small = (int64_t)height * width * n < (1 << 20);
+    const uint32_t TX = small ? 32u : 64u, TY = small ? 8u : 16u;
+    VjpStackFn fn = small ? vjp_stack_kernel_t<32, 8>(params->alpha)
+                          : vjp_stack_kernel_t<64, 16>(params->alpha);
+    if (!fn) return BN_ERR_UNSUPPORTED;
+    s.gn = grad_normals;
+    s.gd = grad_depth;
+    s.tiles_x = ((uint32_t)width + TX - 1) / TX;
+    s.tiles_per_frame = s.tiles_x * (((uint32_t)height + TY - 1) / TY);
+    const uint64_t grid = (uint64_t)s.tiles_per_frame * s.n;
+    hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kBlock), 0, (hipStream_t)stream, s);
     return hipGetLastError() == hipSuccess ? BN_OK : BN_ERR_DEVICE;
 }

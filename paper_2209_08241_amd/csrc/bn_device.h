@@ -43,6 +43,44 @@ struct FrameArgs {
     double inv_gpr;   // 1.0 / gpr
 };
 
+// A stack of frames of one size in one launch: the first frame's arguments,
+// the distance between frames' depth, and what differs per frame (the
+// intrinsics and the ABS threshold that depends on them).  Outputs of frame
+// k are frame k of dense [n][H][W][3] / [n][H][W] / [n] arrays.  Passed by
+// value: the whole structure sits in the kernel-argument segment.
+struct StackFrame {
+    float fx, fy, cx, cy, hconst;
+};
+
+struct StackArgs {
+    FrameArgs f;
+    int64_t depth_fstride;     // elements from one frame's depth to the next
+    uint32_t n;                // frames
+    uint32_t tiles_per_frame;  // workgroups per frame
+    uint32_t vec;              // 1: vector tiles
+    uint32_t tiles_x;          // adjoint: tiles per row
+    const float *gn;           // adjoint: cotangent [n][H][W][3]
+    float *gd;                 // adjoint: gradient [n][H][W]
+    StackFrame fr[BN_MAX_STACK];
+};
+
+// Arguments of frame k of a stack.
+__device__ __forceinline__ FrameArgs stack_frame(const StackArgs &s, uint32_t k) {
+    FrameArgs f = s.f;
+    const StackFrame &p = s.fr[k];
+    f.fx = p.fx;
+    f.fy = p.fy;
+    f.cx = p.cx;
+    f.cy = p.cy;
+    f.hconst = p.hconst;
+    const int64_t npix = (int64_t)f.npix;
+    f.depth += (int64_t)k * s.depth_fstride;
+    if (f.normals) f.normals += (int64_t)k * npix * 3;
+    if (f.mask) f.mask += (int64_t)k * npix;
+    if (f.stats) f.stats += k;
+    return f;
+}
+
 // Methods (bn_params.method).
 constexpr int kFourPair = BN_METHOD_FOUR_PAIR;
 constexpr int kPairRemoval = BN_METHOD_PAIR_REMOVAL;

@@ -42,6 +42,13 @@ void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int
                      float fx, float fy, float cx, float cy, const bn_params *p, float *normals,
                      uint8_t *mask, bn_frame_stats *stats, int px_per_item);
 
+// Checked arguments of a stack of n frames (bn_stack.hip); s.n == 0 when
+// there is nothing to do.  normals / mask stand for the outputs in the
+// checks (the adjoint passes its gradients).
+int stack_args(StackArgs &s, const float *depth, int32_t n, int32_t H, int32_t W,
+               int64_t stride, int64_t fstride, const bn_intrinsics *intr, const bn_params *p,
+               float *normals, uint8_t *mask, bn_frame_stats *stats, int px_per_item);
+
 // Autotuning table (bn_autotune.hip): 0 when nothing is recorded.
 int tuned_plain_variant(int method, int alpha, uint64_t pixels);
 int tuned_batch_blocks_per_cu(int method, int alpha, uint64_t pixels);

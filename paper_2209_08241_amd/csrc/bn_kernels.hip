@@ -42,23 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
     const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
     uint32_t cv = 0, cb = 0;
     if (G == 1) {
-        // one tile: the counts are known before the stores, so the count
-        // atomic goes out first and its round trip overlaps the stores
-        Vec4Out o;
-        vec4_eval_method<A, M>(f, blk, o);
-        CountTicket tk;
-        bool have = false;
-        if (f.stats) {
-            vec4_count(o, cv, cb);
-            uint32_t v, b;
-            block_sum(cv, cb, v, b);
-            if (threadIdx.x == 0) {
-                tk = count_issue(f.stats, blk, gridDim.x, v, b, f.npix, f.overwrite);
-                have = true;
-            }
-        }
-        vec4_write(f, blk, lds, o);
-        if (have) count_finish(tk);
+        vec4_tile_counted<A, M>(f, blk, blk, gridDim.x, lds);
         return;
     }
 #pragma unroll

@@ -355,4 +355,28 @@ __device__ __forceinline__ void run_tile(const FrameArgs &f, bool vec, uint32_t 
     }
 }
 
+// One vector tile with its counts, as part `part` of `nparts` of the frame.
+// The counts are known before the stores, so the count atomic goes out first
+// and its round trip overlaps the stores.
+template <int A, int M>
+__device__ __forceinline__ void vec4_tile_counted(const FrameArgs &f, uint32_t tile,
+                                                  uint32_t part, uint32_t nparts, TileLds &lds) {
+    Vec4Out o;
+    vec4_eval_method<A, M>(f, tile, o);
+    CountTicket tk;
+    bool have = false;
+    if (f.stats) {
+        uint32_t cv = 0, cb = 0;
+        vec4_count(o, cv, cb);
+        uint32_t v, b;
+        block_sum(cv, cb, v, b);
+        if (threadIdx.x == 0) {
+            tk = count_issue(f.stats, part, nparts, v, b, f.npix, f.overwrite);
+            have = true;
+        }
+    }
+    vec4_write(f, tile, lds, o);
+    if (have) count_finish(tk);
+}
+
 }  // namespace bn

@@ -168,3 +168,44 @@ def test_alignment_checked_before_launch():
                                    0) == bn.BN_ERR_INVALID_ARG
     assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, p, 0x20000, 0x30000,
                                    0x40040) == bn.BN_ERR_INVALID_ARG
+
+
+def test_stack_argument_errors():
+    """Rejected before any launch (the addresses are never dereferenced)."""
+    L = bn.lib()
+    p = bn.make_params()
+    good = (bn.Intrinsics * 3)(*[bn.Intrinsics(500.0, 500.0, 3.5, 3.5)] * 3)
+    bad = (bn.Intrinsics * 3)(bn.Intrinsics(500.0, 500.0, 3.5, 3.5),
+                              bn.Intrinsics(500.0, -1.0, 3.5, 3.5),
+                              bn.Intrinsics(500.0, 500.0, 3.5, 3.5))
+    big = (bn.Intrinsics * 65)(*[bn.Intrinsics(500.0, 500.0, 3.5, 3.5)] * 65)
+    D, N, M = 0x10000, 0x20000, 0x30000
+
+    def fwd(n, H, W, row, frame, intr, params=p, stats=0, normals=N):
+        return L.bn_estimate_normals_stack(D, n, H, W, row, frame, intr, ctypes.byref(params),
+                                           normals, M, stats, None)
+
+    def adj(n, H, W, row, frame, intr, params=p, gd=M):
+        return L.bn_normals_vjp_stack(D, n, H, W, row, frame, intr, ctypes.byref(params), N,
+                                      gd, None)
+
+    for f in (fwd, adj):
+        assert f(-1, 8, 8, 8, 64, good) == bn.BN_ERR_INVALID_ARG
+        assert f(65, 8, 8, 8, 64, big) == bn.BN_ERR_UNSUPPORTED
+        assert f(3, 8, 8, 8, 64, None) == bn.BN_ERR_INVALID_ARG
+        assert f(3, 8, 8, 8, 64, bad) == bn.BN_ERR_INVALID_ARG       # frame 1's fy
+        assert f(3, 8, 8, 8, 63, good) == bn.BN_ERR_INVALID_ARG      # frames overlap
+        assert f(3, 8, 8, 7, 64, good) == bn.BN_ERR_INVALID_ARG      # row stride < width
+        assert f(3, 8, 8, 8, -64, good) == bn.BN_ERR_INVALID_ARG
+        assert f(3, 8, 65537, 65537, 1 << 20, good) == bn.BN_ERR_UNSUPPORTED
+        assert f(3, 8, 8, 8, 64, good, params=bn.make_params(alpha=0)) == bn.BN_ERR_INVALID_ARG
+        assert f(0, 8, 8, 8, 64, None) == bn.BN_OK                   # nothing to do
+        assert f(3, 0, 8, 8, 0, good) == bn.BN_OK
+    assert fwd(3, 8, 8, 8, 64, good, stats=0x40001) == bn.BN_ERR_INVALID_ARG
+    assert fwd(3, 8, 8, 8, 64, good, params=bn.make_params(variant=3)) == bn.BN_ERR_UNSUPPORTED
+    assert fwd(3, 8, 8, 8, 64, good, params=bn.make_params(variant=17)) == bn.BN_ERR_INVALID_ARG
+    assert fwd(3, 8, 8, 8, 64, good, normals=0x20002) == bn.BN_ERR_INVALID_ARG
+    assert adj(3, 8, 8, 8, 64, good, params=bn.make_params(method="pair_removal")) == \
+        bn.BN_ERR_UNSUPPORTED
+    assert adj(3, 8, 8, 8, 64, good, params=bn.make_params(variant=1)) == bn.BN_ERR_UNSUPPORTED
+    assert adj(3, 8, 8, 8, 64, good, gd=0x30002) == bn.BN_ERR_INVALID_ARG

@@ -1,0 +1,185 @@
+"""Stacks (bn_estimate_normals_stack / bn_normals_vjp_stack): n frames of one
+size with their own intrinsics in one launch.  Every frame must equal the
+single-frame call on it bit for bit (normals, codes, counts, gradients), and
+one frame of each stack is checked against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2209_08241_amd as bn
+from gpu_util import assert_parity, log
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _stack(frames, pad_row=0, pad_frame=0):
+    """[n, H, W] device view of the frames, rows padded by pad_row elements
+    and frames by pad_frame rows (the padding holds NaN)."""
+    import torch
+    n = len(frames)
+    H, W = frames[0].depth.shape
+    buf = torch.full((n, H + pad_frame, W + pad_row), float("nan"), dtype=torch.float32,
+                     device="cuda")
+    for k, s in enumerate(frames):
+        buf[k, :H, :W] = torch.from_numpy(np.ascontiguousarray(s.depth)).cuda()
+    return buf[:, :H, :W]
+
+
+def _frames(n, H, W, seed, fx_step=37.0):
+    """n scenes of one size, each with different intrinsics."""
+    out = []
+    for k in range(n):
+        s = scenes.sized_frame(H, W, seed=seed + k)
+        s.fx = s.fx + fx_step * k
+        s.fy = s.fy + 0.5 * fx_step * k
+        s.cx = s.cx + 1.25 * k
+        s.cy = s.cy - 0.75 * k
+        out.append(s)
+    return out
+
+
+def _single(d, s, alpha, mode, tau, method="four_pair", scales=0, variant=0):
+    import torch
+    n, m, st = bn.estimate_normals(d, s.fx, s.fy, s.cx, s.cy, alpha, mode, tau, method=method,
+                                   scales=scales, variant=variant)
+    torch.cuda.synchronize()
+    return n, m, st
+
+
+def _assert_stack_equals_single(frames, depth, alpha, mode, tau, method="four_pair", scales=0,
+                                variant=0):
+    import torch
+    intr = [(s.fx, s.fy, s.cx, s.cy) for s in frames]
+    N, M, ST = bn.estimate_normals_stack(depth, intr, alpha, mode, tau, method=method,
+                                         scales=scales, variant=variant)
+    torch.cuda.synchronize()
+    for k, s in enumerate(frames):
+        n, m, st = _single(depth[k], s, alpha, mode, tau, method, scales)
+        assert torch.equal(N[k].view(torch.int32), n.view(torch.int32)), f"frame {k} normals"
+        assert torch.equal(M[k], m), f"frame {k} codes"
+        assert torch.equal(ST[k, :3], st[:3]), f"frame {k} counts"
+    return N, M, ST
+
+
+@pytest.mark.parametrize("method,K", [("four_pair", 0), ("pair_removal", 0), ("multiscale", 2)])
+@pytest.mark.parametrize("mode,tau", [("rel", 4.0), ("abs", 2e-3), ("none", 1.0)])
+def test_stack_equals_single_frames(method, K, mode, tau):
+    """Five 640x480 frames with five different intrinsics (the ABS threshold
+    differs per frame)."""
+    log(f"stack 5x480x640 {method} {mode}")
+    frames = _frames(5, 480, 640, seed=500)
+    d = _stack(frames)
+    N, M, ST = _assert_stack_equals_single(frames, d, 2, mode, tau, method, K)
+    s = frames[3]
+    ref = oracle.variant_f32(s.depth, s.fx, s.fy, s.cx, s.cy, 2, mode, tau, method=method,
+                             scales=K)
+    assert_parity(ref, N[3].cpu().numpy(), M[3].cpu().numpy(), ST[3].cpu().numpy(),
+                  what=f"stack frame 3 {method} {mode}")
+
+
+@pytest.mark.parametrize("H,W,pad_row,pad_frame", [(97, 131, 0, 0), (64, 96, 3, 0),
+                                                   (64, 96, 0, 1), (33, 64, 4, 2),
+                                                   (1, 8, 0, 0), (2, 2, 0, 0)])
+@pytest.mark.parametrize("alpha", [1, 3])
+def test_stack_layouts(H, W, pad_row, pad_frame, alpha):
+    """Ragged widths, padded rows and padded frames (scalar tiles where the
+    layout rules out the vector ones)."""
+    frames = _frames(3, H, W, seed=H * 31 + W, fx_step=11.0)
+    d = _stack(frames, pad_row, pad_frame)
+    _assert_stack_equals_single(frames, d, alpha, "rel", 1.2)
+
+
+def test_stack_forced_variants_and_limits():
+    import torch
+    frames = _frames(4, 120, 160, seed=77)
+    d = _stack(frames)
+    a = _assert_stack_equals_single(frames, d, 2, "rel", 4.0, variant=1)
+    b = _assert_stack_equals_single(frames, d, 2, "rel", 4.0, variant=2)
+    assert torch.equal(a[0].view(torch.int32), b[0].view(torch.int32))
+    assert torch.equal(a[1], b[1])
+    odd = _stack(_frames(2, 10, 13, seed=3))
+    with pytest.raises(bn.BnError) as e:
+        bn.estimate_normals_stack(odd, (500.0, 500.0, 6.0, 4.5), variant=2)
+    assert e.value.status == bn.BN_ERR_UNSUPPORTED
+    for v, want in ((3, bn.BN_ERR_UNSUPPORTED), (9, bn.BN_ERR_INVALID_ARG)):
+        with pytest.raises(bn.BnError) as e:
+            bn.estimate_normals_stack(d, [(s.fx, s.fy, s.cx, s.cy) for s in frames], variant=v)
+        assert e.value.status == want
+    torch.cuda.synchronize()
+
+
+def test_stack_of_64_and_of_1():
+    """The largest stack (64 small frames) and a stack of one."""
+    frames = _frames(64, 48, 64, seed=900, fx_step=3.0)
+    _assert_stack_equals_single(frames, _stack(frames), 2, "rel", 4.0)
+    one = _frames(1, 480, 640, seed=901)
+    _assert_stack_equals_single(one, _stack(one), 2, "rel", 4.0)
+
+
+def test_stack_counts_add_or_overwrite():
+    import torch
+    frames = _frames(3, 240, 320, seed=60)
+    d = _stack(frames)
+    intr = [(s.fx, s.fy, s.cx, s.cy) for s in frames]
+    want = []
+    for k, s in enumerate(frames):
+        want.append(_single(d[k], s, 2, "rel", 4.0)[2][:3].tolist())
+    st = bn.new_stats(3, device="cuda")
+    for _ in range(2):
+        bn.estimate_normals_stack(d, intr, stats=st)
+    torch.cuda.synchronize()
+    assert st[:, :3].tolist() == [[2 * c for c in w] for w in want]
+    bn.estimate_normals_stack(d, intr, stats=st, overwrite_counts=True)
+    torch.cuda.synchronize()
+    assert st[:, :3].tolist() == want
+    assert not st[:, 4:].any()   # the reduction's workspace is clear again
+
+
+@pytest.mark.parametrize("alpha", [1, 2, 3])
+@pytest.mark.parametrize("n,H,W,pad_row", [(4, 480, 640, 0), (3, 97, 131, 2), (16, 48, 64, 0)])
+def test_vjp_stack_equals_single_frames(alpha, n, H, W, pad_row):
+    """Gradients of every frame equal the single-frame adjoint bit for bit
+    (whatever tile shape either call takes), and one frame the oracle."""
+    import torch
+    log(f"vjp stack {n}x{H}x{W} alpha={alpha}")
+    frames = _frames(n, H, W, seed=1000 + n, fx_step=13.0)
+    d = _stack(frames, pad_row)
+    intr = [(s.fx, s.fy, s.cx, s.cy) for s in frames]
+    gen = torch.Generator(device="cuda").manual_seed(alpha * 100 + n)
+    g = torch.randn((n, H, W, 3), device="cuda", generator=gen)
+    G = bn.normals_vjp_stack(d, intr, g, alpha)
+    torch.cuda.synchronize()
+    for k, s in enumerate(frames):
+        gk = bn.normals_vjp(d[k], s.fx, s.fy, s.cx, s.cy, g[k].contiguous(), alpha)
+        torch.cuda.synchronize()
+        assert torch.equal(G[k].view(torch.int32), gk.view(torch.int32)), f"frame {k}"
+    k = n // 2
+    s = frames[k]
+    codes = oracle.normals_f32(s.depth, s.fx, s.fy, s.cx, s.cy, alpha, "rel", 4.0)["mask"]
+    ref = oracle.normals_vjp_f64(s.depth, s.fx, s.fy, s.cx, s.cy, alpha, codes,
+                                 g[k].cpu().numpy().astype(np.float64))
+    got = G[k].cpu().numpy().astype(np.float64)
+    tol = 1e-4 * np.abs(ref).max() + 1e-3 * np.abs(ref)
+    assert np.all(np.abs(got - ref) <= tol)
+
+
+def test_autograd_stack_equals_per_frame():
+    """One backward through the stack equals the per-frame backwards."""
+    import torch
+    frames = _frames(4, 240, 320, seed=1200)
+    d = _stack(frames).contiguous()
+    intr = [(s.fx, s.fy, s.cx, s.cy) for s in frames]
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    t = torch.nn.functional.normalize(torch.randn((4, 240, 320, 3), device="cuda",
+                                                  generator=gen), dim=-1)
+    x = d.clone().requires_grad_(True)
+    n, m = bn.normals_with_grad_stack(x, intr)
+    (n * t).sum().backward()
+    for k, s in enumerate(frames):
+        xk = d[k].clone().requires_grad_(True)
+        nk, mk = bn.normals_with_grad(xk, s.fx, s.fy, s.cx, s.cy)
+        (nk * t[k]).sum().backward()
+        assert torch.equal(n[k].detach().view(torch.int32), nk.detach().view(torch.int32))
+        assert torch.equal(m[k], mk)
+        assert torch.equal(x.grad[k].view(torch.int32), xk.grad.view(torch.int32)), f"frame {k}"
