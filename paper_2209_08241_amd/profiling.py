@@ -3,8 +3,12 @@
     python -m paper_2209_08241_amd.profiling trace  <kernel_stats.csv> <out.md> [--cmd "..."]
     python -m paper_2209_08241_amd.profiling traffic --fetch <dir> --write <dir> \
         --kernel <substring> --pixels <per launch> --workload <name> --out <json> [--cmd "..."]
+    python -m paper_2209_08241_amd.profiling launches [--reps N]
+    python -m paper_2209_08241_amd.profiling valu <counter_collection dir> <out.md> [--cmd "..."]
 
 `trace` turns a `--kernel-trace --stats` kernel_stats.csv into a short table.
+`launches` runs each kernel of interest N times on synthetic frames (a
+program for counter passes); `valu` tabulates a pass of VALU counters over it.
 `traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs into HBM bytes
 per launch of one kernel.  Each counter is calibrated against the copy
 kernel that bench.py runs first (`--calibration-mib`): its bytes read and
@@ -122,6 +126,76 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: 
     return rec
 
 
+def launches(reps: int = 20) -> None:
+    """Each kernel of interest `reps` times: the three methods on one
+    1920x1080 frame, then the stacked forward and adjoint on 16 x 640x480."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import torch
+    import paper_2209_08241_amd as bn
+    from synth import scenes
+    s = scenes.frame_1920x1080(seed=2)
+    d = torch.from_numpy(s.depth).cuda()
+    for method, alpha, K in (("four_pair", 2, 0), ("pair_removal", 2, 0), ("multiscale", 1, 3)):
+        for _ in range(reps):
+            bn.estimate_normals(d, *s.intrinsics, alpha, method=method, scales=K)
+    scs = [scenes.frame_640x480(seed=2000 + i) for i in range(16)]
+    intr = [x.intrinsics for x in scs]
+    st = torch.from_numpy(np.stack([x.depth for x in scs])).cuda()
+    g = torch.randn((16, 480, 640, 3), device="cuda")
+    for _ in range(reps):
+        bn.estimate_normals_stack(st, intr, want_stats=False)
+        bn.normals_vjp_stack(st, intr, g)
+    torch.cuda.synchronize()
+    print("launches done", flush=True)
+
+
+_VALU_WHAT = {
+    "bn::k_vec4<2, 1, 0>": "four-pair, 1920x1080, alpha 2",
+    "bn::k_vec4<2, 1, 1>": "pair removal, 1920x1080, alpha 2",
+    "bn::k_vec4<1, 1, 2>": "multi-scale K=3, 1920x1080, alpha 1",
+    "bn::k_stack<2, 0>": "four-pair stack, 16 x 640x480",
+    "bn::k_vjp_stack<2, 64, 16>": "adjoint stack, 16 x 640x480 (per output)",
+}
+
+
+def valu_summary(pmc_dir: str, out_md: str, cmd: str = "") -> str:
+    rows = _csv_rows(pmc_dir, "*counter_collection.csv")
+    agg: dict = {}
+    for r in rows:
+        k = r.get("Kernel_Name") or r.get("Kernel-Name")
+        if "bn::" not in k:
+            continue
+        short = k.split("(")[0].replace("void ", "")
+        c = agg.setdefault(short, {})
+        name = r.get("Counter_Name") or r.get("Counter-Name")
+        c.setdefault(name, []).append(float(r.get("Counter_Value") or r.get("Counter-Value")))
+        c.setdefault("_dur", []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = ["# VALU counters of the main kernels (rocprofv3 --pmc)", ""]
+    if cmd:
+        lines += ["Command:", "", "```", cmd, "```", ""]
+    lines += ["Medians over each kernel's dispatches.  Instruction counts are per wavefront "
+              "(64 lanes, 4 pixels or outputs per lane, so per pixel = per wavefront / 4); "
+              "VALUBusy is rocprofv3's derived share of the kernel's time in which the vector "
+              "ALUs issue; durations are under the profiler.", "",
+              "| kernel | workload | wavefronts | VALU / wavefront | VALU / pixel | "
+              "SALU / wavefront | LDS / wavefront | VMEM reads / wavefront | VALUBusy | "
+              "VALUUtilization | duration (profiled) |",
+              "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for k, c in agg.items():
+        med = {n: statistics.median(v) for n, v in c.items()}
+        w = med.get("SQ_WAVES", 1.0) or 1.0
+        lines.append(f"| `{k}` | {_VALU_WHAT.get(k, '')} | {w:.0f} | "
+                     f"{med['SQ_INSTS_VALU'] / w:.0f} | {med['SQ_INSTS_VALU'] / w / 4:.0f} | "
+                     f"{med['SQ_INSTS_SALU'] / w:.0f} | {med['SQ_INSTS_LDS'] / w:.1f} | "
+                     f"{med['SQ_INSTS_VMEM_RD'] / w:.1f} | {med['VALUBusy']:.1f}% | "
+                     f"{med['VALUUtilization']:.1f}% | {med['_dur']:.1f} us |")
+    text = "\n".join(lines) + "\n"
+    with open(out_md, "w") as fh:
+        fh.write(text)
+    return text
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -140,8 +214,18 @@ def main():
     p.add_argument("--calib-kernel", default="copyBuffer")
     p.add_argument("--calib-count", type=int, default=4)
     p.add_argument("--cmd", default="")
+    ln = sub.add_parser("launches")
+    ln.add_argument("--reps", type=int, default=20)
+    v = sub.add_parser("valu")
+    v.add_argument("pmc_dir")
+    v.add_argument("out_md")
+    v.add_argument("--cmd", default="")
     a = ap.parse_args()
-    if a.what == "trace":
+    if a.what == "launches":
+        launches(a.reps)
+    elif a.what == "valu":
+        print(valu_summary(a.pmc_dir, a.out_md, a.cmd))
+    elif a.what == "trace":
         print(trace_summary(a.stats_csv, a.out_md, a.cmd))
     else:
         print(json.dumps(traffic(a.fetch, a.write, a.kernel, a.pixels, a.workload, a.out,
