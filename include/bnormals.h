@@ -132,6 +132,7 @@ extern "C" {
 #define BN_MAX_ALPHA 8
 #define BN_MAX_SCALES 8
 #define BN_MAX_STACK 64
+#define BN_SMALL_BATCH 16
 #define BN_MAX_WIDTH 65536
 #define BN_MAX_PIXELS (1LL << 28)
 
@@ -264,7 +265,11 @@ int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t height, int32_t 
  * A plan holds the frame descriptors in device memory and a HIP graph of two
  * kernel nodes: one processes every tile of every frame (one workgroup per
  * tile of 1024 pixels by default), the other sums each frame's counts;
- * running the plan replays the graph.  Frames are described by bn_frame (device
+ * running the plan replays the graph.  A list of at most BN_SMALL_BATCH
+ * frames instead carries its descriptors in the kernel arguments and reduces
+ * its counts inside the one kernel (on a zeroed work area of the plan): an
+ * update of such a list uploads nothing, and a run is a single kernel, its
+ * own one-node graph.  Frames are described by bn_frame (device
  * pointers, owned by the caller, which must stay valid while the plan runs).
  * All frames share `params` (alpha, mode, tau, method, scales, flags;
  * params->variant must be 0);
@@ -276,7 +281,8 @@ int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t height, int32_t 
  * bn_batch_plan_create: validates every frame (the checks of
  *   bn_estimate_normals), allocates the plan (device descriptor table of
  *   n_frames entries, a tile-to-frame table, a table of 4 counts per tile,
- *   two pinned staging copies) and instantiates the graph.
+ *   two pinned staging copies, BN_SMALL_BATCH count work areas) and
+ *   instantiates the graph.
  *   Capacity = n_frames.  Returns BN_OK, BN_ERR_INVALID_ARG,
  *   BN_ERR_UNSUPPORTED, BN_ERR_OOM or BN_ERR_DEVICE; *out_plan is NULL on
  *   error.  Synchronous.
@@ -289,11 +295,12 @@ int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t height, int32_t 
  *   must have finished).
  * bn_batch_run: one replay of the plan's graph over the current frame list
  *   on `stream`.
- * bn_batch_launch: the same two kernels, with the same output, as two
- *   ordinary launches on `stream` instead of a graph replay.  Costs less host
- *   time per call (a graph replay costs tens of microseconds), so it suits
- *   small, latency-bound batches such as a server's; a long batch is the
- *   same either way.
+ * bn_batch_launch: the same kernels (two, or one for a small list), with
+ *   the same output, as ordinary launches on `stream` instead of a graph
+ *   replay.  Costs less host time per call (a graph replay costs tens of
+ *   microseconds), so it suits small, latency-bound batches such as a
+ *   server's; a long batch is the same either way.  Runs of one plan must
+ *   not overlap (they share its descriptors and count work areas).
  * bn_batch_plan_info: pixels, tiles and workgroups of the current list.
  * bn_batch_plan_destroy: frees the plan; the caller makes sure no run of it
  *   is still in flight.

@@ -391,7 +391,8 @@ class BatchPlan:
             raise BnError(rc, "bn_batch_run")
 
     def launch(self, stream=None) -> None:
-        """The same kernels as two plain launches (less host time per call)."""
+        """The same kernels as plain launches (one kernel for lists of at most
+        16 frames, two otherwise): less host time per call than a replay."""
         rc = lib().bn_batch_launch(self._h, ctypes.c_void_p(_stream_handle(stream)))
         if rc != BN_OK:
             raise BnError(rc, "bn_batch_launch")

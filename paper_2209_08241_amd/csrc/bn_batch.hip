@@ -18,6 +18,12 @@
 // The frame descriptors live in device memory, so a plan's graph is
 // replayed as is when the frames change (the grid of the flat shape is
 // updated in place).
+//
+// Lists of at most kSmallFrames frames take another route: their
+// descriptors travel in the kernel arguments (an update uploads nothing)
+// and the counts go through the plain kernels' in-launch reduction on a
+// zeroed scratch work area of the plan, so a launch is a single kernel.
+// This is the latency path of a server's small batches.
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -125,8 +131,66 @@ __global__ __launch_bounds__(kBlock) void k_batch_counts(const BatchFrame *__res
     }
 }
 
+constexpr int kSmallFrames = BN_SMALL_BATCH;
+
+struct SmallBatch {
+    uint32_t nframes;
+    uint32_t ntiles;
+    uint32_t vec_bits;                       // bit k: frame k takes vector tiles
+    uint32_t pad;
+    uint32_t tile_begin[kSmallFrames];       // unused entries: UINT32_MAX
+    uint32_t tile_count[kSmallFrames];
+    FrameArgs f[kSmallFrames];               // work = the plan's scratch for frame k
+};
+
+// Workgroup b takes tile b of the concatenated sequence; its frame is the
+// last one whose first tile is <= b (a scan of uniform scalar values).
+template <int A, int M>
+__global__ __launch_bounds__(kBlock) void k_batch_small(const SmallBatch s) {
+    __shared__ TileLds lds;
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= s.ntiles) return;
+    uint32_t k = 0;
+#pragma unroll
+    for (uint32_t j = 1; j < (uint32_t)kSmallFrames; ++j)
+        if (s.tile_begin[j] <= b) k = j;
+    const FrameArgs f = s.f[k];
+    const uint32_t tile = b - s.tile_begin[k];
+    const uint32_t nparts = s.tile_count[k];
+    if ((s.vec_bits >> k) & 1u) {
+        vec4_tile_counted<A, M>(f, tile, tile, nparts, lds);
+        return;
+    }
+    uint32_t cv = 0, cb = 0;
+    run_tile<A, M>(f, false, tile, lds, cv, cb);
+    if (f.stats) block_counts(f, tile, nparts, cv, cb);
+}
+
 typedef void (*BatchKernelFn)(const BatchFrame *, const uint32_t *, uint32_t *, uint32_t,
                               uint32_t, uint32_t);
+typedef void (*SmallKernelFn)(const SmallBatch);
+
+template <int M>
+static SmallKernelFn small_kernel_m(int alpha) {
+    switch (alpha) {
+        case 1: return k_batch_small<1, M>;
+        case 2: return k_batch_small<2, M>;
+        case 3: return k_batch_small<3, M>;
+        case 4: return k_batch_small<4, M>;
+        case 5: return k_batch_small<5, M>;
+        case 6: return k_batch_small<6, M>;
+        case 7: return k_batch_small<7, M>;
+        case 8: return k_batch_small<8, M>;
+    }
+    return nullptr;
+}
+
+static SmallKernelFn small_kernel(int method, int alpha) {
+    if (method == kFourPair) return small_kernel_m<kFourPair>(alpha);
+    if (method == kPairRemoval) return small_kernel_m<kPairRemoval>(alpha);
+    if (method == kMultiScale) return small_kernel_m<kMultiScale>(alpha);
+    return nullptr;
+}
 
 template <int M>
 static BatchKernelFn batch_kernel_m(int alpha) {
@@ -179,6 +243,16 @@ struct bn_batch_plan {
     bool graph_stale = false;              // node parameters behind the frame list
     uint64_t total_tiles = 0;
     uint64_t total_pixels = 0;
+    // small lists (at most kSmallFrames frames): descriptors in the kernel
+    // arguments, counts reduced on `work`, one kernel (graph sgraph/sexec)
+    bool small_mode = false;
+    SmallBatch small{};
+    SmallKernelFn small_fn = nullptr;
+    bn_frame_stats *work = nullptr;        // kSmallFrames work areas, zero between launches
+    hipGraph_t sgraph = nullptr;
+    hipGraphExec_t sexec = nullptr;
+    hipGraphNode_t snode = nullptr;
+    bool small_stale = false;
 };
 
 namespace {
@@ -257,6 +331,31 @@ int build_table(const bn_frame *frames, int32_t n, const bn_params *p, int32_t c
     hdr->pad = 0;
     if (hdr->chunk > 4096) return BN_ERR_UNSUPPORTED;  // parts stay below 2^22 pixels
     return BN_OK;
+}
+
+// The kernel-argument image of a small list (already validated).
+void build_small(bn_batch_plan *pl, const bn_frame *frames, int32_t n) {
+    SmallBatch &sb = pl->small;
+    std::memset(&sb, 0, sizeof(sb));
+    uint32_t tiles = 0;
+    for (int k = 0; k < kSmallFrames; ++k) sb.tile_begin[k] = UINT32_MAX;
+    for (int32_t k = 0; k < n; ++k) {
+        const bn_frame &s = frames[k];
+        const bool vec = frame_vec(s, &pl->params);
+        uint32_t nt = 0;
+        if (s.height > 0 && s.width > 0) {
+            fill_frame_args(sb.f[k], s.depth, s.height, s.width, s.depth_stride, s.fx, s.fy, s.cx,
+                            s.cy, &pl->params, s.normals, s.mask, s.stats, vec ? 4 : 1);
+            sb.f[k].work = pl->work + k;
+            nt = (sb.f[k].nitems + kBlock - 1) / kBlock;
+        }
+        sb.tile_begin[k] = tiles;
+        sb.tile_count[k] = nt;
+        if (vec) sb.vec_bits |= 1u << k;
+        tiles += nt;
+    }
+    sb.nframes = (uint32_t)n;
+    sb.ntiles = tiles;
 }
 
 hipKernelNodeParams kernel_params(void *func, uint32_t grid, void **args) {
@@ -353,8 +452,30 @@ void free_plan(bn_batch_plan *pl) {
     }
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    if (pl->sexec) (void)hipGraphExecDestroy(pl->sexec);
+    if (pl->sgraph) (void)hipGraphDestroy(pl->sgraph);
+    if (pl->work) (void)hipFree(pl->work);
     free_buffers(pl);
     delete pl;
+}
+
+// The small list's graph: one kernel node, created on first use, its
+// arguments rewritten after each update.
+int refresh_small_node(bn_batch_plan *pl) {
+    void *args[1] = {(void *)&pl->small};
+    hipKernelNodeParams kp =
+        kernel_params(reinterpret_cast<void *>(pl->small_fn), pl->small.ntiles, args);
+    pl->small_stale = false;
+    if (!pl->sexec) {
+        if (hipGraphCreate(&pl->sgraph, 0) != hipSuccess ||
+            hipGraphAddKernelNode(&pl->snode, pl->sgraph, nullptr, 0, &kp) != hipSuccess ||
+            hipGraphInstantiate(&pl->sexec, pl->sgraph, nullptr, nullptr, 0) != hipSuccess)
+            return BN_ERR_DEVICE;
+        return BN_OK;
+    }
+    return hipGraphExecKernelNodeSetParams(pl->sexec, pl->snode, &kp) == hipSuccess
+               ? BN_OK
+               : BN_ERR_DEVICE;
 }
 
 // Write `frames` into the staging copy `k` and send it to the device on
@@ -374,6 +495,10 @@ int upload(bn_batch_plan *pl, const bn_frame *frames, int32_t n, int k, hipStrea
 
 }  // namespace
 
+namespace bn {
+bool batch_plan_uploads(const bn_batch_plan *plan) { return plan && !plan->small_mode; }
+}  // namespace bn
+
 extern "C" {
 
 int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn_params *params,
@@ -385,7 +510,8 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
     if (rc != BN_OK) return rc;
     if (params->variant != VAR_AUTO) return BN_ERR_UNSUPPORTED;
     BatchKernelFn fn = batch_kernel(params->method, params->alpha);
-    if (!fn) return BN_ERR_UNSUPPORTED;
+    SmallKernelFn sfn = small_kernel(params->method, params->alpha);
+    if (!fn || !sfn) return BN_ERR_UNSUPPORTED;
     uint64_t tiles = 0, pixels = 0;
     rc = count_frames(frames_host, n_frames, params, &tiles, &pixels);
     if (rc != BN_OK) return rc;
@@ -395,6 +521,7 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
     pl->params = *params;
     pl->capacity = n_frames;
     pl->fn = fn;
+    pl->small_fn = sfn;
     if (hipGetDevice(&pl->device) != hipSuccess) {
         free_plan(pl);
         return BN_ERR_DEVICE;
@@ -426,11 +553,23 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
         hipMemcpy(pl->dbuf, pl->staging[0], pl->buf_bytes, hipMemcpyHostToDevice) != hipSuccess)
         rc = BN_ERR_DEVICE;
     if (rc == BN_OK) rc = refresh_node(pl);
+    // the small lists' count work areas, zero from here on
+    if (rc == BN_OK &&
+        (hipMalloc(&pl->work, sizeof(bn_frame_stats) * kSmallFrames) != hipSuccess ||
+         hipMemsetAsync(pl->work, 0, sizeof(bn_frame_stats) * kSmallFrames, nullptr) !=
+             hipSuccess ||
+         hipStreamSynchronize(nullptr) != hipSuccess))
+        rc = BN_ERR_DEVICE;
     if (rc != BN_OK) {
         free_plan(pl);
         return rc;
     }
     pl->next = 1;  // staging[0] holds the current table
+    if (n_frames <= kSmallFrames) {
+        build_small(pl, frames_host, n_frames);
+        pl->small_mode = true;
+        pl->small_stale = true;
+    }
     *out_plan = pl;
     return BN_OK;
 }
@@ -443,6 +582,16 @@ int bn_batch_plan_update(bn_batch_plan *plan, const bn_frame *frames_host, int32
     uint64_t tiles = 0, pixels = 0;
     int rc = count_frames(frames_host, n_frames, &plan->params, &tiles, &pixels);
     if (rc != BN_OK) return rc;
+    if (n_frames <= kSmallFrames) {
+        // descriptors in the kernel arguments: nothing to upload
+        build_small(plan, frames_host, n_frames);
+        plan->small_mode = true;
+        plan->small_stale = true;
+        plan->total_tiles = tiles;
+        plan->total_pixels = pixels;
+        return BN_OK;
+    }
+    plan->small_mode = false;
     const uint32_t grid = grid_for(tiles, plan->cus, plan->blocks_per_cu);
     if (tiles > 0 && (tiles + grid - 1) / grid > 4096) return BN_ERR_UNSUPPORTED;
     if (tiles > plan->tile_capacity) {
@@ -488,6 +637,15 @@ int bn_batch_plan_update(bn_batch_plan *plan, const bn_frame *frames_host, int32
 
 int bn_batch_run(bn_batch_plan *plan, void *stream) {
     if (!plan || !plan->exec) return BN_ERR_INVALID_ARG;
+    if (plan->small_mode) {
+        if (plan->small.ntiles == 0) return BN_OK;  // only empty frames
+        if (plan->small_stale) {
+            const int rc = refresh_small_node(plan);
+            if (rc != BN_OK) return rc;
+        }
+        return hipGraphLaunch(plan->sexec, (hipStream_t)stream) == hipSuccess ? BN_OK
+                                                                              : BN_ERR_DEVICE;
+    }
     if (plan->graph_stale) {
         const int rc = refresh_node(plan);
         if (rc != BN_OK) return rc;
@@ -498,6 +656,14 @@ int bn_batch_run(bn_batch_plan *plan, void *stream) {
 int bn_batch_launch(bn_batch_plan *plan, void *stream) {
     if (!plan || !plan->exec) return BN_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    if (plan->small_mode) {
+        if (plan->small.ntiles == 0) return BN_OK;  // only empty frames
+        void *args[1] = {(void *)&plan->small};
+        return hipLaunchKernel(reinterpret_cast<const void *>(plan->small_fn),
+                               dim3(plan->small.ntiles), dim3(kBlock), args, 0, s) == hipSuccess
+                   ? BN_OK
+                   : BN_ERR_DEVICE;
+    }
     BatchArgs a(plan);
     if (hipLaunchKernel(reinterpret_cast<const void *>(plan->fn), dim3(plan->grid),
                         dim3(kBlock), a.main, 0, s) != hipSuccess ||
@@ -512,7 +678,8 @@ int bn_batch_plan_info(const bn_batch_plan *plan, int64_t *n_pixels, int64_t *n_
     if (!plan) return BN_ERR_INVALID_ARG;
     if (n_pixels) *n_pixels = (int64_t)plan->total_pixels;
     if (n_tiles) *n_tiles = (int64_t)plan->total_tiles;
-    if (n_workgroups) *n_workgroups = (int32_t)plan->grid;
+    if (n_workgroups)
+        *n_workgroups = (int32_t)(plan->small_mode ? plan->small.ntiles : plan->grid);
     return BN_OK;
 }
 
@@ -538,6 +705,23 @@ int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_bloc
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return BN_ERR_DEVICE;
+    }
+    if (plan->small_mode) {
+        // one shape only (a workgroup per tile): time it, record nothing
+        int rc = bn_batch_run(plan, s);
+        (void)hipEventRecord(e0, s);
+        const int reps = 3;
+        for (int r = 0; r < reps && rc == BN_OK; ++r) rc = bn_batch_run(plan, s);
+        (void)hipEventRecord(e1, s);
+        if (rc == BN_OK && hipEventSynchronize(e1) != hipSuccess) rc = BN_ERR_DEVICE;
+        float ms = 0.f;
+        if (rc == BN_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != BN_OK) return rc;
+        if (best_blocks_per_cu) *best_blocks_per_cu = 0;
+        if (best_us) *best_us = 1000.f * ms / reps;
+        return BN_OK;
     }
     const uint32_t cands[] = {kFlat, 2, 4, 8};
     uint32_t best = 0;

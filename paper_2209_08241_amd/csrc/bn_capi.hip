@@ -129,6 +129,7 @@ void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int
     f.normals = normals;
     f.mask = mask;
     f.stats = stats;
+    f.work = stats;
     f.stride = stride;
     f.H = H;
     f.W = W;

@@ -26,7 +26,8 @@ struct FrameArgs {
     const float *depth;
     float *normals;
     uint8_t *mask;
-    bn_frame_stats *stats;
+    bn_frame_stats *stats;  // the counts' destination (nullable)
+    bn_frame_stats *work;   // the in-launch reduction's words (stats, or a scratch copy)
     int64_t stride;   // depth row stride, elements
     int32_t H, W;
     float fx, fy, cx, cy;
@@ -78,6 +79,7 @@ __device__ __forceinline__ FrameArgs stack_frame(const StackArgs &s, uint32_t k)
     if (f.normals) f.normals += (int64_t)k * npix * 3;
     if (f.mask) f.mask += (int64_t)k * npix;
     if (f.stats) f.stats += k;
+    if (f.work) f.work += k;
     return f;
 }
 
@@ -364,15 +366,16 @@ __device__ __forceinline__ uint32_t wave_count(bool pred) {
 // A frame's pixels are split into `nparts` parts (workgroups or tiles).  Each
 // part contributes its VALID and BOUNDARY counts with ONE relaxed 64-bit
 // atomic add on the word of slot (part % BN_STATS_SLOTS), each slot on its
-// own 128-byte line of the caller's bn_frame_stats so that the adds of
-// different slots proceed in parallel.  The word packs the counts and an
+// own 128-byte line of a bn_frame_stats used as the work area (the caller's,
+// or a zeroed scratch copy when the destination may hold anything) so that
+// the adds of different slots proceed in parallel.  The word packs the counts and an
 // arrival ticket, so the value the atomic returns holds every earlier
 // contribution: the last arrival of a slot (ticket = parts in the slot - 1)
 // knows the slot total without any fence or reload.  It clears the slot and
 // forwards the total the same way to the level-2 word; the last of those
-// adds the frame totals to the counters (INVALID = pixels - VALID - BOUNDARY)
-// and clears the level-2 word.  The workspace is therefore zero again after
-// every launch.
+// adds (or stores) the frame totals in the destination's counters (INVALID =
+// pixels - VALID - BOUNDARY) and clears the level-2 word.  The work area is
+// therefore zero again after every launch.
 //
 // Level 1 word: VALID [0,24) | BOUNDARY [24,48) | ticket [48,64)
 //   (a slot holds fewer than 2^24 pixels and 2^16 parts for frames of at
@@ -390,25 +393,27 @@ __device__ __forceinline__ unsigned long long *stats_word(bn_frame_stats *st, ui
 // half, so the caller can place other work (the output stores) in between
 // and hide the atomic's round trip behind it.
 struct CountTicket {
-    bn_frame_stats *st;
+    bn_frame_stats *work;
+    bn_frame_stats *out;
     unsigned long long *w1;
     unsigned long long mine1;
     unsigned long long old1;
     uint32_t ns, nparts, npix, overwrite;
 };
 
-__device__ __forceinline__ CountTicket count_issue(bn_frame_stats *st, uint32_t part,
-                                                   uint32_t nparts, uint32_t nvalid,
-                                                   uint32_t nboundary, uint32_t npix,
-                                                   uint32_t overwrite) {
+__device__ __forceinline__ CountTicket count_issue(bn_frame_stats *work, bn_frame_stats *out,
+                                                   uint32_t part, uint32_t nparts,
+                                                   uint32_t nvalid, uint32_t nboundary,
+                                                   uint32_t npix, uint32_t overwrite) {
     CountTicket k;
     k.overwrite = overwrite;
     const uint32_t s = part % BN_STATS_SLOTS;
-    k.st = st;
+    k.work = work;
+    k.out = out;
     k.ns = nparts / BN_STATS_SLOTS + (s < nparts % BN_STATS_SLOTS ? 1u : 0u);
     k.nparts = nparts;
     k.npix = npix;
-    k.w1 = stats_word(st, s);
+    k.w1 = stats_word(work, s);
     k.mine1 = (unsigned long long)nvalid | ((unsigned long long)nboundary << 24) | (1ull << 48);
     k.old1 = atomicAdd(k.w1, k.mine1);
     return k;
@@ -436,7 +441,7 @@ __device__ __forceinline__ void count_finish(const CountTicket &k) {
     const uint32_t bs = (uint32_t)((tot1 >> 24) & 0xffffffull);
     const uint32_t nactive =
         k.nparts < (uint32_t)BN_STATS_SLOTS ? k.nparts : (uint32_t)BN_STATS_SLOTS;
-    unsigned long long *w2 = stats_word(k.st, BN_STATS_SLOTS);
+    unsigned long long *w2 = stats_word(k.work, BN_STATS_SLOTS);
     const unsigned long long mine2 =
         (unsigned long long)vs | ((unsigned long long)bs << 29) | (1ull << 58);
     const unsigned long long old2 = atomicAdd(w2, mine2);
@@ -445,13 +450,14 @@ __device__ __forceinline__ void count_finish(const CountTicket &k) {
     atomicExch(w2, 0ull);
     const uint32_t vt = (uint32_t)(tot2 & ((1ull << 29) - 1));
     const uint32_t bt = (uint32_t)((tot2 >> 29) & ((1ull << 29) - 1));
-    put_counts(k.st, vt, bt, k.npix, k.overwrite);
+    put_counts(k.out, vt, bt, k.npix, k.overwrite);
 }
 
-__device__ __forceinline__ void reduce_counts(bn_frame_stats *st, uint32_t part, uint32_t nparts,
-                                              uint32_t nvalid, uint32_t nboundary,
-                                              uint32_t npix, uint32_t overwrite) {
-    count_finish(count_issue(st, part, nparts, nvalid, nboundary, npix, overwrite));
+__device__ __forceinline__ void reduce_counts(bn_frame_stats *work, bn_frame_stats *out,
+                                              uint32_t part, uint32_t nparts, uint32_t nvalid,
+                                              uint32_t nboundary, uint32_t npix,
+                                              uint32_t overwrite) {
+    count_finish(count_issue(work, out, part, nparts, nvalid, nboundary, npix, overwrite));
 }
 
 // Block-wide sum of wave-uniform counts (one workgroup barrier): the totals,
@@ -477,12 +483,11 @@ __device__ __forceinline__ void block_sum(uint32_t cv, uint32_t cb, uint32_t &v,
 }
 
 // Block-wide sum of wave-uniform counts; thread 0 then calls reduce_counts.
-__device__ __forceinline__ void block_counts(bn_frame_stats *st, uint32_t part, uint32_t nparts,
-                                             uint32_t cv, uint32_t cb, uint32_t npix,
-                                             uint32_t overwrite) {
+__device__ __forceinline__ void block_counts(const FrameArgs &f, uint32_t part, uint32_t nparts,
+                                             uint32_t cv, uint32_t cb) {
     uint32_t v, b;
     block_sum(cv, cb, v, b);
-    if (threadIdx.x == 0) reduce_counts(st, part, nparts, v, b, npix, overwrite);
+    if (threadIdx.x == 0) reduce_counts(f.work, f.stats, part, nparts, v, b, f.npix, f.overwrite);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b%8).

@@ -3,8 +3,8 @@
 // the pixels valid in both, and the local plane-fit normals that the paper
 // uses as ground truth on real depth maps (25 neighbours: a 5x5 window).
 //
-// These are off the estimator's hot path and run in FP64 (full rate on this
-// GPU's vector units), storing binary32 results.
+// These are off the estimator's hot path and run in FP64 (on this GPU's
+// vector units as fast as unpacked binary32), storing binary32 results.
 #include <cmath>
 
 #include "bn_internal.h"

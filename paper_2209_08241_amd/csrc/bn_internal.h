@@ -49,6 +49,11 @@ int stack_args(StackArgs &s, const float *depth, int32_t n, int32_t H, int32_t W
                int64_t stride, int64_t fstride, const bn_intrinsics *intr, const bn_params *p,
                float *normals, uint8_t *mask, bn_frame_stats *stats, int px_per_item);
 
+// True when the plan's current list went to the device through an upload
+// on the update's stream (false for small lists, whose descriptors travel in
+// the kernel arguments).
+bool batch_plan_uploads(const bn_batch_plan *plan);
+
 // Autotuning table (bn_autotune.hip): 0 when nothing is recorded.
 int tuned_plain_variant(int method, int alpha, uint64_t pixels);
 int tuned_batch_blocks_per_cu(int method, int alpha, uint64_t pixels);

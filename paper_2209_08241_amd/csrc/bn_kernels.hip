@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kBlock) void k_scalar(FrameArgs f) {
     const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
     uint32_t cv = 0, cb = 0;
     run_tile<A, M>(f, false, blk, lds, cv, cb);
-    if (f.stats) block_counts(f.stats, blk, gridDim.x, cv, cb, f.npix, f.overwrite);
+    if (f.stats) block_counts(f, blk, gridDim.x, cv, cb);
 }
 
 // Vector kernel: four consecutive pixels of a row per thread, G tiles of
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
         if (tile * kBlock >= f.nitems) break;  // uniform over the workgroup
         run_tile<A, M>(f, true, tile, lds, cv, cb);
     }
-    if (f.stats) block_counts(f.stats, blk, gridDim.x, cv, cb, f.npix, f.overwrite);
+    if (f.stats) block_counts(f, blk, gridDim.x, cv, cb);
 }
 
 // ---------------------------------------------------------------------------

@@ -4,9 +4,10 @@
 // outputs, plus its depth when it comes from host memory, plus its counts)
 // fits in the HBM budget; admission starts its host-to-device copy on a copy
 // stream, or makes it launchable at once when its depth is already in
-// device memory (the launch stores its counts, so nothing needs zeroing).  Whenever fewer than `max_batches_in_flight` launches are queued on
-// the GPU, every admitted request whose input is on the device (up to
-// `max_batch`) goes into one batch-plan launch on the compute stream.  So new
+// device memory (the launch stores its counts, so nothing needs zeroing).
+// Whenever fewer than `max_batches_in_flight` launches are queued on the GPU,
+// every admitted request whose input is on the device (up to `max_batch`)
+// goes into one batch-plan launch on the compute stream.  So new
 // requests are admitted and copied while earlier batches run, and each
 // launch takes whatever is ready: continuous batching.  A request's slot is
 // returned to the budget when the client releases the request.
@@ -225,11 +226,13 @@ class HipBackend : public Backend {
         }
         rc = bn_batch_plan_update(plan, fr.data(), (int32_t)fr.size(), upload_);
         if (rc != BN_OK) return rc;
-        hipEvent_t up = take_event();
-        if (!up || hipEventRecord(up, upload_) != hipSuccess ||
-            hipStreamWaitEvent(compute_, up, 0) != hipSuccess)
-            return BN_ERR_DEVICE;
-        uploads_.push_back(up);
+        if (batch_plan_uploads(plan)) {
+            hipEvent_t up = take_event();
+            if (!up || hipEventRecord(up, upload_) != hipSuccess ||
+                hipStreamWaitEvent(compute_, up, 0) != hipSuccess)
+                return BN_ERR_DEVICE;
+            uploads_.push_back(up);
+        }
         // plain launches: a graph replay costs more host time than the
         // kernels of a typical batch of requests take on the GPU
         rc = bn_batch_launch(plan, compute_);

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kBlock) void k_stack(const StackArgs s) {
     }
     uint32_t cv = 0, cb = 0;
     run_tile<A, M>(f, false, tile, lds, cv, cb);
-    if (f.stats) block_counts(f.stats, tile, s.tiles_per_frame, cv, cb, f.npix, f.overwrite);
+    if (f.stats) block_counts(f, tile, s.tiles_per_frame, cv, cb);
 }
 
 typedef void (*StackFn)(const StackArgs);

@@ -371,7 +371,7 @@ __device__ __forceinline__ void vec4_tile_counted(const FrameArgs &f, uint32_t t
         uint32_t v, b;
         block_sum(cv, cb, v, b);
         if (threadIdx.x == 0) {
-            tk = count_issue(f.stats, part, nparts, v, b, f.npix, f.overwrite);
+            tk = count_issue(f.work, f.stats, part, nparts, v, b, f.npix, f.overwrite);
             have = true;
         }
     }

@@ -203,3 +203,83 @@ def test_direct_launch_equals_graph_replay():
                 ref = oracle.normals_f32(s.depth, s.fx, s.fy, s.cx, s.cy, 2, "rel", 4.0)
                 assert_parity(ref, n.cpu().numpy(), m.cpu().numpy(), st.cpu().numpy(),
                               what=f"list {k} {s.depth.shape}")
+
+
+def _plain_outputs(fr, alpha, mode, tau, method="four_pair", scales=0):
+    import torch
+    n, m, st = bn.estimate_normals(fr.depth, fr.fx, fr.fy, fr.cx, fr.cy, alpha, mode, tau,
+                                   method=method, scales=scales)
+    torch.cuda.synchronize()
+    return n, m, st
+
+
+def _assert_equal_plain(frames, alpha, mode, tau, method="four_pair", scales=0, times=1):
+    import torch
+    for k, fr in enumerate(frames):
+        n, m, st = _plain_outputs(fr, alpha, mode, tau, method, scales)
+        assert torch.equal(fr.normals.view(torch.int32), n.view(torch.int32)), f"frame {k}"
+        assert torch.equal(fr.mask, m), f"frame {k}"
+        if fr.stats is not None:
+            assert fr.stats[:3].tolist() == [times * c for c in st[:3].tolist()], f"frame {k}"
+
+
+@pytest.mark.parametrize("method,alpha,K", [("four_pair", 2, 0), ("pair_removal", 1, 0),
+                                           ("multiscale", 2, 3), ("multiscale", 3, 3)])
+def test_small_lists(method, alpha, K):
+    """Lists of at most 16 frames carry their descriptors in the kernel
+    arguments and reduce their counts in the same kernel: outputs and counts
+    equal the plain launches, through the graph and through plain launches,
+    and repeated runs add the counts (the scratch work areas return to zero)."""
+    import torch
+    rng = np.random.default_rng(alpha * 10 + K)
+    sizes = [(97, 131), (240, 320), (0, 8), (33, 64), (480, 640), (5, 7)]
+    host = [scenes.sized_frame(H, W, seed=300 + k) if H > 0 else None
+            for k, (H, W) in enumerate(sizes)]
+    frames = []
+    for s, (H, W) in zip(host, sizes):
+        if s is None:
+            frames.append(bn.BatchFrame(torch.empty((0, W), device="cuda"), 100.0, 100.0,
+                                        3.5, 0.0))
+        else:
+            frames.append(bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy))
+    for n in (1, 4, len(frames)):
+        sub = frames[:n]
+        with bn.BatchPlan(sub, alpha, "rel", 4.0, method=method, scales=K) as plan:
+            for how in ("run", "launch"):
+                for f in sub:
+                    f.stats.zero_()
+                for _ in range(3):
+                    getattr(plan, how)()
+                torch.cuda.synchronize()
+                _assert_equal_plain(sub, alpha, "rel", 4.0, method, K, times=3)
+    log(f"small lists {method} alpha={alpha} K={K} ok (rng {rng.integers(9)})")
+
+
+def test_small_and_table_lists_through_one_plan():
+    """One plan alternates between lists above and below the small-list
+    limit; every list's outputs equal the plain launches, and a list of 16
+    frames with the overwrite flag stores its counts."""
+    import torch
+    pool = [scenes.sized_frame(H, W, seed=400 + k) for k, (H, W) in
+            enumerate([(120, 160), (97, 131), (240, 320), (64, 64)] * 6)]
+    frames = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in pool]
+    with bn.BatchPlan(frames, 2, "rel", 4.0, overwrite_counts=True) as plan:
+        for n, how in ((3, "launch"), (24, "run"), (16, "run"), (17, "launch"), (1, "run"),
+                       (24, "launch"), (2, "launch")):
+            sub = frames[:n]
+            plan.update(sub)
+            for f in sub:
+                f.normals.fill_(5.0)
+                f.mask.fill_(7)
+                f.stats.fill_(3)   # overwritten counts; garbage elsewhere is not read
+            getattr(plan, how)()
+            torch.cuda.synchronize()
+            info = plan.info()
+            assert info["tiles"] == sum(
+                (f.depth.shape[0] * (f.depth.shape[1] // 4 if f.depth.shape[1] % 4 == 0
+                                     else f.depth.shape[1]) + 255) // 256 for f in sub)
+            for k, f in enumerate(sub):
+                n_, m_, st_ = _plain_outputs(f, 2, "rel", 4.0)
+                assert torch.equal(f.normals.view(torch.int32), n_.view(torch.int32)), (n, k)
+                assert torch.equal(f.mask, m_), (n, k)
+                assert f.stats[:3].tolist() == st_[:3].tolist(), (n, k)
