@@ -625,7 +625,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-budget-gib", type=int, default=16)
-    ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--serve-max-batch", type=int, default=16,
+                    help="requests per launch (16 = the small-list limit: one kernel per launch)")
     ap.add_argument("--serve-in-flight", type=int, default=2)
     ap.add_argument("--quick", action="store_true",
                     help="headline numbers only (no methods, latency, copy or multi-core oracle)")

@@ -679,7 +679,7 @@ def _bind_server(L) -> None:
 class Server:
     """bn_server: continuous batching of mixed-size frames under an HBM budget."""
 
-    def __init__(self, budget_bytes: int, max_batch: int = 64, max_batches_in_flight: int = 2,
+    def __init__(self, budget_bytes: int, max_batch: int = 16, max_batches_in_flight: int = 2,
                  alpha: int = 2, mode="rel", tau: float = 4.0, backend: str = "hip",
                  fake_ns_per_pixel: float = 0.004, fake_launch_ns: float = 5000.0,
                  fake_copy_gbs: float = 25.0, *, method="four_pair", scales: int = 0):

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchFrame *__restrict__
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
     uint32_t fi = tile_frame[t];
-    while (t < tend && fi < nframes) {
+    while (fi < nframes) {
         const FrameArgs f = frames[fi].a;
         const uint32_t tb = frames[fi].tile_begin;
         const uint32_t nt = frames[fi].ntiles;
@@ -84,6 +84,9 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchFrame *__restrict__
             run_tile<A, M>(f, vec, t - tb, lds, cv, cb);
             if (f.stats && lane == 0) wave_counts[4 * (int64_t)t + wave] = cv | (cb << 16);
         }
+        // done (always so in the flat shape) before looking at the next
+        // frame's descriptor, which would hold the workgroup for one more load
+        if (t >= tend) break;
         do {
             ++fi;
         } while (fi < nframes && frames[fi].ntiles == 0);

@@ -48,11 +48,14 @@ def test_results_are_the_same_alone_and_in_the_mix(serve_frames):
     dev = [torch.from_numpy(s.depth).cuda() for s in serve_frames]
     host = [torch.from_numpy(s.depth).pin_memory() for s in serve_frames]
     refs = [alone(s, d) for s, d in zip(serve_frames, dev)]
-    with bn.Server(8 << 30, max_batch=16, max_batches_in_flight=2) as srv:
+    big = max(range(len(serve_frames)), key=lambda k: serve_frames[k].depth.size)
+    # one launch at a time, led by the largest frames: the requests submitted
+    # while those run are launched together
+    with bn.Server(8 << 30, max_batch=16, max_batches_in_flight=1) as srv:
         reqs = []
         rng = np.random.default_rng(1)
-        for i in range(40):
-            k = int(rng.integers(len(serve_frames)))
+        order = [big, big] + [int(rng.integers(len(serve_frames))) for _ in range(38)]
+        for i, k in enumerate(order):
             on_host = bool(i % 3 == 0)
             s = serve_frames[k]
             rid = srv.submit(host[k] if on_host else dev[k], s.fx, s.fy, s.cx, s.cy)
@@ -66,7 +69,24 @@ def test_results_are_the_same_alone_and_in_the_mix(serve_frames):
         st = srv.stats()
         log(f"mix: {st['batches']} launches, largest {st['max_batch_seen']} frames")
         assert st["completed"] == 40 and st["bytes_in_use"] == 0
-        assert st["batches"] < 40            # requests were batched together
+        assert st["max_batch_seen"] > 1      # some requests were launched together
+
+
+def test_burst_is_batched(serve_frames):
+    """Requests arriving together (a burst submitted from native code) are
+    launched in batches of up to max_batch."""
+    import torch
+    pool = [bn.BatchFrame(torch.from_numpy(s.depth).cuda(), s.fx, s.fy, s.cx, s.cy,
+                          want_stats=False) for s in serve_frames]
+    for max_batch in (16, 64):
+        with bn.Server(16 << 30, max_batch=max_batch, max_batches_in_flight=2) as srv:
+            r = srv.run_poisson(pool, rate_hz=1e12, n_requests=300, seed=3001)
+            st = srv.stats()
+            log(f"burst of 300, max_batch {max_batch}: {st['batches']} launches, largest "
+                f"{st['max_batch_seen']}, {r['pixels'] / r['wall_s'] / 1e6:.0f} Mpix/s")
+            assert st["completed"] == 300
+            assert st["batches"] < 300 // 4 and st["max_batch_seen"] > 4
+            assert st["max_batch_seen"] <= max_batch
 
 
 def test_budget_pressure_queues_but_completes(serve_frames):
