@@ -288,6 +288,21 @@ def run_plain(args, torch, bn, scenes):
                             "unit": "Mpix/s", "roofline": roofline(px, mms)})
             log(f"{name}: {methods[-1]['value']:.0f} Mpix/s")
         extra["methods"] = methods
+        # the small plain configuration: 640x480, a ring of 256 buffers
+        # (1.6 GB, beyond the last-level cache), one launch per frame
+        scs640 = [scenes.frame_640x480(seed=1 + i) for i in range(8)]
+        r640 = Ring(torch, bn, scs640, 256)
+        kw640 = dict(alpha=args.alpha, mode=args.mode, tau=args.tau)
+        parity_check(r640, kw640, args.alpha, args.mode, args.tau)
+        ms640, steps640, _, _ = r640.time(kw640, 2560, 256)
+        px640 = 640 * 480
+        extra["plain640"] = {"workload": "plain 640x480, one launch per frame, ring of 256 "
+                                         "buffers (8 distinct scenes, seeds 1..8)",
+                             "value": px640 / (ms640 * 1e-3) / 1e6, "unit": "Mpix/s",
+                             "us_per_frame": ms640 * 1e3, "steps": steps640,
+                             "roofline": roofline(px640, ms640)}
+        log(f"plain 640x480: {ms640 * 1e3:.2f} us per frame")
+        del r640
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the oracle for {args.cpu_seconds} s (one thread)")
@@ -702,7 +717,7 @@ def main():
             ach["batched_frac_of_pattern"] = (out["batched"]["roofline"]["achieved"]
                                               / ach["pattern_GBs"])
         line["achievable"] = ach
-    for k in ("batched", "serving", "differentiation", "methods", "hot_cache",
+    for k in ("batched", "serving", "differentiation", "methods", "hot_cache", "plain640",
               "single_launch_us", "cpu_oracle_all_cores"):
         if k in out:
             line[k] = out[k]

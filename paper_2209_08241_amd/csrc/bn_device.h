@@ -222,26 +222,30 @@ __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, floa
     const PairVec p1 = pair_vec(-(e4 * d3), d4 * e3, d4 * d3, xc, yc, f);
     const PairVec p2 = pair_vec(-(e4 * d5), -(d4 * e5), d4 * d5, xc, yc, f);
     const PairVec p3 = pair_vec(e2 * d5, -(d2 * e5), d2 * d5, xc, yc, f);
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    sx = sx + (p0.keep ? p0.mx : 0.0f);
-    sy = sy + (p0.keep ? p0.my : 0.0f);
-    sz = sz + (p0.keep ? p0.mz : 0.0f);
-    sx = sx + (p1.keep ? p1.mx : 0.0f);
-    sy = sy + (p1.keep ? p1.my : 0.0f);
-    sz = sz + (p1.keep ? p1.mz : 0.0f);
-    sx = sx + (p2.keep ? p2.mx : 0.0f);
-    sy = sy + (p2.keep ? p2.my : 0.0f);
-    sz = sz + (p2.keep ? p2.mz : 0.0f);
-    sx = sx + (p3.keep ? p3.mx : 0.0f);
-    sy = sy + (p3.keep ? p3.my : 0.0f);
-    sz = sz + (p3.keep ? p3.mz : 0.0f);
-    const float sx2 = sx * sx;
-    const float sy2 = sy * sy;
-    const float sz2 = sz * sz;
-    const float Qs = (sx2 + sy2) + sz2;
+    const bool all = (p0.keep & p1.keep & p2.keep & p3.keep) != 0u;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f, Qs = 0.0f;
+    // the sum of the passing pairs serves only pixels where some pair
+    // fails; most wavefronts have none and skip it (a uniform branch)
+    if (__any(!all)) {
+        sx = sx + (p0.keep ? p0.mx : 0.0f);
+        sy = sy + (p0.keep ? p0.my : 0.0f);
+        sz = sz + (p0.keep ? p0.mz : 0.0f);
+        sx = sx + (p1.keep ? p1.mx : 0.0f);
+        sy = sy + (p1.keep ? p1.my : 0.0f);
+        sz = sz + (p1.keep ? p1.mz : 0.0f);
+        sx = sx + (p2.keep ? p2.mx : 0.0f);
+        sy = sy + (p2.keep ? p2.my : 0.0f);
+        sz = sz + (p2.keep ? p2.mz : 0.0f);
+        sx = sx + (p3.keep ? p3.mx : 0.0f);
+        sy = sy + (p3.keep ? p3.my : 0.0f);
+        sz = sz + (p3.keep ? p3.mz : 0.0f);
+        const float sx2 = sx * sx;
+        const float sy2 = sy * sy;
+        const float sz2 = sz * sz;
+        Qs = (sx2 + sy2) + sz2;
+    }
     // all four pass: the four-pair closed form, in which d1 cancels exactly
     const PixelTerms t = eval_terms(inside, d1, d2, d3, d4, d5, xc, yc, f);
-    const bool all = (p0.keep & p1.keep & p2.keep & p3.keep) != 0u;
     sx = all ? t.mx : sx;
     sy = all ? t.my : sy;
     sz = all ? t.mz : sz;
