@@ -74,7 +74,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchFrame *__restrict__
     const uint32_t wave = threadIdx.x >> 6;
     uint32_t fi = tile_frame[t];
     while (fi < nframes) {
-        const FrameArgs f = frames[fi].a;
+        FrameArgs f = frames[fi].a;
+        frame_pointers_global(f, &frames[fi].a);
         const uint32_t tb = frames[fi].tile_begin;
         const uint32_t nt = frames[fi].ntiles;
         const bool vec = frames[fi].vec != 0;

@@ -6,6 +6,8 @@
 // reduction of the per-frame counts.
 #pragma once
 
+#include <cstddef>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -64,6 +66,33 @@ struct StackArgs {
     float *gd;                 // adjoint: gradient [n][H][W]
     StackFrame fr[BN_MAX_STACK];
 };
+
+// Frame pointers loaded from device memory (a batch's frame descriptors) are
+// generic to the compiler, which then emits FLAT accesses through them; FLAT
+// operations also count on the LDS counter, so every LDS wait of a tile
+// would wait for the tile's memory traffic too.  Reading the pointer fields
+// as global-address-space pointers lets the compiler use global
+// instructions.  (The layout is FrameArgs' first five fields.)
+#define BN_GLOBAL __attribute__((address_space(1)))
+struct FramePointersGlobal {
+    BN_GLOBAL const float *depth;
+    BN_GLOBAL float *normals;
+    BN_GLOBAL uint8_t *mask;
+    BN_GLOBAL bn_frame_stats *stats;
+    BN_GLOBAL bn_frame_stats *work;
+};
+
+static_assert(sizeof(FramePointersGlobal) == 40 && offsetof(FrameArgs, work) == 32,
+              "FramePointersGlobal mirrors the first fields of FrameArgs");
+
+__device__ __forceinline__ void frame_pointers_global(FrameArgs &f, const FrameArgs *src) {
+    const FramePointersGlobal g = *reinterpret_cast<const FramePointersGlobal *>(src);
+    f.depth = (const float *)g.depth;
+    f.normals = (float *)g.normals;
+    f.mask = (uint8_t *)g.mask;
+    f.stats = (bn_frame_stats *)g.stats;
+    f.work = (bn_frame_stats *)g.work;
+}
 
 // Arguments of frame k of a stack.
 __device__ __forceinline__ FrameArgs stack_frame(const StackArgs &s, uint32_t k) {
