@@ -94,26 +94,36 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchFrame *__restrict__
     }
 }
 
-// One workgroup per frame: sum the frame's wavefront counts and add the
-// totals to its bn_frame_stats (or store them, BN_FLAG_COUNTS_OVERWRITE).
+// Sums of the wavefront counts: workgroup (f, c) takes chunk c of
+// kCountChunk tiles of frame f.  A frame of one chunk adds its totals to its
+// bn_frame_stats (or stores them, BN_FLAG_COUNTS_OVERWRITE) at once; the
+// chunks of a larger frame combine through the in-launch reduction of the
+// plain kernels, on the plan's work area for the frame, so that one huge
+// frame is not summed by a single workgroup.
+constexpr uint32_t kCountChunk = 4096;
+
 __global__ __launch_bounds__(kBlock) void k_batch_counts(const BatchFrame *__restrict__ frames,
                                                          const uint32_t *__restrict__ wave_counts,
                                                          uint32_t nframes) {
     __shared__ uint32_t s_sum[kBlock / 64][2];
     const uint32_t fi = blockIdx.x;
     if (fi >= nframes) return;
-    bn_frame_stats *st = frames[fi].a.stats;
+    FrameArgs f = frames[fi].a;
+    frame_pointers_global(f, &frames[fi].a);
     const uint32_t nt = frames[fi].ntiles;
-    if (!st || nt == 0) return;  // uniform over the workgroup
+    const uint32_t nchunks = (nt + kCountChunk - 1) / kCountChunk;
+    const uint32_t c = blockIdx.y;
+    if (!f.stats || c >= nchunks) return;  // uniform over the workgroup
+    const uint32_t kb = c * kCountChunk, ke = min(nt, kb + kCountChunk);
     // the 4 wavefront counts of a tile are one 16-byte load; unrolled so that
     // several loads are in flight per thread
     const uint4 *wc = reinterpret_cast<const uint4 *>(wave_counts) + frames[fi].tile_begin;
     uint32_t v = 0, b = 0;
 #pragma unroll 8
-    for (uint32_t k = threadIdx.x; k < nt; k += kBlock) {
-        const uint4 c = wc[k];
-        v += (c.x & 0xffffu) + (c.y & 0xffffu) + (c.z & 0xffffu) + (c.w & 0xffffu);
-        b += (c.x >> 16) + (c.y >> 16) + (c.z >> 16) + (c.w >> 16);
+    for (uint32_t k = kb + threadIdx.x; k < ke; k += kBlock) {
+        const uint4 q = wc[k];
+        v += (q.x & 0xffffu) + (q.y & 0xffffu) + (q.z & 0xffffu) + (q.w & 0xffffu);
+        b += (q.x >> 16) + (q.y >> 16) + (q.z >> 16) + (q.w >> 16);
     }
     // wavefront sums through DPP-free shuffles, then across the 4 wavefronts
     for (int off = 32; off > 0; off >>= 1) {
@@ -131,7 +141,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_counts(const BatchFrame *__res
             vt += s_sum[w][0];
             bt += s_sum[w][1];
         }
-        put_counts(st, vt, bt, frames[fi].a.npix, frames[fi].a.overwrite);
+        if (nchunks == 1)
+            put_counts(f.stats, vt, bt, f.npix, f.overwrite);
+        else
+            reduce_counts(f.work, f.stats, c, nchunks, vt, bt, f.npix, f.overwrite);
     }
 }
 
@@ -252,7 +265,10 @@ struct bn_batch_plan {
     bool small_mode = false;
     SmallBatch small{};
     SmallKernelFn small_fn = nullptr;
-    bn_frame_stats *work = nullptr;        // kSmallFrames work areas, zero between launches
+    // one count work area per frame of the capacity, zero between launches
+    // (the small lists' in-kernel reductions, the large frames' count sums)
+    bn_frame_stats *work = nullptr;
+    uint32_t count_chunks = 1;             // grid.y of the count sums
     hipGraph_t sgraph = nullptr;
     hipGraphExec_t sexec = nullptr;
     hipGraphNode_t snode = nullptr;
@@ -306,11 +322,12 @@ uint32_t grid_for(uint64_t tiles, int cus, uint32_t blocks_per_cu) {
 
 // Host image of the descriptors of `frames` (already validated) in `base`.
 int build_table(const bn_frame *frames, int32_t n, const bn_params *p, int32_t capacity,
-                uint32_t grid, void *base) {
+                uint32_t grid, bn_frame_stats *work, uint32_t *count_chunks, void *base) {
     auto *hdr = static_cast<BatchHeader *>(base);
     auto *fr = reinterpret_cast<BatchFrame *>(hdr + 1);
     auto *tf = reinterpret_cast<uint32_t *>(static_cast<char *>(base) + table_offset(capacity));
     uint64_t tiles = 0;
+    *count_chunks = 1;
     for (int32_t k = 0; k < n; ++k) {
         const bn_frame &s = frames[k];
         const bool vec = frame_vec(s, p);
@@ -320,8 +337,11 @@ int build_table(const bn_frame *frames, int32_t n, const bn_params *p, int32_t c
         if (s.height > 0 && s.width > 0) {
             fill_frame_args(b.a, s.depth, s.height, s.width, s.depth_stride, s.fx, s.fy, s.cx,
                             s.cy, p, s.normals, s.mask, s.stats, vec ? 4 : 1);
+            b.a.work = work + k;
             nt = ((uint64_t)b.a.nitems + kBlock - 1) / kBlock;
         }
+        const uint32_t nc = (uint32_t)((nt + kCountChunk - 1) / kCountChunk);
+        if (nc > *count_chunks) *count_chunks = nc;
         b.tile_begin = (uint32_t)tiles;
         b.ntiles = (uint32_t)nt;
         b.vec = vec ? 1u : 0u;
@@ -362,11 +382,11 @@ void build_small(bn_batch_plan *pl, const bn_frame *frames, int32_t n) {
     sb.ntiles = tiles;
 }
 
-hipKernelNodeParams kernel_params(void *func, uint32_t grid, void **args) {
+hipKernelNodeParams kernel_params(void *func, dim3 grid, void **args) {
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof(kp));
     kp.func = func;
-    kp.gridDim = dim3(grid);
+    kp.gridDim = grid;
     kp.blockDim = dim3(kBlock);
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
@@ -398,7 +418,7 @@ struct BatchArgs {
           counts{(void *)&frames, (void *)&wave_counts_c, (void *)&nframes} {}
     BatchArgs(const BatchArgs &) = delete;
     BatchArgs &operator=(const BatchArgs &) = delete;
-    uint32_t count_grid() const { return nframes ? nframes : 1u; }
+    dim3 count_grid(const bn_batch_plan *pl) const { return dim3(nframes ? nframes : 1u, pl->count_chunks); }
 };
 
 // Kernel node parameters (buffer pointers, header values, grids) into the
@@ -407,7 +427,7 @@ int refresh_node(bn_batch_plan *pl) {
     BatchArgs a(pl);
     hipKernelNodeParams kp = kernel_params(reinterpret_cast<void *>(pl->fn), pl->grid, a.main);
     hipKernelNodeParams cp = kernel_params(reinterpret_cast<void *>(k_batch_counts),
-                                           a.count_grid(), a.counts);
+                                           a.count_grid(pl), a.counts);
     pl->graph_stale = false;
     if (!pl->exec) {
         if (hipGraphCreate(&pl->graph, 0) != hipSuccess ||
@@ -486,7 +506,8 @@ int refresh_small_node(bn_batch_plan *pl) {
 // `stream` (header, descriptors and the used part of the tile table).
 int upload(bn_batch_plan *pl, const bn_frame *frames, int32_t n, int k, hipStream_t stream,
            uint64_t tiles) {
-    int rc = build_table(frames, n, &pl->params, pl->capacity, pl->grid, pl->staging[k]);
+    int rc = build_table(frames, n, &pl->params, pl->capacity, pl->grid, pl->work,
+                         &pl->count_chunks, pl->staging[k]);
     if (rc != BN_OK) return rc;
     pl->hdr = *static_cast<const BatchHeader *>(pl->staging[k]);
     const size_t bytes = table_offset(pl->capacity) + sizeof(uint32_t) * (size_t)tiles;
@@ -549,21 +570,25 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
             return BN_ERR_DEVICE;
         }
     }
+    // the counts' work areas, one per frame of the capacity, zero from here on
+    const size_t work_bytes = sizeof(bn_frame_stats) * (size_t)n_frames;
+    if (hipMalloc(&pl->work, work_bytes) != hipSuccess) {
+        free_plan(pl);
+        return BN_ERR_OOM;
+    }
+    if (hipMemsetAsync(pl->work, 0, work_bytes, nullptr) != hipSuccess ||
+        hipStreamSynchronize(nullptr) != hipSuccess) {
+        free_plan(pl);
+        return BN_ERR_DEVICE;
+    }
     rc = alloc_buffers(pl, tiles > 0 ? tiles : 1);
     if (rc == BN_OK) rc = build_table(frames_host, n_frames, params, pl->capacity, pl->grid,
-                                      pl->staging[0]);
+                                      pl->work, &pl->count_chunks, pl->staging[0]);
     if (rc == BN_OK) pl->hdr = *static_cast<const BatchHeader *>(pl->staging[0]);
     if (rc == BN_OK &&
         hipMemcpy(pl->dbuf, pl->staging[0], pl->buf_bytes, hipMemcpyHostToDevice) != hipSuccess)
         rc = BN_ERR_DEVICE;
     if (rc == BN_OK) rc = refresh_node(pl);
-    // the small lists' count work areas, zero from here on
-    if (rc == BN_OK &&
-        (hipMalloc(&pl->work, sizeof(bn_frame_stats) * kSmallFrames) != hipSuccess ||
-         hipMemsetAsync(pl->work, 0, sizeof(bn_frame_stats) * kSmallFrames, nullptr) !=
-             hipSuccess ||
-         hipStreamSynchronize(nullptr) != hipSuccess))
-        rc = BN_ERR_DEVICE;
     if (rc != BN_OK) {
         free_plan(pl);
         return rc;
@@ -671,7 +696,7 @@ int bn_batch_launch(bn_batch_plan *plan, void *stream) {
     BatchArgs a(plan);
     if (hipLaunchKernel(reinterpret_cast<const void *>(plan->fn), dim3(plan->grid),
                         dim3(kBlock), a.main, 0, s) != hipSuccess ||
-        hipLaunchKernel(reinterpret_cast<const void *>(k_batch_counts), dim3(a.count_grid()),
+        hipLaunchKernel(reinterpret_cast<const void *>(k_batch_counts), a.count_grid(plan),
                         dim3(kBlock), a.counts, 0, s) != hipSuccess)
         return BN_ERR_DEVICE;
     return BN_OK;

@@ -283,3 +283,27 @@ def test_small_and_table_lists_through_one_plan():
                 assert torch.equal(f.normals.view(torch.int32), n_.view(torch.int32)), (n, k)
                 assert torch.equal(f.mask, m_), (n, k)
                 assert f.stats[:3].tolist() == st_[:3].tolist(), (n, k)
+
+
+def test_large_frame_counts_in_chunks():
+    """A frame of more than 4096 tiles has its counts summed in chunks that
+    combine through the plan's work area: counts equal the plain launch's,
+    added over repeated runs and stored with the overwrite flag."""
+    import torch
+    big = scenes.sized_frame(3072, 4096, seed=700)
+    small = [scenes.sized_frame(40, 64, seed=701 + k) for k in range(16)]
+    frames = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in [big] + small]
+    want = [_plain_outputs(f, 2, "rel", 4.0)[2][:3].tolist() for f in frames]
+    for overwrite in (False, True):
+        with bn.BatchPlan(frames, 2, "rel", 4.0, overwrite_counts=overwrite) as plan:
+            for f in frames:
+                f.stats.zero_()
+            for how in ("run", "launch", "run"):
+                getattr(plan, how)()
+            torch.cuda.synchronize()
+            times = 1 if overwrite else 3
+            for k, f in enumerate(frames):
+                assert f.stats[:3].tolist() == [times * c for c in want[k]], (overwrite, k)
+    n, m, _ = _plain_outputs(frames[0], 2, "rel", 4.0)
+    assert torch.equal(frames[0].normals.view(torch.int32), n.view(torch.int32))
+    assert torch.equal(frames[0].mask, m)
