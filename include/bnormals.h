@@ -264,8 +264,9 @@ int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t height, int32_t 
  *
  * A plan holds the frame descriptors in device memory and a HIP graph of two
  * kernel nodes: one processes every tile of every frame (one workgroup per
- * tile of 1024 pixels by default), the other sums each frame's counts;
- * running the plan replays the graph.  A list of at most BN_SMALL_BATCH
+ * tile of 1024 pixels by default), the other sums each frame's counts (in
+ * chunks of 4096 tiles for large frames); running the plan replays the
+ * graph.  A list of at most BN_SMALL_BATCH
  * frames instead carries its descriptors in the kernel arguments and reduces
  * its counts inside the one kernel (on a zeroed work area of the plan): an
  * update of such a list uploads nothing, and a run is a single kernel, its
@@ -281,8 +282,8 @@ int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t height, int32_t 
  * bn_batch_plan_create: validates every frame (the checks of
  *   bn_estimate_normals), allocates the plan (device descriptor table of
  *   n_frames entries, a tile-to-frame table, a table of 4 counts per tile,
- *   two pinned staging copies, BN_SMALL_BATCH count work areas) and
- *   instantiates the graph.
+ *   two pinned staging copies, n_frames count work areas) and instantiates
+ *   the graph.
  *   Capacity = n_frames.  Returns BN_OK, BN_ERR_INVALID_ARG,
  *   BN_ERR_UNSUPPORTED, BN_ERR_OOM or BN_ERR_DEVICE; *out_plan is NULL on
  *   error.  Synchronous.
