@@ -21,7 +21,7 @@
  *     This assignment is the one that turns the four-pair average of Eq. 7
  *     into the closed forms of Eqs. 10-12 (u runs with the column and fx,
  *     v with the row and fy, as in the pinhole model under Eq. 3).
- *  2. Validity (the paper is silent; this build's reading): the pixel is
+ *  2. Validity (the paper is silent; the reading taken here): the pixel is
  *     INVALID when the stencil leaves the image or a tap d1..d5 is not a
  *     finite positive depth.
  *  3. Normal, in FP64 (Section 3.1):
