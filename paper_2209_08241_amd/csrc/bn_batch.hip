@@ -59,8 +59,14 @@ struct BatchHeader {
 // of a tile (VALID | BOUNDARY << 16, at most 256 pixels each) into
 // wave_counts[4 t + w]; a second kernel of the same graph sums them per
 // frame.  The main kernel thus has neither atomics nor workgroup barriers.
+// At most 80 scalar registers: left alone the compiler takes 92 (allocated
+// as 96), which it counts as fitting 8 wavefronts per SIMD, but the
+// measured mean occupancy was 6.5 against 7.6 for the kernels of 61-67
+// registers; capped at 80 (a few spills to VGPR lanes) the 256-frame mix
+// runs 540 -> 527 us (72 and 64 spill more and are slower).
 template <int A, int M>
-__global__ __launch_bounds__(kBlock) void k_batch(const BatchFrame *__restrict__ frames,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(80))) void k_batch(
+    const BatchFrame *__restrict__ frames,
                                                   const uint32_t *__restrict__ tile_frame,
                                                   uint32_t *__restrict__ wave_counts,
                                                   uint32_t ntiles, uint32_t chunk,
