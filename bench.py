@@ -39,7 +39,10 @@ def log(msg):
 
 
 def kernel_hash() -> str:
+    """The measured kernels' sources and the flags they are compiled with."""
+    from paper_2209_08241_amd.build import HIPCC_FLAGS
     h = hashlib.sha256()
+    h.update(" ".join(HIPCC_FLAGS).encode())
     for name in KERNEL_SOURCES:
         p = os.path.join(ROOT, "paper_2209_08241_amd", "csrc", name)
         if os.path.exists(p):
@@ -438,6 +441,9 @@ def plain_launches(args, torch, bn, frames, stream, px):
     return res
 
 
+SETS = 6   # buffer sets the differentiation timings cycle over
+
+
 def run_diff(args, torch, bn, scenes):
     """Differentiation: 16 x 640x480 frames (seeds 2000..2015) as one stack.
     The adjoint kernel over the stack (one launch), the forward over the
@@ -474,14 +480,17 @@ def run_diff(args, torch, bn, scenes):
     log("adjoint parity frame 0 ok")
     stream = torch.cuda.Stream()
 
-    def timed_graph(fn, reps=50):
-        """us per call of fn(stream), captured once and replayed."""
+    def timed_graph(fn, reps=20, calls=2 * SETS):
+        """us per call of fn(stream, buffer set): `calls` calls captured in
+        one graph, cycling over the buffer sets, replayed back to back (one
+        call per graph would time the graph launch as well)."""
         with torch.cuda.stream(stream):
-            fn(stream)
+            fn(stream, 0)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
-            fn(torch.cuda.current_stream())
+            for c in range(calls):
+                fn(torch.cuda.current_stream(), c % SETS)
         for _ in range(3):
             g.replay()
         torch.cuda.synchronize()
@@ -493,23 +502,29 @@ def run_diff(args, torch, bn, scenes):
                 g.replay()
             end.record(stream)
         end.synchronize()
-        return start.elapsed_time(end) * 1e3 / reps
+        return start.elapsed_time(end) * 1e3 / (reps * calls)
 
     adj_bytes = 20                      # depth 4 B + cotangent 12 B in, gradient 4 B out
     fwd_bytes = 17                      # depth 4 B in, normal 12 B + code 1 B out
-    nrm = torch.empty((n, H, W, 3), device=dev)
-    msk = torch.empty((n, H, W), dtype=torch.uint8, device=dev)
-    us_adj = timed_graph(lambda st: bn.normals_vjp_stack(depth, intr, grads, grad_depth=gd,
-                                                         stream=st, **kw))
-    us_fwd = timed_graph(lambda st: bn.estimate_normals_stack(depth, intr, normals=nrm, mask=msk,
-                                                              want_stats=False, stream=st, **kw))
+    # SETS copies of every buffer (160 MB a set), used in turn, so that the
+    # 256 MB last-level cache cannot hold what a call reads and writes
+    D = [depth] + [depth.clone() for _ in range(SETS - 1)]
+    G = [grads] + [grads.clone() for _ in range(SETS - 1)]
+    GD = [gd] + [torch.empty_like(gd) for _ in range(SETS - 1)]
+    NRM = [torch.empty((n, H, W, 3), device=dev) for _ in range(SETS)]
+    MSK = [torch.empty((n, H, W), dtype=torch.uint8, device=dev) for _ in range(SETS)]
+    us_adj = timed_graph(lambda st, i: bn.normals_vjp_stack(D[i], intr, G[i], grad_depth=GD[i],
+                                                            stream=st, **kw))
+    us_fwd = timed_graph(lambda st, i: bn.estimate_normals_stack(D[i], intr, normals=NRM[i],
+                                                                 mask=MSK[i], want_stats=False,
+                                                                 stream=st, **kw))
 
-    def per_frame(st):
+    def per_frame(st, i):
         for k, s in enumerate(scs):
-            bn.normals_vjp(depth[k], s.fx, s.fy, s.cx, s.cy, grads[k], grad_depth=gd[k],
+            bn.normals_vjp(D[i][k], s.fx, s.fy, s.cx, s.cy, G[i][k], grad_depth=GD[i][k],
                            stream=st, **kw)
 
-    us_adj_frames = timed_graph(per_frame)
+    us_adj_frames = timed_graph(per_frame, reps=5)
 
     def rl(bpp, us):
         a = bpp * n * px / (us * 1e-6) / 1e9
@@ -535,7 +550,8 @@ def run_diff(args, torch, bn, scenes):
     log(f"stack of 16: adjoint {us_adj:.1f} us, forward {us_fwd:.1f} us, 16 single-frame "
         f"adjoints {us_adj_frames:.1f} us; step {ms_step:.3f} ms")
     return {"workload": "16 x 640x480 (seeds 2000..2015) as one stack [16, 480, 640] with "
-                        "per-frame intrinsics; kernels graph-replayed; full step = stacked "
+                        "per-frame intrinsics; kernels graph-replayed, 12 calls a graph over "
+                        f"{SETS} distinct sets of buffers; full step = stacked "
                         "forward + cosine loss vs the noise-free depth's normals + stacked "
                         "backward, eager, one host synchronisation per step",
             "adjoint_us_per_stack": us_adj, "adjoint_us_per_frame": us_adj / n,

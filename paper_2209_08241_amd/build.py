@@ -24,6 +24,10 @@ ARCH = os.environ.get("BN_OFFLOAD_ARCH", "gfx950")
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off",
+    # the SLP vectorizer packs the per-pixel validity flags into vector
+    # registers and tests them there (about 15 instructions where 5 compares
+    # and 4 scalar ANDs do)
+    "-fno-slp-vectorize",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # every device atomic here is issued by one lane; the wavefront-combining
     # rewrite adds a wait for the atomic's return right after it

@@ -5,25 +5,65 @@
 // For a VALID pixel the output is o/|o| with o = (mx, my, -mz) the scaled
 // vector of Eqs. 10-12 (see bn_device.h), a smooth function of the taps
 // d2..d5 through P = d2-d4, S = d2+d4, Q = d3-d5, T = d3+d5.  With
-// g_o = (g - (n.g) n)/|o| the gradient with respect to o,
-//   dP = g_ox fx T - g_oz xc T          dQ = g_oy fy S - g_oz yc S
-//   dS = g_oy fy Q - g_oz (yc Q + a T)  dT = g_ox fx P - g_oz (xc P + a S)
+// g_o = (g - (n.g) n)/|o| the gradient with respect to o and
+//   u = fx g_ox - xc g_oz,   v = fy g_oy - yc g_oz,   z = a g_oz,
+// the partial derivatives are
+//   dP = T u,   dQ = S v,   dS = Q v - T z,   dT = P u - S z
 // and the taps receive  d2: dP + dS,  d4: -dP + dS,  d3: dQ + dT,
 // d5: -dQ + dT.
 //
-// Gather form: a workgroup owns a TX x TY tile of output depths (64 x 16, or
-// 32 x 8 on frames under 2^20 pixels, which would otherwise leave most
-// compute units idle).  It stages the depth of the tile plus a 2-alpha ring
-// in LDS, evaluates every pixel of
-// the tile plus an alpha ring once (its code and its four tap gradients, in
-// LDS), and each output depth then sums the four contributions that land on
-// it, in a fixed order.  No atomics: the result is deterministic.
+// Gather form, no atomics (deterministic): the depth at (x, y) is tap 2 of
+// (x-a, y), tap 4 of (x+a, y), tap 3 of (x, y-a) and tap 5 of (x, y+a), and
+// its gradient is ((g2 + g4) + g3) + g5 of those four pixels, in that order
+// in every kernel here, so all of them give the same bits.
+//
+// Vector kernels (rows of whole float4 groups, a <= 4): a workgroup owns a
+// strip of 62 float4 groups (248 columns) and a band of 4 RB rows, RB rows
+// per wavefront.  Lane l evaluates group 62 s - 1 + l of each row (its
+// codes and tap gradients, from float4 loads), so lanes 1..62 own the
+// strip's outputs and lanes 0 and 63 are the halo; the horizontal taps and
+// the tap-2 / tap-4 gradients move between neighbouring lanes by DPP.  Each
+// wavefront rolls down its rows keeping the last 2a rows' gradients in
+// registers; the a rows next to a neighbouring wavefront's rows are finished
+// after one workgroup barrier, from the neighbour's gradients left in LDS,
+// and the 2a rows above and below the band are evaluated once, shared out
+// over the four wavefronts.  Per output: 1 + a / (2 RB) row evaluations.
+//
+// Scalar kernels (any layout, any a): a workgroup owns a TX x TY tile of
+// output depths (64 x 16, or 32 x 8 on frames under 2^20 pixels, which
+// would otherwise leave most compute units idle).  It stages the depth of
+// the tile plus a 2-alpha ring in LDS, evaluates every pixel of the tile
+// plus an alpha ring once (its code and its four tap gradients, in LDS),
+// and each output depth then sums the four contributions that land on it.
 #include "bn_device.h"
 #include "bn_internal.h"
 
 #pragma clang fp contract(off)
 
 namespace bn {
+
+// Tap gradients of one pixel (meaningful when its code is VALID).
+struct TapGrads {
+    float g2, g3, g4, g5;
+};
+
+__device__ __forceinline__ TapGrads tap_grads(const PixelTerms &t, float gx, float gy, float gz,
+                                              float xc, float yc, const FrameArgs &f) {
+    const float inv = __builtin_amdgcn_rsqf(t.q);
+    const float nx = t.mx * inv, ny = t.my * inv, nz = -(t.mz * inv);
+    const float dot = (nx * gx + ny * gy) + nz * gz;
+    const float ox = (gx - dot * nx) * inv;
+    const float oy = (gy - dot * ny) * inv;
+    const float oz = (gz - dot * nz) * inv;
+    const float u = f.fx * ox - xc * oz;
+    const float v = f.fy * oy - yc * oz;
+    const float z = f.af * oz;
+    const float dP = t.T * u;
+    const float dQ = t.S * v;
+    const float dS = t.Q * v - t.T * z;
+    const float dT = t.P * u - t.S * z;
+    return TapGrads{dP + dS, dQ + dT, dS - dP, dT - dQ};
+}
 
 // One TX x TY tile of the gradient of one frame.
 template <int A, int TX, int TY>
@@ -83,21 +123,11 @@ __device__ __forceinline__ void vjp_tile(const FrameArgs &f, const float *__rest
             const float yc = (float)Y - f.cy;
             const PixelTerms t = eval_terms(inside, d1, d2, d3, d4, d5, xc, yc, f);
             if (t.code == BN_VALID) {
-                const float inv = __builtin_amdgcn_rsqf(t.q);
-                const float nx = t.mx * inv, ny = t.my * inv, nz = -(t.mz * inv);
-                const float gx = cg[i][0], gy = cg[i][1], gz = cg[i][2];
-                const float dot = (nx * gx + ny * gy) + nz * gz;
-                const float ox = (gx - dot * nx) * inv;
-                const float oy = (gy - dot * ny) * inv;
-                const float oz = (gz - dot * nz) * inv;
-                const float dP = ox * f.fx * t.T - oz * xc * t.T;
-                const float dQ = oy * f.fy * t.S - oz * yc * t.S;
-                const float dS = oy * f.fy * t.Q - oz * (yc * t.Q + f.af * t.T);
-                const float dT = ox * f.fx * t.P - oz * (xc * t.P + f.af * t.S);
-                g2 = dP + dS;
-                g4 = dS - dP;
-                g3 = dQ + dT;
-                g5 = dT - dQ;
+                const TapGrads d = tap_grads(t, cg[i][0], cg[i][1], cg[i][2], xc, yc, f);
+                g2 = d.g2;
+                g3 = d.g3;
+                g4 = d.g4;
+                g5 = d.g5;
             }
         }
         s_g[0][k] = g2;
@@ -134,6 +164,239 @@ __global__ __launch_bounds__(kBlock) void k_vjp_stack(const StackArgs s) {
     const int64_t npix = (int64_t)s.f.npix;
     vjp_tile<A, TX, TY>(stack_frame(s, k), s.gn + (int64_t)k * npix * 3, s.gd + (int64_t)k * npix,
                         tile, s.tiles_x);
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels.
+// ---------------------------------------------------------------------------
+constexpr int kVjpGroups = 62;  // output float4 groups per strip (lanes 1..62)
+
+// One row of evaluated pixels: per lane, for its 4 pixels, the sum of the
+// tap-2 gradient of the pixel a to the left and the tap-4 gradient of the
+// pixel a to the right (h), and its own tap-3 and tap-5 gradients.
+struct RowGrads {
+    f4 h, g3, g5;
+};
+
+// The loads of one row: the depth of the lane's group in rows y, y-a and
+// y+a, the halo lanes' outer group of row y, and the cotangents.
+struct RowLoad {
+    f4 c, up, dn, side, k0, k1, k2;
+};
+
+__device__ __forceinline__ bool vjp4_row_live(const FrameArgs &f, int y, int a) {
+    return y >= a && y + a < f.H;
+}
+
+// Rows whose codes are all INVALID (the border rows and rows out of the
+// frame) are skipped by the whole wavefront.  xl: the lane's column clamped
+// into the frame.  Every load in a row is unconditional (a clamped lane
+// loads some group of the row); the values a clamped load brings in only
+// reach pixels that are not inside, whose codes are INVALID and whose
+// gradients are therefore zero.
+template <int A>
+__device__ __forceinline__ void vjp4_load(const FrameArgs &f, const float *__restrict__ gn, int y,
+                                          int x0, int xl, uint32_t lane, RowLoad &L) {
+    if (!vjp4_row_live(f, y, A)) return;
+    const float *rp = f.depth + (int64_t)y * f.stride;
+    L.c = *reinterpret_cast<const f4 *>(rp + xl);
+    L.up = *reinterpret_cast<const f4 *>(rp - (int64_t)A * f.stride + xl);
+    L.dn = *reinterpret_cast<const f4 *>(rp + (int64_t)A * f.stride + xl);
+    const f4 *gp = reinterpret_cast<const f4 *>(gn + 3 * (int64_t)y * f.W) + 3 * (xl >> 2);
+    L.k0 = gp[0];
+    L.k1 = gp[1];
+    L.k2 = gp[2];
+    if (lane == 0) L.side = *reinterpret_cast<const f4 *>(rp + max(x0 - 4, 0));
+    if (lane == 63) L.side = *reinterpret_cast<const f4 *>(rp + min(x0 + 4, f.W - 4));
+}
+
+template <int A>
+__device__ __forceinline__ RowGrads vjp4_eval(const FrameArgs &f, int y, int x0, uint32_t lane,
+                                              const RowLoad &L) {
+    RowGrads r;
+    r.h = r.g3 = r.g5 = f4{0.f, 0.f, 0.f, 0.f};
+    if (!vjp4_row_live(f, y, A)) return r;
+    const bool gin = (x0 >= 0) & (x0 < f.W);
+    const f4 c = L.c, up = L.up, dn = L.dn, k0 = L.k0, k1 = L.k1, k2 = L.k2;
+    // Row window x0-4 .. x0+7 (the halo lanes loaded their outer float4).
+    f4 lk = from_left(c), rk = from_right(c);
+    if (lane == 0) lk = L.side;
+    if (lane == 63) rk = L.side;
+    const float row[12] = {lk.x, lk.y, lk.z, lk.w, c.x, c.y, c.z, c.w, rk.x, rk.y, rk.z, rk.w};
+    const float upv[4] = {up.x, up.y, up.z, up.w};
+    const float dnv[4] = {dn.x, dn.y, dn.z, dn.w};
+    const float cg[12] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w, k2.x, k2.y, k2.z, k2.w};
+    const float yc = (float)y - f.cy;
+    float g2[4], g3[4], g4[4], g5[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int x = x0 + j;
+        const bool inside = gin & (x >= A) & (x + A < f.W);
+        const float xc = (float)x - f.cx;
+        const PixelTerms t = eval_terms(inside, row[4 + j], row[4 + j + A], dnv[j],
+                                        row[4 + j - A], upv[j], xc, yc, f);
+        const bool valid = t.code == BN_VALID;
+        const TapGrads d = tap_grads(t, cg[3 * j], cg[3 * j + 1], cg[3 * j + 2], xc, yc, f);
+        g2[j] = valid ? d.g2 : 0.f;
+        g3[j] = valid ? d.g3 : 0.f;
+        g4[j] = valid ? d.g4 : 0.f;
+        g5[j] = valid ? d.g5 : 0.f;
+    }
+    float h[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float a = j - A >= 0 ? g2[j - A] : from_left(g2[j - A + 4]);
+        const float b = j + A < 4 ? g4[j + A] : from_right(g4[j + A - 4]);
+        h[j] = a + b;
+    }
+    r.h = f4{h[0], h[1], h[2], h[3]};
+    r.g3 = f4{g3[0], g3[1], g3[2], g3[3]};
+    r.g5 = f4{g5[0], g5[1], g5[2], g5[3]};
+    return r;
+}
+
+template <int A>
+__device__ __forceinline__ RowGrads vjp4_row(const FrameArgs &f, const float *__restrict__ gn,
+                                             int y, int x0, int xl, uint32_t lane) {
+    RowLoad L;
+    vjp4_load<A>(f, gn, y, x0, xl, lane, L);
+    return vjp4_eval<A>(f, y, x0, lane, L);
+}
+
+// Strip `strip`, band `band` of one frame (see the top of the file).
+template <int A, int RB>
+__device__ __forceinline__ void vjp4_band(const FrameArgs &f, const float *__restrict__ gn,
+                                          float *__restrict__ gd, uint32_t strip,
+                                          uint32_t band) {
+    static_assert(A >= 1 && A <= 4 && RB >= 2 * A, "band rows per wavefront");
+    // x3[w]: tap-3 gradients of the a rows above wavefront w's rows;
+    // x5[w]: tap-5 gradients of the a rows below wavefront w-1's rows.
+    __shared__ f4 x3[5][A][64];
+    __shared__ f4 x5[5][A][64];
+    const uint32_t lane = threadIdx.x & 63u;
+    // the wavefront index, uniform: row addresses and bounds are scalar
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int x0 = 4 * ((int)(strip * kVjpGroups + lane) - 1);
+    const int xl = min(max(x0, 0), f.W - 4);
+    const int y0 = (int)(band * 4u * RB);
+    const int yw = y0 + (int)w * RB;
+    const bool out_lane = (lane >= 1u) & (lane <= (uint32_t)kVjpGroups) & (x0 < f.W);
+    auto put = [&](int y, f4 v) {
+        if (out_lane && y < f.H)
+            __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(gd + (int64_t)y * f.W + x0));
+    };
+    // The band's 2a outer rows, dealt round the wavefronts.
+    for (int k = (int)w; k < 2 * A; k += 4) {
+        if (k < A) {
+            x3[0][k][lane] = vjp4_row<A>(f, gn, y0 - A + k, x0, xl, lane).g3;
+        } else {
+            x5[4][k - A][lane] = vjp4_row<A>(f, gn, y0 + 4 * RB + (k - A), x0, xl, lane).g5;
+        }
+    }
+    f4 h[RB], g3[RB], top5[A], bot[A];
+    // each row's loads are issued before the previous row is evaluated
+    RowLoad cur, nxt;
+    vjp4_load<A>(f, gn, yw, x0, xl, lane, cur);
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        if (i + 1 < RB) vjp4_load<A>(f, gn, yw + i + 1, x0, xl, lane, nxt);
+        const RowGrads e = vjp4_eval<A>(f, yw + i, x0, lane, cur);
+        cur = nxt;
+        h[i] = e.h;
+        g3[i] = e.g3;
+        if (i < A) x5[w][i][lane] = e.g5;             // for the wavefront above
+        if (i >= RB - A) x3[w + 1][i - (RB - A)][lane] = e.g3;  // for the one below
+        const int j = i - A;                           // the row that e.g5 completes
+        if (j >= 0 && j < A) top5[j] = e.g5;
+        if (j >= A && j < RB - A) put(yw + j, (h[j] + g3[j - A]) + e.g5);
+        if (i >= RB - A) bot[i - (RB - A)] = h[i] + g3[i - A];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < A; ++j) put(yw + j, (h[j] + x3[w][j][lane]) + top5[j]);
+#pragma unroll
+    for (int j = 0; j < A; ++j) put(yw + RB - A + j, bot[j] + x5[w + 1][j][lane]);
+}
+
+template <int A, int RB>
+__global__ __launch_bounds__(kBlock) void k_vjp4(FrameArgs f, const float *__restrict__ gn,
+                                                 float *__restrict__ gd, uint32_t strips) {
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    vjp4_band<A, RB>(f, gn, gd, b % strips, b / strips);
+}
+
+// A stack: workgroup b takes band-strip b % T of frame b / T.
+template <int A, int RB>
+__global__ __launch_bounds__(kBlock) void k_vjp4_stack(const StackArgs s) {
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t k = b / s.tiles_per_frame;
+    const uint32_t t = b - k * s.tiles_per_frame;
+    const int64_t npix = (int64_t)s.f.npix;
+    vjp4_band<A, RB>(stack_frame(s, k), s.gn + (int64_t)k * npix * 3, s.gd + (int64_t)k * npix,
+                     t % s.tiles_x, t / s.tiles_x);
+}
+
+// Rows per wavefront: 8, or 4 (a <= 2) when the grid of 8-row bands would
+// hold fewer than kVjpMinGroups workgroups (measured: a 1920x1080 frame,
+// 272 workgroups of 8-row bands, 11.6 us with 4-row bands against 14.9 us;
+// 16 frames of 640x480, 720 workgroups, 21.9 us with 8-row bands against
+// 22.8 us).
+constexpr uint64_t kVjpMinGroups = 512;
+
+struct Vjp4Shape {
+    int rb;
+    uint32_t strips, bands;
+};
+
+static Vjp4Shape vjp4_shape(int32_t H, int32_t W, int32_t n, int alpha) {
+    Vjp4Shape s;
+    s.strips = (uint32_t)((W / 4 + kVjpGroups - 1) / kVjpGroups);
+    const uint64_t big = (uint64_t)s.strips * (uint64_t)((H + 31) / 32) * (uint64_t)n;
+    s.rb = (alpha <= 2 && big < kVjpMinGroups) ? 4 : 8;
+    s.bands = (uint32_t)((H + 4 * s.rb - 1) / (4 * s.rb));
+    return s;
+}
+
+typedef void (*Vjp4Fn)(FrameArgs, const float *, float *, uint32_t);
+typedef void (*Vjp4StackFn)(const StackArgs);
+
+static Vjp4Fn vjp4_kernel(int a, int rb) {
+    if (rb == 4) {
+        if (a == 1) return k_vjp4<1, 4>;
+        if (a == 2) return k_vjp4<2, 4>;
+        return nullptr;
+    }
+    switch (a) {
+        case 1: return k_vjp4<1, 8>;
+        case 2: return k_vjp4<2, 8>;
+        case 3: return k_vjp4<3, 8>;
+        case 4: return k_vjp4<4, 8>;
+    }
+    return nullptr;
+}
+
+static Vjp4StackFn vjp4_stack_kernel(int a, int rb) {
+    if (rb == 4) {
+        if (a == 1) return k_vjp4_stack<1, 4>;
+        if (a == 2) return k_vjp4_stack<2, 4>;
+        return nullptr;
+    }
+    switch (a) {
+        case 1: return k_vjp4_stack<1, 8>;
+        case 2: return k_vjp4_stack<2, 8>;
+        case 3: return k_vjp4_stack<3, 8>;
+        case 4: return k_vjp4_stack<4, 8>;
+    }
+    return nullptr;
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p % 16) == 0; }
+
+// The vector kernels' layout: rows of whole, 16-byte aligned float4 groups.
+static bool vjp4_layout(const float *depth, int32_t W, int64_t stride, int64_t fstride,
+                        const float *gn, const float *gd, int alpha) {
+    return alpha <= 4 && W % 4 == 0 && stride % 4 == 0 && fstride % 4 == 0 && aligned16(depth) &&
+           aligned16(gn) && aligned16(gd);
 }
 
 typedef void (*VjpFn)(FrameArgs, const float *, float *, uint32_t);
@@ -188,6 +451,17 @@ extern "C" int bn_normals_vjp(const float *depth, int32_t height, int32_t width,
                           reinterpret_cast<const uint8_t *>(grad_depth));
     if (rc != BN_OK) return rc;
     if (height == 0 || width == 0) return BN_OK;
+    if (vjp4_layout(depth, width, depth_stride, 0, grad_normals, grad_depth, params->alpha)) {
+        const Vjp4Shape sh = vjp4_shape(height, width, 1, params->alpha);
+        Vjp4Fn fn = vjp4_kernel(params->alpha, sh.rb);
+        if (!fn) return BN_ERR_UNSUPPORTED;
+        FrameArgs f;
+        fill_frame_args(f, depth, height, width, depth_stride, fx, fy, cx, cy, params, nullptr,
+                        nullptr, nullptr, 1);
+        hipLaunchKernelGGL(fn, dim3(sh.strips * sh.bands), dim3(kBlock), 0, (hipStream_t)stream,
+                           f, grad_normals, grad_depth, sh.strips);
+        return hipGetLastError() == hipSuccess ? BN_OK : BN_ERR_DEVICE;
+    }
     const bool small = (int64_t)height * width < (1 << 20);
     const uint32_t TX = small ? 32u : 64u, TY = small ? 8u : 16u;
     VjpFn fn = small ? vjp_kernel_t<32, 8>(params->alpha) : vjp_kernel_t<64, 16>(params->alpha);
@@ -219,6 +493,19 @@ extern "C" int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t heigh
     if (rc != BN_OK || s.n == 0) return rc;
     s.f.normals = nullptr;  // the gradients travel in gn / gd
     s.f.mask = nullptr;
+    s.gn = grad_normals;
+    s.gd = grad_depth;
+    if (vjp4_layout(depth, width, depth_stride, depth_frame_stride, grad_normals, grad_depth,
+                    params->alpha)) {
+        const Vjp4Shape sh = vjp4_shape(height, width, s.n, params->alpha);
+        Vjp4StackFn fn = vjp4_stack_kernel(params->alpha, sh.rb);
+        if (!fn) return BN_ERR_UNSUPPORTED;
+        s.tiles_x = sh.strips;
+        s.tiles_per_frame = sh.strips * sh.bands;
+        const uint64_t grid = (uint64_t)s.tiles_per_frame * s.n;
+        hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kBlock), 0, (hipStream_t)stream, s);
+        return hipGetLastError() == hipSuccess ? BN_OK : BN_ERR_DEVICE;
+    }
     // each frame is small when the stack as a whole would not fill the chip
     // with the larger tiles
     const bool small = (int64_t)height * width * n < (1 << 20);
@@ -226,8 +513,6 @@ extern "C" int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t heigh
     VjpStackFn fn = small ? vjp_stack_kernel_t<32, 8>(params->alpha)
                           : vjp_stack_kernel_t<64, 16>(params->alpha);
     if (!fn) return BN_ERR_UNSUPPORTED;
-    s.gn = grad_normals;
-    s.gd = grad_depth;
     s.tiles_x = ((uint32_t)width + TX - 1) / TX;
     s.tiles_per_frame = s.tiles_x * (((uint32_t)height + TY - 1) / TY);
     const uint64_t grid = (uint64_t)s.tiles_per_frame * s.n;

@@ -128,7 +128,8 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: 
 
 def launches(reps: int = 20) -> None:
     """Each kernel of interest `reps` times: the three methods on one
-    1920x1080 frame, then the stacked forward and adjoint on 16 x 640x480."""
+    1920x1080 frame, then the stacked forward and adjoint (vector kernel, and
+    scalar tiles on a padded copy) on 16 x 640x480."""
     sys.path.insert(0, ROOT)
     import numpy as np
     import torch
@@ -143,19 +144,26 @@ def launches(reps: int = 20) -> None:
     intr = [x.intrinsics for x in scs]
     st = torch.from_numpy(np.stack([x.depth for x in scs])).cuda()
     g = torch.randn((16, 480, 640, 3), device="cuda")
+    # the same stack with a row stride of 641: the adjoint's scalar tiles
+    pad = torch.zeros((16, 480, 641), device="cuda")
+    pad[:, :, :640] = st
     for _ in range(reps):
         bn.estimate_normals_stack(st, intr, want_stats=False)
         bn.normals_vjp_stack(st, intr, g)
+        bn.normals_vjp_stack(pad[:, :, :640], intr, g)
     torch.cuda.synchronize()
     print("launches done", flush=True)
 
 
+# kernel -> (workload, pixels or outputs per dispatch)
 _VALU_WHAT = {
-    "bn::k_vec4<2, 1, 0>": "four-pair, 1920x1080, alpha 2",
-    "bn::k_vec4<2, 1, 1>": "pair removal, 1920x1080, alpha 2",
-    "bn::k_vec4<1, 1, 2>": "multi-scale K=3, 1920x1080, alpha 1",
-    "bn::k_stack<2, 0>": "four-pair stack, 16 x 640x480",
-    "bn::k_vjp_stack<2, 64, 16>": "adjoint stack, 16 x 640x480 (per output)",
+    "bn::k_vec4<2, 1, 0>": ("four-pair, 1920x1080, alpha 2", 2073600),
+    "bn::k_vec4<2, 1, 1>": ("pair removal, 1920x1080, alpha 2", 2073600),
+    "bn::k_vec4<1, 1, 2>": ("multi-scale K=3, 1920x1080, alpha 1", 2073600),
+    "bn::k_stack<2, 0>": ("four-pair stack, 16 x 640x480", 16 * 307200),
+    "bn::k_vjp4_stack<2, 8>": ("adjoint stack, 16 x 640x480, vector kernel", 16 * 307200),
+    "bn::k_vjp_stack<2, 64, 16>": ("adjoint stack, 16 x 640x480, scalar tiles (row stride 641)",
+                                   16 * 307200),
 }
 
 
@@ -174,10 +182,11 @@ def valu_summary(pmc_dir: str, out_md: str, cmd: str = "") -> str:
     lines = ["# VALU counters of the main kernels (rocprofv3 --pmc)", ""]
     if cmd:
         lines += ["Command:", "", "```", cmd, "```", ""]
-    lines += ["Medians over each kernel's dispatches.  Instruction counts are per wavefront "
-              "(64 lanes, 4 pixels or outputs per lane, so per pixel = per wavefront / 4); "
-              "VALUBusy is rocprofv3's derived share of the kernel's time in which the vector "
-              "ALUs issue; durations are under the profiler.", "",
+    lines += ["Medians over each kernel's dispatches.  Instruction counts are per wavefront; "
+              "VALU / pixel is the lane-instructions per pixel (or output) of the dispatch, "
+              "SQ_INSTS_VALU x 64 / pixels; VALUBusy is rocprofv3's derived share of the "
+              "kernel's time in which the vector ALUs issue; durations are under the "
+              "profiler.", "",
               "| kernel | workload | wavefronts | VALU / wavefront | VALU / pixel | "
               "SALU / wavefront | LDS / wavefront | VMEM reads / wavefront | VALUBusy | "
               "VALUUtilization | duration (profiled) |",
@@ -185,8 +194,10 @@ def valu_summary(pmc_dir: str, out_md: str, cmd: str = "") -> str:
     for k, c in agg.items():
         med = {n: statistics.median(v) for n, v in c.items()}
         w = med.get("SQ_WAVES", 1.0) or 1.0
-        lines.append(f"| `{k}` | {_VALU_WHAT.get(k, '')} | {w:.0f} | "
-                     f"{med['SQ_INSTS_VALU'] / w:.0f} | {med['SQ_INSTS_VALU'] / w / 4:.0f} | "
+        what, npx = _VALU_WHAT.get(k, ("", 0))
+        per_px = f"{med['SQ_INSTS_VALU'] * 64 / npx:.0f}" if npx else ""
+        lines.append(f"| `{k}` | {what} | {w:.0f} | "
+                     f"{med['SQ_INSTS_VALU'] / w:.0f} | {per_px} | "
                      f"{med['SQ_INSTS_SALU'] / w:.0f} | {med['SQ_INSTS_LDS'] / w:.1f} | "
                      f"{med['SQ_INSTS_VMEM_RD'] / w:.1f} | {med['VALUBusy']:.1f}% | "
                      f"{med['VALUUtilization']:.1f}% | {med['_dur']:.1f} us |")

@@ -150,3 +150,53 @@ def test_differentiation_batch_16():
         assert np.all(err <= vjp_tol(ref)), f"frame {i}: {err.max():.3g} vs {np.abs(ref).max():.3g}"
         worst = max(worst, float(err.max() / np.abs(ref).max()))
     log(f"differentiation batch: worst max|err|/max|grad| = {worst:.2e}")
+
+
+@pytest.mark.parametrize("alpha", [1, 2, 3, 4])
+@pytest.mark.parametrize("H,W", [(1, 4), (3, 8), (5, 4), (9, 12), (33, 252), (70, 256),
+                                 (97, 500), (130, 996), (480, 640), (257, 1992)])
+def test_vjp_vector_layout_equals_scalar_layout(alpha, H, W):
+    """Rows of whole float4 groups take the vector kernels (bands of rows
+    rolled per wavefront); a row stride that is not a multiple of 4 takes the
+    scalar tiles.  Both sum the same four contributions in the same order,
+    so the gradients agree bit for bit, at every width relative to the
+    248-column strips and every height relative to the bands."""
+    import torch
+    rng = np.random.default_rng(H * 7919 + W + alpha)
+    d = rng.uniform(1.0, 1.3, size=(H, W)).astype(np.float32)
+    d[rng.random((H, W)) < 0.02] = 0.0
+    g = torch.from_numpy(rng.standard_normal((H, W, 3)).astype(np.float32)).cuda()
+    fx, fy, cx, cy = 150.0, 160.0, (W - 1) / 2, (H - 1) / 2
+    vec = bn.normals_vjp(to_gpu(d), fx, fy, cx, cy, g, alpha, "rel", 1.1)
+    sca = bn.normals_vjp(to_gpu(d, 1), fx, fy, cx, cy, g, alpha, "rel", 1.1)
+    # an output 4 bytes off 16-byte alignment also takes the scalar tiles
+    buf = torch.empty(H * W + 1, dtype=torch.float32, device="cuda")
+    off = bn.normals_vjp(to_gpu(d), fx, fy, cx, cy, g, alpha, "rel", 1.1,
+                         grad_depth=buf[1:].view(H, W))
+    torch.cuda.synchronize()
+    assert torch.equal(vec.view(torch.int32), sca.view(torch.int32))
+    assert torch.equal(vec.view(torch.int32), off.view(torch.int32))
+    if H * W <= 70 * 256:
+        o = oracle.default()
+        codes = o.normals_f32(d, fx, fy, cx, cy, alpha, "rel", 1.1)["mask"]
+        ref = o.normals_vjp_f64(d, fx, fy, cx, cy, alpha, codes, g.cpu().numpy().astype(np.float64))
+        assert np.all(np.abs(vec.cpu().numpy() - ref) <= vjp_tol(ref))
+
+
+@pytest.mark.parametrize("alpha", [1, 2, 4])
+@pytest.mark.parametrize("n,H,W", [(1, 480, 640), (3, 61, 252), (16, 480, 640), (40, 120, 160)])
+def test_vjp_stack_vector_layout_equals_scalar_layout(alpha, n, H, W):
+    """The stack adjoint, vector kernels (frame stride a multiple of 4)
+    against scalar tiles (row stride W + 1), bit for bit."""
+    import torch
+    rng = np.random.default_rng(n * 1000 + H + alpha)
+    d = rng.uniform(1.0, 1.3, size=(n, H, W)).astype(np.float32)
+    g = torch.from_numpy(rng.standard_normal((n, H, W, 3)).astype(np.float32)).cuda()
+    intr = [(150.0 + 3 * k, 160.0, (W - 1) / 2, (H - 1) / 2) for k in range(n)]
+    dv = torch.from_numpy(d).cuda()
+    pad = torch.full((n, H, W + 1), float("nan"), device="cuda")
+    pad[:, :, :W] = dv
+    vec = bn.normals_vjp_stack(dv, intr, g, alpha, "rel", 1.1)
+    sca = bn.normals_vjp_stack(pad[:, :, :W], intr, g, alpha, "rel", 1.1)
+    torch.cuda.synchronize()
+    assert torch.equal(vec.view(torch.int32), sca.view(torch.int32))
