@@ -201,7 +201,7 @@ typedef struct bn_frame {
  * BN_ERR_UNSUPPORTED (alpha > BN_MAX_ALPHA, scales > BN_MAX_SCALES, or a
  * forced variant that the method or the buffers' layout does not allow:
  * the multi-scale method takes the vector variants only when alpha * scales
- * <= 8) or BN_ERR_DEVICE.
+ * <= 16) or BN_ERR_DEVICE.
  */
 int bn_estimate_normals(const float *depth, int32_t height, int32_t width,
                         int64_t depth_stride, float fx, float fy, float cx, float cy,

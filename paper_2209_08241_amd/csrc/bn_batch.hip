@@ -208,10 +208,12 @@ static SmallKernelFn small_kernel_m(int alpha) {
     return nullptr;
 }
 
-static SmallKernelFn small_kernel(int method, int alpha) {
+static SmallKernelFn small_kernel(int method, int alpha, int scales) {
+    method = kernel_method(method, alpha, scales);
     if (method == kFourPair) return small_kernel_m<kFourPair>(alpha);
     if (method == kPairRemoval) return small_kernel_m<kPairRemoval>(alpha);
     if (method == kMultiScale) return small_kernel_m<kMultiScale>(alpha);
+    if (method == kMultiScaleLong) return small_kernel_m<kMultiScaleLong>(alpha);
     return nullptr;
 }
 
@@ -230,10 +232,12 @@ static BatchKernelFn batch_kernel_m(int alpha) {
     return nullptr;
 }
 
-static BatchKernelFn batch_kernel(int method, int alpha) {
+static BatchKernelFn batch_kernel(int method, int alpha, int scales) {
+    method = kernel_method(method, alpha, scales);
     if (method == kFourPair) return batch_kernel_m<kFourPair>(alpha);
     if (method == kPairRemoval) return batch_kernel_m<kPairRemoval>(alpha);
     if (method == kMultiScale) return batch_kernel_m<kMultiScale>(alpha);
+    if (method == kMultiScaleLong) return batch_kernel_m<kMultiScaleLong>(alpha);
     return nullptr;
 }
 
@@ -540,8 +544,8 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
     int rc = check_params_args(params);
     if (rc != BN_OK) return rc;
     if (params->variant != VAR_AUTO) return BN_ERR_UNSUPPORTED;
-    BatchKernelFn fn = batch_kernel(params->method, params->alpha);
-    SmallKernelFn sfn = small_kernel(params->method, params->alpha);
+    BatchKernelFn fn = batch_kernel(params->method, params->alpha, params->scales);
+    SmallKernelFn sfn = small_kernel(params->method, params->alpha, params->scales);
     if (!fn || !sfn) return BN_ERR_UNSUPPORTED;
     uint64_t tiles = 0, pixels = 0;
     rc = count_frames(frames_host, n_frames, params, &tiles, &pixels);

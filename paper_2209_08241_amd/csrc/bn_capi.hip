@@ -40,7 +40,7 @@ int check_params_args(const bn_params *p) {
 }
 
 bool method_has_vec4(const bn_params *p) {
-    return p->method != BN_METHOD_MULTISCALE || p->alpha * p->scales <= BN_MAX_ALPHA;
+    return p->method != BN_METHOD_MULTISCALE || p->alpha * p->scales <= kMsVecReach;
 }
 
 int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, float fx,

@@ -116,6 +116,25 @@ __device__ __forceinline__ FrameArgs stack_frame(const StackArgs &s, uint32_t k)
 constexpr int kFourPair = BN_METHOD_FOUR_PAIR;
 constexpr int kPairRemoval = BN_METHOD_PAIR_REMOVAL;
 constexpr int kMultiScale = BN_METHOD_MULTISCALE;
+// Largest alpha * scales the multi-scale vector tiles serve: the row window
+// then spans at most 4 float4s right of the lane's own, and the vertical taps
+// at most min(8, 16 / alpha) float4s of the rows below.  Reaches up to
+// kMsShortReach take a separate instantiation with half the registers
+// (kernel method kMultiScaleLong marks the longer one; it is no public
+// method value).
+constexpr int kMsVecReach = 16;
+constexpr int kMsShortReach = 8;
+constexpr int kMultiScaleLong = 0x12;
+
+__host__ __device__ constexpr bool is_multiscale(int m) {
+    return m == kMultiScale || m == kMultiScaleLong;
+}
+
+// The kernel method of a request: the public method, with multi-scale
+// reaches beyond kMsShortReach on the longer instantiation.
+__host__ __device__ constexpr int kernel_method(int method, int alpha, int scales) {
+    return method == kMultiScale && alpha * scales > kMsShortReach ? kMultiScaleLong : method;
+}
 
 // A finite depth > 0: bit patterns 0x00000001 .. 0x7f7fffff.  Integer test,
 // so it does not depend on the denormal mode.

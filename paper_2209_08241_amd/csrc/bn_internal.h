@@ -35,7 +35,7 @@ int check_stats_arg(const bn_frame_stats *stats);
 bool vec4_layout(const float *depth, int32_t W, int64_t stride, const float *normals,
                  const uint8_t *mask);
 // True when the method can take vector tiles (multi-scale: alpha * scales
-// <= 8).
+// <= kMsVecReach).
 bool method_has_vec4(const bn_params *p);
 // Per-frame kernel arguments (derived constants included).
 void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t stride,

@@ -115,9 +115,11 @@ hipError_t launch_plain(int variant, int method, const FrameArgs &f, hipStream_t
         fn = plain_kernel<kPairRemoval>(variant, f.alpha);
     } else if (method == kMultiScale) {
         // scalar tiles take any offsets at run time; vector tiles serve
-        // alpha * scales <= 8
+        // alpha * scales <= kMsVecReach, in two instantiations
         fn = variant == VAR_SCALAR ? k_scalar<1, kMultiScale>
-                                   : plain_kernel<kMultiScale>(variant, f.alpha);
+             : kernel_method(method, f.alpha, f.scales) == kMultiScaleLong
+                 ? plain_kernel<kMultiScaleLong>(variant, f.alpha)
+                 : plain_kernel<kMultiScale>(variant, f.alpha);
     }
     if (!fn) return hipErrorInvalidValue;
     const uint64_t per_block = (uint64_t)kBlock * vi->groups_per_thread;

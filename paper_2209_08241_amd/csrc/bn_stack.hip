@@ -51,11 +51,14 @@ static StackFn stack_kernel_m(int alpha) {
     return nullptr;
 }
 
-static StackFn stack_kernel(int method, int alpha, bool vec) {
+static StackFn stack_kernel(int method, int alpha, int scales, bool vec) {
     if (method == kFourPair) return stack_kernel_m<kFourPair>(alpha);
     if (method == kPairRemoval) return stack_kernel_m<kPairRemoval>(alpha);
     // multi-scale scalar tiles take the offsets at run time
-    if (method == kMultiScale) return vec ? stack_kernel_m<kMultiScale>(alpha) : k_stack<1, kMultiScale>;
+    if (method == kMultiScale && !vec) return k_stack<1, kMultiScale>;
+    if (kernel_method(method, alpha, scales) == kMultiScaleLong)
+        return stack_kernel_m<kMultiScaleLong>(alpha);
+    if (method == kMultiScale) return stack_kernel_m<kMultiScale>(alpha);
     return nullptr;
 }
 
@@ -119,7 +122,7 @@ extern "C" int bn_estimate_normals_stack(const float *depth, int32_t n, int32_t 
                         params, normals, mask, stats, 4);
         if (rc != BN_OK) return rc;
     }
-    StackFn fn = stack_kernel(params->method, params->alpha, vec);
+    StackFn fn = stack_kernel(params->method, params->alpha, params->scales, vec);
     if (!fn) return BN_ERR_UNSUPPORTED;
     s.vec = vec ? 1u : 0u;
     s.tiles_per_frame = (s.f.nitems + kBlock - 1) / kBlock;

@@ -119,13 +119,13 @@ __device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec
     o.codes = codes;
 }
 
-// Multi-scale vector tile (alpha * scales <= 8): the taps lie right of and
+// Multi-scale vector tile (alpha * scales <= REACH): the taps lie right of and
 // below each pixel, so the row window extends to the right only and the
 // vertical taps are the float4s of rows y + i alpha.  Same arithmetic per
 // scale as the scalar tile.
-template <int A>
+template <int A, int REACH>
 __device__ __forceinline__ void vec4_eval_ms(const FrameArgs &f, uint32_t tile, Vec4Out &o) {
-    constexpr int KMAX = 8 / A;
+    constexpr int KMAX = REACH / A < BN_MAX_SCALES ? REACH / A : BN_MAX_SCALES;
     constexpr int RR = (A * KMAX + 3) / 4;  // float4s needed on the right
     const uint32_t t = threadIdx.x;
     const uint32_t lane = t & 63u;
@@ -200,8 +200,8 @@ __device__ __forceinline__ void vec4_eval_ms(const FrameArgs &f, uint32_t tile, 
 // The vector tile of method M.
 template <int A, int M>
 __device__ __forceinline__ void vec4_eval_method(const FrameArgs &f, uint32_t tile, Vec4Out &o) {
-    if constexpr (M == kMultiScale) {
-        vec4_eval_ms<A>(f, tile, o);
+    if constexpr (is_multiscale(M)) {
+        vec4_eval_ms<A, M == kMultiScaleLong ? kMsVecReach : kMsShortReach>(f, tile, o);
     } else {
         vec4_eval<A, M>(f, tile, o);
     }
@@ -265,7 +265,7 @@ __device__ __forceinline__ void scalar_eval(const FrameArgs &f, uint32_t tile, S
     r.live = live;
     uint32_t code = BN_INVALID;
     float nx = 0.f, ny = 0.f, nz = 0.f;
-    if (M == kMultiScale && live) {
+    if (is_multiscale(M) && live) {
         const uint32_t y = row_of(i, f.inv_gpr);
         const uint32_t x = i - y * f.gpr;
         const uint32_t reach = (uint32_t)(f.scales * f.alpha);
@@ -276,7 +276,7 @@ __device__ __forceinline__ void scalar_eval(const FrameArgs &f, uint32_t tile, S
         ny = o.ny;
         nz = o.nz;
         code = o.code;
-    } else if (M != kMultiScale && live) {
+    } else if (!is_multiscale(M) && live) {
         const uint32_t y = row_of(i, f.inv_gpr);
         const uint32_t x = i - y * f.gpr;
         const bool inside = (x >= (uint32_t)A) & (x + A < (uint32_t)f.W) &
@@ -337,7 +337,7 @@ __device__ __forceinline__ void scalar_count(const ScalarOut &r, uint32_t &cv, u
 
 // One whole tile of either kind, method M.  No workgroup barrier:
 // consecutive tiles of a workgroup may overlap freely.  The multi-scale
-// method takes vector tiles only when alpha * scales <= 8 (the host's
+// method takes vector tiles only when alpha * scales <= kMsVecReach (the host's
 // choice).
 template <int A, int M>
 __device__ __forceinline__ void run_tile(const FrameArgs &f, bool vec, uint32_t tile, TileLds &lds,

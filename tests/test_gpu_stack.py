@@ -62,7 +62,8 @@ def _assert_stack_equals_single(frames, depth, alpha, mode, tau, method="four_pa
     return N, M, ST
 
 
-@pytest.mark.parametrize("method,K", [("four_pair", 0), ("pair_removal", 0), ("multiscale", 2)])
+@pytest.mark.parametrize("method,K", [("four_pair", 0), ("pair_removal", 0), ("multiscale", 2),
+                                      ("multiscale", 5)])
 @pytest.mark.parametrize("mode,tau", [("rel", 4.0), ("abs", 2e-3), ("none", 1.0)])
 def test_stack_equals_single_frames(method, K, mode, tau):
     """Five 640x480 frames with five different intrinsics (the ABS threshold

@@ -52,14 +52,15 @@ def test_pair_removal_640(f640, alpha, mode, tau, variant):
 
 
 @pytest.mark.parametrize("alpha,K", [(1, 1), (1, 3), (2, 2), (2, 4), (3, 2), (4, 2), (8, 1),
-                                     (1, 8), (8, 8)])
+                                     (1, 8), (2, 5), (2, 8), (3, 3), (3, 5), (4, 4), (5, 3),
+                                     (7, 2), (8, 2), (3, 6), (8, 8)])
 @pytest.mark.parametrize("mode,tau", [("rel", 4.0), ("abs", 5e-3), ("none", 1.0)])
 def test_multiscale_640(f640, alpha, K, mode, tau):
     """Every variant the offsets allow against the oracle, and the vector
     tiles against the scalar tiles bit for bit."""
     log(f"multiscale 640x480 alpha={alpha} K={K} {mode}")
     s = f640
-    variants = (0, 1, 2, 3, 4) if alpha * K <= 8 else (0, 1)
+    variants = (0, 1, 2, 3, 4) if alpha * K <= 16 else (0, 1)
     scalar = run(s.depth, *s.intrinsics, alpha, mode, tau, MS, K, 1)
     for variant in variants:
         check(s.depth, *s.intrinsics, alpha, mode, tau, MS, K, variant,
@@ -69,15 +70,15 @@ def test_multiscale_640(f640, alpha, K, mode, tau):
             assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), f"v={variant}"
 
 
-@pytest.mark.parametrize("alpha,K", [(3, 3), (2, 5), (8, 2), (1, 8)])
+@pytest.mark.parametrize("alpha,K", [(3, 3), (2, 5), (8, 2), (1, 8), (3, 6), (8, 3), (5, 4)])
 def test_multiscale_vector_variants_need_short_reach(f640, alpha, K):
-    """Vector tiles serve alpha * K <= 8 only; beyond it the request for one
+    """Vector tiles serve alpha * K <= 16 only; beyond it the request for one
     is refused and the automatic choice is the scalar tile."""
     import torch
     s = f640
     d = to_gpu(s.depth)
     for v in (2, 3, 4):
-        if alpha * K <= 8:
+        if alpha * K <= 16:
             bn.estimate_normals(d, *s.intrinsics, alpha, method=MS, scales=K, variant=v)
             continue
         with pytest.raises(bn.BnError) as e:
