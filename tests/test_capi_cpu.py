@@ -62,9 +62,9 @@ def test_version_and_status_strings():
     (dict(method="pair_removal", scales=3), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
     (dict(method="multiscale", scales=0), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
     (dict(method="multiscale", scales=9), (8, 8, 8, 500.0, 500.0), bn.BN_ERR_UNSUPPORTED),
-    (dict(method="multiscale", alpha=3, scales=3, variant=2), (8, 8, 8, 500.0, 500.0),
+    (dict(method="multiscale", alpha=3, scales=6, variant=2), (8, 8, 8, 500.0, 500.0),
      bn.BN_ERR_UNSUPPORTED),
-    (dict(method="multiscale", alpha=2, scales=5, variant=4), (8, 8, 8, 500.0, 500.0),
+    (dict(method="multiscale", alpha=5, scales=4, variant=4), (8, 8, 8, 500.0, 500.0),
      bn.BN_ERR_UNSUPPORTED),
     (dict(), (8, 8, 7, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
     (dict(), (-1, 8, 8, 500.0, 500.0), bn.BN_ERR_INVALID_ARG),
