@@ -153,14 +153,15 @@ def test_differentiation_batch_16():
 
 
 @pytest.mark.parametrize("alpha", [1, 2, 3, 4])
-@pytest.mark.parametrize("H,W", [(1, 4), (3, 8), (5, 4), (9, 12), (33, 252), (70, 256),
-                                 (97, 500), (130, 996), (480, 640), (257, 1992)])
+@pytest.mark.parametrize("H,W", [(1, 4), (3, 8), (5, 4), (9, 12), (31, 224), (32, 228),
+                                 (33, 252), (64, 448), (65, 8), (70, 256), (97, 500),
+                                 (130, 996), (480, 640), (257, 1992)])
 def test_vjp_vector_layout_equals_scalar_layout(alpha, H, W):
     """Rows of whole float4 groups take the vector kernels (bands of rows
     rolled per wavefront); a row stride that is not a multiple of 4 takes the
     scalar tiles.  Both sum the same four contributions in the same order,
-    so the gradients agree bit for bit, at every width relative to the
-    248-column strips and every height relative to the bands."""
+    so the gradients agree bit for bit, at widths on and off the 224-column
+    strips and heights on and off the 16- and 32-row bands."""
     import torch
     rng = np.random.default_rng(H * 7919 + W + alpha)
     d = rng.uniform(1.0, 1.3, size=(H, W)).astype(np.float32)
