@@ -32,25 +32,27 @@ sys.path.insert(0, ROOT)
 BYTES_PER_PIXEL = 17          # 4 B depth in, 12 B normal + 1 B code out
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E, AMD published peak
 KERNEL_SOURCES = ["bn_device.h", "bn_tiles.h", "bn_kernels.hip", "bn_batch.hip"]
+ADJOINT_SOURCES = ["bn_device.h", "bn_adjoint.hip", "bn_stack.hip"]
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
-    """The measured kernels' sources and the flags they are compiled with."""
+def kernel_hash(sources=None) -> str:
+    """The measured kernels' sources (the forward kernels' by default) and the
+    flags they are compiled with."""
     from paper_2209_08241_amd.build import HIPCC_FLAGS
     h = hashlib.sha256()
     h.update(" ".join(HIPCC_FLAGS).encode())
-    for name in KERNEL_SOURCES:
+    for name in (KERNEL_SOURCES if sources is None else sources):
         p = os.path.join(ROOT, "paper_2209_08241_amd", "csrc", name)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, launch_pixels: int):
+def load_traffic(workload: str, launch_pixels: int, sources=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel sources; else None."""
     p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
@@ -60,7 +62,7 @@ def load_traffic(workload: str, launch_pixels: int):
         rec = json.load(open(p))
     except Exception:
         return None
-    if rec.get("kernel_hash") != kernel_hash():
+    if rec.get("kernel_hash") != kernel_hash(sources):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -526,10 +528,10 @@ def run_diff(args, torch, bn, scenes):
 
     us_adj_frames = timed_graph(per_frame, reps=5)
 
-    def rl(bpp, us):
+    def rl(bpp, us, traffic=None):
         a = bpp * n * px / (us * 1e-6) / 1e9
         return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": a / HBM_PEAK_GBS, "bytes_per_pixel": bpp}
+                "frac": a / HBM_PEAK_GBS, "bytes_per_pixel": bpp, "traffic": traffic}
 
     def step():
         x = depth.clone().requires_grad_(True)
@@ -555,7 +557,9 @@ def run_diff(args, torch, bn, scenes):
                         "forward + cosine loss vs the noise-free depth's normals + stacked "
                         "backward, eager, one host synchronisation per step",
             "adjoint_us_per_stack": us_adj, "adjoint_us_per_frame": us_adj / n,
-            "adjoint_mpix_s": n * px / us_adj, "adjoint_roofline": rl(adj_bytes, us_adj),
+            "adjoint_mpix_s": n * px / us_adj,
+            "adjoint_roofline": rl(adj_bytes, us_adj,
+                                   load_traffic("adjoint_stack16", n * px, ADJOINT_SOURCES)),
             "forward_us_per_stack": us_fwd, "forward_mpix_s": n * px / us_fwd,
             "forward_roofline": rl(fwd_bytes, us_fwd),
             "adjoint_single_frame_launches_us": us_adj_frames,

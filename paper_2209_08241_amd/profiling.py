@@ -4,11 +4,14 @@
     python -m paper_2209_08241_amd.profiling traffic --fetch <dir> --write <dir> \
         --kernel <substring> --pixels <per launch> --workload <name> --out <json> [--cmd "..."]
     python -m paper_2209_08241_amd.profiling launches [--reps N]
+    python -m paper_2209_08241_amd.profiling diff [--reps N] [--calibration-mib M]
     python -m paper_2209_08241_amd.profiling valu <counter_collection dir> <out.md> [--cmd "..."]
 
 `trace` turns a `--kernel-trace --stats` kernel_stats.csv into a short table.
 `launches` runs each kernel of interest N times on synthetic frames (a
 program for counter passes); `valu` tabulates a pass of VALU counters over it.
+`diff` runs the stacked forward and adjoint on 16 x 640x480 over six distinct
+buffer sets in turn (as bench.py times them), after a calibration copy.
 `traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs into HBM bytes
 per launch of one kernel.  Each counter is calibrated against the copy
 kernel that bench.py runs first (`--calibration-mib`): its bytes read and
@@ -48,7 +51,8 @@ def trace_summary(stats_csv: str, out_md: str, cmd: str = "") -> str:
         lines += ["Command:", "", "```", cmd, "```", ""]
     lines += ["| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        lines.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.3f} | "
+        name = r["Name"] if len(r["Name"]) <= 160 else r["Name"][:100] + " ..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.3f} | "
                      f"{float(r['MinNs']) / 1e3:.3f} | {float(r['MaxNs']) / 1e3:.3f} | "
                      f"{float(r['Percentage']):.2f} |")
     text = "\n".join(lines) + "\n"
@@ -85,9 +89,9 @@ def _calibration_values(disp, needle: str, count: int):
 
 def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: str,
             out_json: str, calib_bytes: int, calib_kernel: str, cmd: str = "",
-            calib_count: int = 4) -> dict:
+            calib_count: int = 4, bytes_per_pixel: int = 17, adjoint: bool = False) -> dict:
     sys.path.insert(0, ROOT)
-    from bench import kernel_hash   # noqa: E402  (same hash bench.py checks)
+    import bench   # noqa: E402  (the hash bench.py checks)
     f_rows = _csv_rows(fetch_dir, "*counter_collection.csv")
     w_rows = _csv_rows(write_dir, "*counter_collection.csv")
     f = _per_dispatch(f_rows, "FETCH_SIZE")
@@ -107,7 +111,7 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: 
         "workload": workload,
         "kernel": kernel,
         "pixels_per_launch": pixels,
-        "algorithmic_bytes_per_launch": 17 * pixels,
+        "algorithmic_bytes_per_launch": bytes_per_pixel * pixels,
         "hbm_read_bytes_per_launch": rb,
         "hbm_write_bytes_per_launch": wb,
         "hbm_bytes_per_launch": rb + wb,
@@ -118,7 +122,7 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: 
         "calibration": f"{calib_kernel} (largest {calib_count} dispatches): {calib_bytes} bytes "
                        f"read and written each",
         "dispatches": {"fetch": len(fk), "write": len(wk)},
-        "kernel_hash": kernel_hash(),
+        "kernel_hash": bench.kernel_hash(bench.ADJOINT_SOURCES if adjoint else None),
         "command": cmd,
     }
     with open(out_json, "w") as fh:
@@ -156,6 +160,42 @@ def launches(reps: int = 20) -> None:
 
 
 # kernel -> (workload, pixels or outputs per dispatch)
+def diff_launches(reps: int = 12, calibration_mib: int = 1024) -> None:
+    """The differentiation workload of bench.py under a profiler: a
+    calibration copy (4 times), then the stacked forward and adjoint on
+    16 x 640x480, `reps` calls each, cycling over six buffer sets."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import torch
+    import paper_2209_08241_amd as bn
+    from synth import scenes
+    if calibration_mib:
+        src = torch.ones(calibration_mib * (1 << 20) // 4, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    sets = 6
+    scs = [scenes.frame_640x480(seed=2000 + i) for i in range(16)]
+    intr = [x.intrinsics for x in scs]
+    d0 = torch.from_numpy(np.stack([x.depth for x in scs])).cuda()
+    g0 = torch.randn((16, 480, 640, 3), device="cuda")
+    D = [d0.clone() for _ in range(sets)]
+    G = [g0.clone() for _ in range(sets)]
+    GD = [torch.empty((16, 480, 640), device="cuda") for _ in range(sets)]
+    N = [torch.empty((16, 480, 640, 3), device="cuda") for _ in range(sets)]
+    M = [torch.empty((16, 480, 640), dtype=torch.uint8, device="cuda") for _ in range(sets)]
+    for r in range(reps):
+        i = r % sets
+        bn.estimate_normals_stack(D[i], intr, normals=N[i], mask=M[i], want_stats=False)
+    for r in range(reps):
+        i = r % sets
+        bn.normals_vjp_stack(D[i], intr, G[i], grad_depth=GD[i])
+    torch.cuda.synchronize()
+    print("diff launches done", flush=True)
+
+
 _VALU_WHAT = {
     "bn::k_vec4<2, 1, 0>": ("four-pair, 1920x1080, alpha 2", 2073600),
     "bn::k_vec4<2, 1, 1>": ("pair removal, 1920x1080, alpha 2", 2073600),
@@ -225,8 +265,14 @@ def main():
     p.add_argument("--calib-kernel", default="copyBuffer")
     p.add_argument("--calib-count", type=int, default=4)
     p.add_argument("--cmd", default="")
+    p.add_argument("--bytes-per-pixel", type=int, default=17)
+    p.add_argument("--adjoint", action="store_true",
+                   help="hash the adjoint's sources (bench.ADJOINT_SOURCES)")
     ln = sub.add_parser("launches")
     ln.add_argument("--reps", type=int, default=20)
+    df = sub.add_parser("diff")
+    df.add_argument("--reps", type=int, default=12)
+    df.add_argument("--calibration-mib", type=int, default=1024)
     v = sub.add_parser("valu")
     v.add_argument("pmc_dir")
     v.add_argument("out_md")
@@ -234,13 +280,16 @@ def main():
     a = ap.parse_args()
     if a.what == "launches":
         launches(a.reps)
+    elif a.what == "diff":
+        diff_launches(a.reps, a.calibration_mib)
     elif a.what == "valu":
         print(valu_summary(a.pmc_dir, a.out_md, a.cmd))
     elif a.what == "trace":
         print(trace_summary(a.stats_csv, a.out_md, a.cmd))
     else:
         print(json.dumps(traffic(a.fetch, a.write, a.kernel, a.pixels, a.workload, a.out,
-                                 a.calib_bytes, a.calib_kernel, a.cmd, a.calib_count), indent=1))
+                                 a.calib_bytes, a.calib_kernel, a.cmd, a.calib_count,
+                                 a.bytes_per_pixel, a.adjoint), indent=1))
 
 
 if __name__ == "__main__":

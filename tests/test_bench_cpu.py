@@ -28,10 +28,10 @@ def test_traffic_summaries_follow_the_kernel_sources(monkeypatch, tmp_path):
     prof.mkdir()
     (prof / "traffic_demo.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "kernel_hash", lambda: "a" * 16)
+    monkeypatch.setattr(bench, "kernel_hash", lambda sources=None: "a" * 16)
     assert bench.load_traffic("demo", 1) == 4.5e7
     assert bench.load_traffic("missing", 1) is None
-    monkeypatch.setattr(bench, "kernel_hash", lambda: "0" * 16)
+    monkeypatch.setattr(bench, "kernel_hash", lambda sources=None: "0" * 16)
     assert bench.load_traffic("demo", 1) is None
 
 
@@ -48,3 +48,8 @@ def test_one_gpu_only():
     assert r.returncode == 2
     assert "one GPU" in (r.stdout + r.stderr)
     assert not r.stdout.strip().startswith("{")
+
+
+def test_adjoint_summary_hashes_the_adjoint_sources():
+    assert bench.kernel_hash(bench.ADJOINT_SOURCES) != bench.kernel_hash()
+    assert "bn_adjoint.hip" in bench.ADJOINT_SOURCES
