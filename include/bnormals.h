@@ -219,7 +219,10 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width,
  *   grad_normals [height][width][3] binary32, dense
  *   grad_depth   [height][width] binary32 out, dense, overwritten
  * Same argument rules and errors as bn_estimate_normals (params->variant 0);
- * BN_ERR_UNSUPPORTED for a method other than BN_METHOD_FOUR_PAIR.
+ * BN_ERR_UNSUPPORTED for a method other than BN_METHOD_FOUR_PAIR.  Width and
+ * depth_stride multiples of 4, the three arrays 16-byte aligned and alpha
+ * <= 4 take a vector kernel; any other layout takes scalar tiles.  Both sum
+ * each gradient's four contributions in the same order: the same bits.
  */
 int bn_normals_vjp(const float *depth, int32_t height, int32_t width, int64_t depth_stride,
                    float fx, float fy, float cx, float cy, const bn_params *params,
