@@ -342,23 +342,20 @@ __global__ __launch_bounds__(kBlock) void k_vjp4_stack(const StackArgs s) {
                      t % s.tiles_x, t / s.tiles_x);
 }
 
-// Rows per wavefront: 8, or 4 (a <= 2) when the grid of 8-row bands would
-// hold fewer than kVjpMinGroups workgroups (measured: a 1920x1080 frame,
-// 272 workgroups of 8-row bands, 11.6 us with 4-row bands against 14.9 us;
-// 16 frames of 640x480, 720 workgroups, 21.9 us with 8-row bands against
-// 22.8 us).
-constexpr uint64_t kVjpMinGroups = 512;
-
+// Rows per wavefront: the fewest that the band edges allow (RB >= 2a), so
+// that the grid holds the most workgroups: 4 for a <= 2, 8 for a = 3, 4.
+// (Measured with six buffer sets: 8-row bands for a = 2 took 14.9 against
+// 11.6 us on a 1920x1080 frame, 35.9 against 31.2 us on 64 frames of
+// 320x240, and the same on 16 frames of 640x480 or 4 of 1920x1080.)
 struct Vjp4Shape {
     int rb;
     uint32_t strips, bands;
 };
 
-static Vjp4Shape vjp4_shape(int32_t H, int32_t W, int32_t n, int alpha) {
+static Vjp4Shape vjp4_shape(int32_t H, int32_t W, int alpha) {
     Vjp4Shape s;
     s.strips = (uint32_t)((W / 4 + kVjpGroups - 1) / kVjpGroups);
-    const uint64_t big = (uint64_t)s.strips * (uint64_t)((H + 31) / 32) * (uint64_t)n;
-    s.rb = (alpha <= 2 && big < kVjpMinGroups) ? 4 : 8;
+    s.rb = alpha <= 2 ? 4 : 8;
     s.bands = (uint32_t)((H + 4 * s.rb - 1) / (4 * s.rb));
     return s;
 }
@@ -373,8 +370,6 @@ static Vjp4Fn vjp4_kernel(int a, int rb) {
         return nullptr;
     }
     switch (a) {
-        case 1: return k_vjp4<1, 8>;
-        case 2: return k_vjp4<2, 8>;
         case 3: return k_vjp4<3, 8>;
         case 4: return k_vjp4<4, 8>;
     }
@@ -388,8 +383,6 @@ static Vjp4StackFn vjp4_stack_kernel(int a, int rb) {
         return nullptr;
     }
     switch (a) {
-        case 1: return k_vjp4_stack<1, 8>;
-        case 2: return k_vjp4_stack<2, 8>;
         case 3: return k_vjp4_stack<3, 8>;
         case 4: return k_vjp4_stack<4, 8>;
     }
@@ -458,7 +451,7 @@ extern "C" int bn_normals_vjp(const float *depth, int32_t height, int32_t width,
     if (rc != BN_OK) return rc;
     if (height == 0 || width == 0) return BN_OK;
     if (vjp4_layout(depth, width, depth_stride, 0, grad_normals, grad_depth, params->alpha)) {
-        const Vjp4Shape sh = vjp4_shape(height, width, 1, params->alpha);
+        const Vjp4Shape sh = vjp4_shape(height, width, params->alpha);
         Vjp4Fn fn = vjp4_kernel(params->alpha, sh.rb);
         if (!fn) return BN_ERR_UNSUPPORTED;
         FrameArgs f;
@@ -503,7 +496,7 @@ extern "C" int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t heigh
     s.gd = grad_depth;
     if (vjp4_layout(depth, width, depth_stride, depth_frame_stride, grad_normals, grad_depth,
                     params->alpha)) {
-        const Vjp4Shape sh = vjp4_shape(height, width, s.n, params->alpha);
+        const Vjp4Shape sh = vjp4_shape(height, width, params->alpha);
         Vjp4StackFn fn = vjp4_stack_kernel(params->alpha, sh.rb);
         if (!fn) return BN_ERR_UNSUPPORTED;
         s.tiles_x = sh.strips;
