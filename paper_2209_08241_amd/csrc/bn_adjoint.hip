@@ -19,8 +19,9 @@
 //
 // Vector kernels (rows of whole float4 groups, a <= 4): a workgroup owns a
 // strip of 56 float4 groups (224 columns: the strip's gradient rows start on
-// 128-byte lines, and so do its cotangent rows) and a band of 4 RB rows, RB
-// rows per wavefront.  Lane l evaluates group 56 s - 4 + l of each row (its
+// 128-byte lines, and so do its cotangent rows) and a band of NW RB rows,
+// RB rows per wavefront, NW = 4 or 8 wavefronts.  Lane l evaluates group
+// 56 s - 4 + l of each row (its
 // codes and tap gradients, from float4 loads), so lanes 4..59 own the
 // strip's outputs and lanes 3 and 60 are the halo; the horizontal taps and
 // the tap-2 / tap-4 gradients move between neighbouring lanes by DPP.  Each
@@ -28,7 +29,7 @@
 // registers; the a rows next to a neighbouring wavefront's rows are finished
 // after one workgroup barrier, from the neighbour's gradients left in LDS,
 // and the 2a rows above and below the band are evaluated once, shared out
-// over the four wavefronts.  Per output: 1 + a / (2 RB) row evaluations.
+// over the wavefronts.  Per output: 1 + 2a / (NW RB) row evaluations.
 //
 // Scalar kernels (any layout, any a): a workgroup owns a TX x TY tile of
 // output depths (64 x 16, or 32 x 8 on frames under 2^20 pixels, which
@@ -269,21 +270,21 @@ __device__ __forceinline__ RowGrads vjp4_row(const FrameArgs &f, const float *__
 }
 
 // Strip `strip`, band `band` of one frame (see the top of the file).
-template <int A, int RB>
+template <int A, int RB, int NW>
 __device__ __forceinline__ void vjp4_band(const FrameArgs &f, const float *__restrict__ gn,
                                           float *__restrict__ gd, uint32_t strip,
                                           uint32_t band) {
-    static_assert(A >= 1 && A <= 4 && RB >= 2 * A, "band rows per wavefront");
+    static_assert(A >= 1 && A <= 4 && RB >= 2 * A && (NW == 4 || NW == 8), "band shape");
     // x3[w]: tap-3 gradients of the a rows above wavefront w's rows;
     // x5[w]: tap-5 gradients of the a rows below wavefront w-1's rows.
-    __shared__ f4 x3[5][A][64];
-    __shared__ f4 x5[5][A][64];
+    __shared__ f4 x3[NW + 1][A][64];
+    __shared__ f4 x5[NW + 1][A][64];
     const uint32_t lane = threadIdx.x & 63u;
     // the wavefront index, uniform: row addresses and bounds are scalar
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int x0 = 4 * ((int)(strip * kVjpGroups + lane) - kVjpLead);
     const int xl = min(max(x0, 0), f.W - 4);
-    const int y0 = (int)(band * 4u * RB);
+    const int y0 = (int)(band * (uint32_t)(NW * RB));
     const int yw = y0 + (int)w * RB;
     const bool out_lane = (lane >= (uint32_t)kVjpLead) &
                           (lane < (uint32_t)(kVjpLead + kVjpGroups)) & (x0 < f.W);
@@ -292,11 +293,11 @@ __device__ __forceinline__ void vjp4_band(const FrameArgs &f, const float *__res
             __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(gd + (int64_t)y * f.W + x0));
     };
     // The band's 2a outer rows, dealt round the wavefronts.
-    for (int k = (int)w; k < 2 * A; k += 4) {
+    for (int k = (int)w; k < 2 * A; k += NW) {
         if (k < A) {
             x3[0][k][lane] = vjp4_row<A>(f, gn, y0 - A + k, x0, xl, lane).g3;
         } else {
-            x5[4][k - A][lane] = vjp4_row<A>(f, gn, y0 + 4 * RB + (k - A), x0, xl, lane).g5;
+            x5[NW][k - A][lane] = vjp4_row<A>(f, gn, y0 + NW * RB + (k - A), x0, xl, lane).g5;
         }
     }
     f4 h[RB], g3[RB], top5[A], bot[A];
@@ -324,22 +325,22 @@ __device__ __forceinline__ void vjp4_band(const FrameArgs &f, const float *__res
     for (int j = 0; j < A; ++j) put(yw + RB - A + j, bot[j] + x5[w + 1][j][lane]);
 }
 
-template <int A, int RB>
-__global__ __launch_bounds__(kBlock) void k_vjp4(FrameArgs f, const float *__restrict__ gn,
-                                                 float *__restrict__ gd, uint32_t strips) {
+template <int A, int RB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_vjp4(FrameArgs f, const float *__restrict__ gn,
+                                                  float *__restrict__ gd, uint32_t strips) {
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
-    vjp4_band<A, RB>(f, gn, gd, b % strips, b / strips);
+    vjp4_band<A, RB, NW>(f, gn, gd, b % strips, b / strips);
 }
 
 // A stack: workgroup b takes band-strip b % T of frame b / T.
-template <int A, int RB>
-__global__ __launch_bounds__(kBlock) void k_vjp4_stack(const StackArgs s) {
+template <int A, int RB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_vjp4_stack(const StackArgs s) {
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t k = b / s.tiles_per_frame;
     const uint32_t t = b - k * s.tiles_per_frame;
     const int64_t npix = (int64_t)s.f.npix;
-    vjp4_band<A, RB>(stack_frame(s, k), s.gn + (int64_t)k * npix * 3, s.gd + (int64_t)k * npix,
-                     t % s.tiles_x, t / s.tiles_x);
+    vjp4_band<A, RB, NW>(stack_frame(s, k), s.gn + (int64_t)k * npix * 3,
+                         s.gd + (int64_t)k * npix, t % s.tiles_x, t / s.tiles_x);
 }
 
 // Rows per wavefront: the fewest that the band edges allow (RB >= 2a), so
@@ -347,46 +348,59 @@ __global__ __launch_bounds__(kBlock) void k_vjp4_stack(const StackArgs s) {
 // (Measured with six buffer sets: 8-row bands for a = 2 took 14.9 against
 // 11.6 us on a 1920x1080 frame, 35.9 against 31.2 us on 64 frames of
 // 320x240, and the same on 16 frames of 640x480 or 4 of 1920x1080.)
+// Wavefronts per workgroup: 8 (a band of 8 RB rows shares its 2a outer rows
+// among more rows) when that still gives kVjpWide workgroups, else 4
+// (measured: 16 x 640x480 25.4 against 26.1 us, 4 x 1920x1080 39.5
+// against 41.2; one 1920x1080 frame, 306 workgroups of 8, 13.4 against
+// 12.4 us).
+constexpr uint64_t kVjpWide = 512;
+
 struct Vjp4Shape {
-    int rb;
+    int rb, nw;
     uint32_t strips, bands;
 };
 
-static Vjp4Shape vjp4_shape(int32_t H, int32_t W, int alpha) {
+static Vjp4Shape vjp4_shape(int32_t H, int32_t W, int32_t n, int alpha) {
     Vjp4Shape s;
     s.strips = (uint32_t)((W / 4 + kVjpGroups - 1) / kVjpGroups);
     s.rb = alpha <= 2 ? 4 : 8;
-    s.bands = (uint32_t)((H + 4 * s.rb - 1) / (4 * s.rb));
+    const uint64_t wide = (uint64_t)s.strips * (uint64_t)((H + 8 * s.rb - 1) / (8 * s.rb)) * n;
+    s.nw = wide >= kVjpWide ? 8 : 4;
+    s.bands = (uint32_t)((H + s.nw * s.rb - 1) / (s.nw * s.rb));
     return s;
 }
 
 typedef void (*Vjp4Fn)(FrameArgs, const float *, float *, uint32_t);
 typedef void (*Vjp4StackFn)(const StackArgs);
 
-static Vjp4Fn vjp4_kernel(int a, int rb) {
-    if (rb == 4) {
-        if (a == 1) return k_vjp4<1, 4>;
-        if (a == 2) return k_vjp4<2, 4>;
-        return nullptr;
-    }
+template <int NW>
+static Vjp4Fn vjp4_kernel_w(int a) {
     switch (a) {
-        case 3: return k_vjp4<3, 8>;
-        case 4: return k_vjp4<4, 8>;
+        case 1: return k_vjp4<1, 4, NW>;
+        case 2: return k_vjp4<2, 4, NW>;
+        case 3: return k_vjp4<3, 8, NW>;
+        case 4: return k_vjp4<4, 8, NW>;
     }
     return nullptr;
 }
 
-static Vjp4StackFn vjp4_stack_kernel(int a, int rb) {
-    if (rb == 4) {
-        if (a == 1) return k_vjp4_stack<1, 4>;
-        if (a == 2) return k_vjp4_stack<2, 4>;
-        return nullptr;
-    }
+template <int NW>
+static Vjp4StackFn vjp4_stack_kernel_w(int a) {
     switch (a) {
-        case 3: return k_vjp4_stack<3, 8>;
-        case 4: return k_vjp4_stack<4, 8>;
+        case 1: return k_vjp4_stack<1, 4, NW>;
+        case 2: return k_vjp4_stack<2, 4, NW>;
+        case 3: return k_vjp4_stack<3, 8, NW>;
+        case 4: return k_vjp4_stack<4, 8, NW>;
     }
     return nullptr;
+}
+
+static Vjp4Fn vjp4_kernel(const Vjp4Shape &sh, int a) {
+    return sh.nw == 8 ? vjp4_kernel_w<8>(a) : vjp4_kernel_w<4>(a);
+}
+
+static Vjp4StackFn vjp4_stack_kernel(const Vjp4Shape &sh, int a) {
+    return sh.nw == 8 ? vjp4_stack_kernel_w<8>(a) : vjp4_stack_kernel_w<4>(a);
 }
 
 static bool aligned16(const void *p) { return ((uintptr_t)p % 16) == 0; }
@@ -451,13 +465,13 @@ extern "C" int bn_normals_vjp(const float *depth, int32_t height, int32_t width,
     if (rc != BN_OK) return rc;
     if (height == 0 || width == 0) return BN_OK;
     if (vjp4_layout(depth, width, depth_stride, 0, grad_normals, grad_depth, params->alpha)) {
-        const Vjp4Shape sh = vjp4_shape(height, width, params->alpha);
-        Vjp4Fn fn = vjp4_kernel(params->alpha, sh.rb);
+        const Vjp4Shape sh = vjp4_shape(height, width, 1, params->alpha);
+        Vjp4Fn fn = vjp4_kernel(sh, params->alpha);
         if (!fn) return BN_ERR_UNSUPPORTED;
         FrameArgs f;
         fill_frame_args(f, depth, height, width, depth_stride, fx, fy, cx, cy, params, nullptr,
                         nullptr, nullptr, 1);
-        hipLaunchKernelGGL(fn, dim3(sh.strips * sh.bands), dim3(kBlock), 0, (hipStream_t)stream,
+        hipLaunchKernelGGL(fn, dim3(sh.strips * sh.bands), dim3(64 * sh.nw), 0, (hipStream_t)stream,
                            f, grad_normals, grad_depth, sh.strips);
         return hipGetLastError() == hipSuccess ? BN_OK : BN_ERR_DEVICE;
     }
@@ -496,13 +510,13 @@ extern "C" int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t heigh
     s.gd = grad_depth;
     if (vjp4_layout(depth, width, depth_stride, depth_frame_stride, grad_normals, grad_depth,
                     params->alpha)) {
-        const Vjp4Shape sh = vjp4_shape(height, width, params->alpha);
-        Vjp4StackFn fn = vjp4_stack_kernel(params->alpha, sh.rb);
+        const Vjp4Shape sh = vjp4_shape(height, width, s.n, params->alpha);
+        Vjp4StackFn fn = vjp4_stack_kernel(sh, params->alpha);
         if (!fn) return BN_ERR_UNSUPPORTED;
         s.tiles_x = sh.strips;
         s.tiles_per_frame = sh.strips * sh.bands;
         const uint64_t grid = (uint64_t)s.tiles_per_frame * s.n;
-        hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kBlock), 0, (hipStream_t)stream, s);
+        hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(64 * sh.nw), 0, (hipStream_t)stream, s);
         return hipGetLastError() == hipSuccess ? BN_OK : BN_ERR_DEVICE;
     }
     // each frame is small when the stack as a whole would not fill the chip

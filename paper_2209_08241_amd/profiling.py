@@ -201,7 +201,7 @@ _VALU_WHAT = {
     "bn::k_vec4<2, 1, 1>": ("pair removal, 1920x1080, alpha 2", 2073600),
     "bn::k_vec4<1, 1, 2>": ("multi-scale K=3, 1920x1080, alpha 1", 2073600),
     "bn::k_stack<2, 0>": ("four-pair stack, 16 x 640x480", 16 * 307200),
-    "bn::k_vjp4_stack<2, 4>": ("adjoint stack, 16 x 640x480, vector kernel", 16 * 307200),
+    "bn::k_vjp4_stack<2, 4, 8>": ("adjoint stack, 16 x 640x480, vector kernel", 16 * 307200),
     "bn::k_vjp_stack<2, 64, 16>": ("adjoint stack, 16 x 640x480, scalar tiles (row stride 641)",
                                    16 * 307200),
 }

@@ -184,11 +184,13 @@ def test_vjp_vector_layout_equals_scalar_layout(alpha, H, W):
         assert np.all(np.abs(vec.cpu().numpy() - ref) <= vjp_tol(ref))
 
 
-@pytest.mark.parametrize("alpha", [1, 2, 4])
-@pytest.mark.parametrize("n,H,W", [(1, 480, 640), (3, 61, 252), (16, 480, 640), (40, 120, 160)])
+@pytest.mark.parametrize("alpha", [1, 2, 3, 4])
+@pytest.mark.parametrize("n,H,W", [(1, 480, 640), (3, 61, 252), (16, 480, 640), (40, 120, 160),
+                                   (64, 240, 320)])
 def test_vjp_stack_vector_layout_equals_scalar_layout(alpha, n, H, W):
-    """The stack adjoint, vector kernels (frame stride a multiple of 4)
-    against scalar tiles (row stride W + 1), bit for bit."""
+    """The stack adjoint, vector kernels (frame stride a multiple of 4; bands
+    of four or eight wavefronts by the size of the stack) against scalar
+    tiles (row stride W + 1), bit for bit."""
     import torch
     rng = np.random.default_rng(n * 1000 + H + alpha)
     d = rng.uniform(1.0, 1.3, size=(n, H, W)).astype(np.float32)
