@@ -125,7 +125,8 @@ def test_poisson_load_completes(serve_frames):
         assert srv.stats()["completed"] == 400
 
 
-@pytest.mark.parametrize("method,alpha,K", [("pair_removal", 2, 0), ("multiscale", 1, 3)])
+@pytest.mark.parametrize("method,alpha,K", [("pair_removal", 2, 0), ("multiscale", 1, 3),
+                                           ("multiscale", 3, 4)])
 def test_methods_served_equal_alone(serve_frames, method, alpha, K):
     import torch
     frames = serve_frames[:4]
