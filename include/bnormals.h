@@ -217,7 +217,7 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width,
  * constant 0).  d1 does not enter Eqs. 10-12, so a pixel's own depth gets
  * gradient only through its four neighbours' normals.
  *   grad_normals [height][width][3] binary32, dense
- *   grad_depth   [height][width] binary32 out, dense, overwritten
+ *   grad_depth   [height][width] binary32 out, dense, 4-byte aligned, overwritten
  * Same argument rules and errors as bn_estimate_normals (params->variant 0);
  * BN_ERR_UNSUPPORTED for a method other than BN_METHOD_FOUR_PAIR.  Width and
  * depth_stride multiples of 4, the three arrays 16-byte aligned and alpha

@@ -464,6 +464,7 @@ extern "C" int bn_normals_vjp(const float *depth, int32_t height, int32_t width,
                           reinterpret_cast<const uint8_t *>(grad_depth));
     if (rc != BN_OK) return rc;
     if (height == 0 || width == 0) return BN_OK;
+    if ((uintptr_t)grad_depth % 4) return BN_ERR_INVALID_ARG;
     if (vjp4_layout(depth, width, depth_stride, 0, grad_normals, grad_depth, params->alpha)) {
         const Vjp4Shape sh = vjp4_shape(height, width, 1, params->alpha);
         Vjp4Fn fn = vjp4_kernel(sh, params->alpha);

@@ -104,6 +104,17 @@ def test_adjoint_only_for_the_four_pair_method():
         assert rc == bn.BN_ERR_UNSUPPORTED
 
 
+def test_adjoint_alignment_checked_before_launch():
+    L = bn.lib()
+    p = bn.make_params()
+    for depth, gn, gd in ((0x10002, 0x20000, 0x30000), (0x10000, 0x20002, 0x30000),
+                          (0x10000, 0x20000, 0x30002)):
+        rc = L.bn_normals_vjp(ctypes.c_void_p(depth), 8, 8, 8, ctypes.c_float(500.0),
+                              ctypes.c_float(500.0), ctypes.c_float(3.5), ctypes.c_float(3.5),
+                              ctypes.byref(p), ctypes.c_void_p(gn), ctypes.c_void_p(gd), None)
+        assert rc == bn.BN_ERR_INVALID_ARG, (hex(depth), hex(gn), hex(gd))
+
+
 def test_null_pointers_rejected():
     p = bn.make_params()
     assert bn.raw_estimate_normals(0, 8, 8, 8, 500.0, 500.0, 1.0, 1.0, p, 0x20000, 0x30000, 0) \
