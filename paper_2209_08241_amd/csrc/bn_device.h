@@ -408,8 +408,10 @@ __device__ __forceinline__ f4 from_right(f4 v) {
     return f4{from_right(v.x), from_right(v.y), from_right(v.z), from_right(v.w)};
 }
 
+// The builtin ballot takes the lane mask of a compare as it is (HIP's
+// __ballot takes an int and forms a 0/1 value per lane first).
 __device__ __forceinline__ uint32_t wave_count(bool pred) {
-    return (uint32_t)__popcll(__ballot(pred));
+    return (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(pred));
 }
 
 // ---------------------------------------------------------------------------

@@ -55,23 +55,25 @@ __device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec
     const uint32_t i = tile * kBlock + t;
     const bool live = i < f.nitems;
     o.live = live;
-    uint32_t y = 0, x0 = 0;
-    if (live) {
-        y = row_of(i, f.inv_gpr);
-        x0 = (i - y * f.gpr) * 4u;
-    }
+    // Every load is unconditional: a lane past the frame's last item takes
+    // the last item's position, and a row A above or below that leaves the
+    // frame is replaced by row y itself.  What such a load brings in only
+    // reaches pixels that are not inside (or not live), whose codes are
+    // INVALID whatever it holds.
+    const uint32_t il = live ? i : f.nitems - 1u;
+    const uint32_t y = row_of(il, f.inv_gpr);
+    const uint32_t x0 = (il - y * f.gpr) * 4u;
     const float *rp = f.depth + (int64_t)y * f.stride;
     const bool rows_in = live & (y >= (uint32_t)A) & (y + A < (uint32_t)f.H);
-    f4 c = {0.f, 0.f, 0.f, 0.f}, up = {0.f, 0.f, 0.f, 0.f}, dn = {0.f, 0.f, 0.f, 0.f};
-    if (live) c = *reinterpret_cast<const f4 *>(rp + x0);
-    if (rows_in) {
-        up = *reinterpret_cast<const f4 *>(rp - (int64_t)A * f.stride + x0);
-        dn = *reinterpret_cast<const f4 *>(rp + (int64_t)A * f.stride + x0);
-    }
+    const int64_t su = y >= (uint32_t)A ? (int64_t)A * f.stride : 0;
+    const int64_t sd = y + A < (uint32_t)f.H ? (int64_t)A * f.stride : 0;
+    const f4 c = *reinterpret_cast<const f4 *>(rp + x0);
+    const f4 up = *reinterpret_cast<const f4 *>(rp - su + x0);
+    const f4 dn = *reinterpret_cast<const f4 *>(rp + sd + x0);
     // Row window x0-4R .. x0+4+4R-1.  Neighbouring float4s come from the
     // adjacent lanes; the first / last lane of the wave loads its missing
-    // float4 itself.  Values taken across a row end only feed border
-    // pixels, which are INVALID whatever they hold.
+    // float4 itself (clamped into the row).  Values taken across a row end
+    // only feed border pixels, which are INVALID whatever they hold.
     float row[Win<A>::N];
     row[4 * R + 0] = c.x;
     row[4 * R + 1] = c.y;
@@ -82,14 +84,8 @@ __device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec
     for (int k = 1; k <= R; ++k) {
         lk = from_left(lk);
         rk = from_right(rk);
-        if (lane == 0) {
-            const int xs = (int)x0 - 4 * k;
-            lk = (live && xs >= 0) ? *reinterpret_cast<const f4 *>(rp + xs) : f4{0.f, 0.f, 0.f, 0.f};
-        }
-        if (lane == 63) {
-            const int xs = (int)x0 + 4 * k;
-            rk = (live && xs < f.W) ? *reinterpret_cast<const f4 *>(rp + xs) : f4{0.f, 0.f, 0.f, 0.f};
-        }
+        if (lane == 0) lk = *reinterpret_cast<const f4 *>(rp + max((int)x0 - 4 * k, 0));
+        if (lane == 63) rk = *reinterpret_cast<const f4 *>(rp + min((int)x0 + 4 * k, f.W - 4));
         row[4 * (R - k) + 0] = lk.x;
         row[4 * (R - k) + 1] = lk.y;
         row[4 * (R - k) + 2] = lk.z;
@@ -237,14 +233,16 @@ __device__ __forceinline__ void vec4_write(const FrameArgs &f, uint32_t tile, Ti
     }
 }
 
+// Ballots of the compares and a scalar AND with the live lanes.
 __device__ __forceinline__ void vec4_count(const Vec4Out &o, uint32_t &cv, uint32_t &cb) {
-    const bool live = o.live;
+    const uint64_t lm = __builtin_amdgcn_ballot_w64(o.live);
     const uint32_t codes = o.codes;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const uint32_t c = (codes >> (8 * j)) & 0xffu;
-        cv += wave_count(live & (c == BN_VALID));
-        cb += wave_count(live & (c == BN_BOUNDARY));
+        cv += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(c == BN_VALID) & lm);
+        cb += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(c == BN_BOUNDARY) &
+                                             lm);
     }
 }
 
@@ -365,9 +363,9 @@ __device__ __forceinline__ void vec4_tile_counted(const FrameArgs &f, uint32_t t
     vec4_eval_method<A, M>(f, tile, o);
     CountTicket tk;
     bool have = false;
+    uint32_t cv = 0, cb = 0;
+    vec4_count(o, cv, cb);
     if (f.stats) {
-        uint32_t cv = 0, cb = 0;
-        vec4_count(o, cv, cb);
         uint32_t v, b;
         block_sum(cv, cb, v, b);
         if (threadIdx.x == 0) {
