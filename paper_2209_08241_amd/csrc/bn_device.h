@@ -136,15 +136,17 @@ __host__ __device__ constexpr int kernel_method(int method, int alpha, int scale
     return method == kMultiScale && alpha * scales > kMsShortReach ? kMultiScaleLong : method;
 }
 
-// A finite depth > 0: bit patterns 0x00000001 .. 0x7f7fffff.  Integer test,
-// so it does not depend on the denormal mode.
+// A finite depth > 0: bit patterns 0x00000001 .. 0x7f7fffff, that is the
+// classes positive subnormal and positive normal (one class test: it reads
+// the bit pattern, whatever the denormal mode).
 __device__ __forceinline__ uint32_t tap_ok(float d) {
-    return (__float_as_uint(d) - 1u) < 0x7f7fffffu ? 1u : 0u;
+    return __builtin_amdgcn_classf(d, 0x180) ? 1u : 0u;  // +subnormal | +normal
 }
 
-// q is a finite number >= FLT_MIN: bit patterns 0x00800000 .. 0x7f7fffff.
+// q is a finite number >= FLT_MIN: bit patterns 0x00800000 .. 0x7f7fffff,
+// the class positive normal.
 __device__ __forceinline__ uint32_t q_ok(float q) {
-    return (__float_as_uint(q) - 0x00800000u) < 0x7f000000u ? 1u : 0u;
+    return __builtin_amdgcn_classf(q, 0x100) ? 1u : 0u;  // +normal
 }
 
 // Row of a flat work item: floor(i / gpr) exactly, for i < 2^28 and
