@@ -135,6 +135,19 @@ def _run(fn, depth, dt, ct, fx, fy, cx, cy, alpha, mode, tau, want_r, want_rho, 
     return out
 
 
+def _band_buffers(out, n, W):
+    """Output buffers of a band of n rows: fresh ones, or the caller's (which
+    must be C-contiguous and large enough)."""
+    if out is None:
+        return np.zeros((n, W, 3), dtype=np.float64), np.zeros((n, W), dtype=np.uint8)
+    normals, mask = out
+    if (normals.dtype != np.float64 or mask.dtype != np.uint8 or
+            not normals.flags.c_contiguous or not mask.flags.c_contiguous or
+            normals.size < 3 * n * W or mask.size < n * W):
+        raise ValueError("band buffers too small or of the wrong type")
+    return normals, mask
+
+
 class Oracle:
     """The oracle entry points bound to one library file."""
 
@@ -152,8 +165,12 @@ class Oracle:
         return _run(self.L.bno_normals_f32, depth, np.float32, ctypes.c_float,
                     fx, fy, cx, cy, alpha, mode, tau, want_r, want_rho, eq7)
 
-    def normals_f32_rows(self, depth, fx, fy, cx, cy, alpha, mode, tau, row_begin, row_end):
-        """Rows [row_begin, row_end) of normals_f32 on the full frame."""
+    def normals_f32_rows(self, depth, fx, fy, cx, cy, alpha, mode, tau, row_begin, row_end,
+                         out=None):
+        """Rows [row_begin, row_end) of normals_f32 on the full frame.  out:
+        optional (normals, mask) buffers (C-contiguous float64 and uint8 of at
+        least (row_end - row_begin) * W * 3 and * W elements) to write into;
+        the band occupies their first elements."""
         depth = np.asarray(depth)
         if depth.ndim != 2 or depth.dtype != np.float32:
             raise TypeError("depth must be a 2-D float32 array")
@@ -162,8 +179,7 @@ class Oracle:
         H, W = depth.shape
         stride = depth.strides[0] // 4 if H > 0 else W
         n = row_end - row_begin
-        normals = np.zeros((n, W, 3), dtype=np.float64)
-        mask = np.zeros((n, W), dtype=np.uint8)
+        normals, mask = _band_buffers(out, n, W)
         counts = np.zeros(3, dtype=np.uint64)
         none = ctypes.cast(None, ctypes.POINTER(ctypes.c_double))
         rc = self.L.bno_normals_f32_rows(
@@ -209,10 +225,10 @@ class Oracle:
 
     def variant_f32(self, depth, fx, fy, cx, cy, alpha=2, mode="rel", tau=4.0, *,
                     method="four_pair", scales=0, rows=None, want_r=False, want_rho=False,
-                    want_keep=False, gap=False):
+                    want_keep=False, gap=False, out=None):
         """Any method (four_pair, pair_removal, multiscale), binary32 depth in,
         FP64 normals out, binary32 decisions; rows=(begin, end) evaluates
-        those rows of the frame only."""
+        those rows of the frame only (out: as for normals_f32_rows)."""
         depth = np.asarray(depth)
         if depth.ndim != 2 or depth.dtype != np.float32:
             raise TypeError("depth must be a 2-D float32 array")
@@ -222,8 +238,7 @@ class Oracle:
         stride = depth.strides[0] // 4 if H > 0 else W
         rb, re = (0, H) if rows is None else rows
         n = re - rb
-        normals = np.zeros((n, W, 3), dtype=np.float64)
-        mask = np.zeros((n, W), dtype=np.uint8)
+        normals, mask = _band_buffers(out, n, W)
         counts = np.zeros(3, dtype=np.uint64)
         r = np.empty((n, W)) if want_r else None
         rho = np.empty((n, W)) if want_rho else None

@@ -381,9 +381,66 @@ def pin_fp32_degenerate(o):
     assert np.all(out["mask"][interior(9, 9, 1)] == VALID)
 
 
+def pin_row_bands(o):
+    """The row-band entries (rows [a, b) of a frame, in full-frame
+    coordinates, written from the first element of the output) must place
+    each row where the full-frame call puts it.  Two independent facts: on a
+    binary32 plane the band's own rows are INVALID exactly where their
+    full-frame row y is within alpha of the top or bottom edge, and VALID
+    with the plane normal (within the binary32 bound) elsewhere; and on a
+    noisy scene every method's band equals the matching rows of the
+    full-frame output bit for bit.  Each band is written into buffers of the
+    whole frame's size pre-filled with a sentinel, so a band written at the
+    wrong offset shows as sentinel rows."""
+    def band(method, scales, d, intr, a, rb, re, mode="rel"):
+        H, W = d.shape
+        nb = np.full((H, W, 3), -7.0)
+        mb = np.full((H, W), 0xEE, dtype=np.uint8)
+        if method == "four_pair_rows":
+            r = o.normals_f32_rows(d, *intr, a, mode, 4.0, rb, re, out=(nb, mb))
+        else:
+            r = o.variant_f32(d, *intr, alpha=a, mode=mode, tau=4.0, method=method,
+                              scales=scales, rows=(rb, re), out=(nb, mb))
+        n = re - rb
+        assert np.all(nb[n:] == -7.0) and np.all(mb[n:] == 0xEE), \
+            f"{method}: band [{rb},{re}) wrote past its {n} rows"
+        return nb[:n], mb[:n], r["counts"]
+
+    # absolute row positions from a plane (independent of the full-frame call)
+    n_pl = camera_facing_plane(30.0, 120.0)
+    d = scenes.plane_depth(H0, W0, FX0, FY0, CX0, CY0, n_pl, -2.0).astype(np.float32)
+    intr = (FX0, FY0, CX0, CY0)
+    for a in (1, 2):
+        for rb, re in ((0, 3), (1, 7), (5, 6), (H0 - 4, H0), (a + 3, H0 - 2)):
+            nrm, msk, _ = band("four_pair_rows", 0, d, intr, a, rb, re, mode="none")
+            ys = np.arange(rb, re)
+            row_in = (ys >= a) & (ys <= H0 - 1 - a)
+            col_in = (np.arange(W0) >= a) & (np.arange(W0) <= W0 - 1 - a)
+            exp = np.where(row_in[:, None] & col_in[None, :], VALID, INVALID)
+            assert np.array_equal(msk, exp), f"band [{rb},{re}) alpha={a}: rows misplaced"
+            err = np.abs(nrm[exp == VALID] - n_pl).max() if np.any(exp == VALID) else 0.0
+            assert err <= 4 * 2.0 ** -24 * max(FX0, FY0) / a, f"band plane error {err:.3g}"
+
+    # every method's band equals the full frame's rows, bit for bit
+    s = _noisy(seed=33, H=36, W=44)
+    intr = s.intrinsics
+    for method, scales, a in (("four_pair_rows", 0, 2), ("four_pair", 0, 1),
+                              ("pair_removal", 0, 2), ("multiscale", 2, 1)):
+        if method == "four_pair_rows":
+            full = o.normals_f32(s.depth, *intr, alpha=a, mode="rel", tau=4.0)
+        else:
+            full = o.variant_f32(s.depth, *intr, alpha=a, mode="rel", tau=4.0, method=method,
+                                 scales=scales)
+        for rb, re in ((1, 4), (6, 7), (9, 36), (20, 36)):
+            nrm, msk, cnt = band(method, scales, s.depth, intr, a, rb, re)
+            assert np.array_equal(msk, full["mask"][rb:re]), f"{method} band [{rb},{re}) mask"
+            assert np.array_equal(nrm, full["normals"][rb:re]), f"{method} band [{rb},{re})"
+            assert np.array_equal(cnt.astype(np.int64), np.bincount(msk.ravel(), minlength=3))
+
+
 ALL_PINS = [pin_plane_exact_f64, pin_plane_f32_bound, pin_sphere_second_order,
             pin_pca_planar, pin_pca_sphere, pin_eq7_identity, pin_unit_and_facing,
             pin_center_tap_unused, pin_invalid_taps, pin_border, pin_counts,
             pin_mask_scale_invariance, pin_mask_mirror, pin_mask_transpose,
             pin_rel_fronto, pin_abs_fronto, pin_rel_tilted_plane, pin_step_edges,
-            pin_fp32_degenerate]
+            pin_fp32_degenerate, pin_row_bands]

@@ -36,6 +36,9 @@ MUTANTS = {
     "no_degenerate_rule": [("if (!isfinite(q) || q < FLT_MIN)", "if (!isfinite(q))")],
     "boundary_keeps_normal": [("if (code == ORC_VALID) {", "if (code != ORC_INVALID) {")],
     "q_missing_mz": [("float q = (mx2 + my2) + mz2;", "float q = (mx2 + my2);")],
+    # row bands: output indexed by the full-frame row instead of the band row
+    "band_rows_full_frame_index": [("int64_t i = (int64_t)(y - row_begin) * W + x;",
+                                    "int64_t i = (int64_t)y * W + x;")],
     # pair removal
     "pair_34_wrong_direction": [("const int sh[4] = {1, -1, -1, 1};",
                                  "const int sh[4] = {1, 1, -1, 1};")],
