@@ -39,6 +39,57 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _gen(job):
+    """One host frame of the run (a process-pool job)."""
+    from synth import scenes
+    kind, a = job
+    if kind == "1080":
+        return scenes.frame_1920x1080(seed=a)
+    if kind == "640":
+        return scenes.frame_640x480(seed=a)
+    H, W, seed = a
+    return scenes.sized_frame(H, W, seed)
+
+
+def generate_inputs(args) -> dict:
+    """Every host frame the run uses, generated before anything touches the
+    GPU: the process pool forks, and a process that has initialised HIP must
+    not fork.  The pool is shut down (its workers joined) before returning."""
+    import concurrent.futures as cf
+    from synth import scenes
+    jobs = {}
+    if args.workload == "batch":
+        jobs["batch"] = [("sized", (H, W, 1000 + i))
+                         for i, (H, W) in enumerate(scenes.batch_shapes())]
+    else:
+        nd = min(args.distinct, args.ring)
+        if not args.no_batch and not args.no_serve:
+            # the slowest job (4096x3072) first, so the pool stays busy
+            jobs["serve"] = [("sized", (H, W, 3000 + k))
+                             for k, (H, W) in enumerate(scenes.SERVE_SIZES)]
+        jobs["plain"] = [("1080", 2 + i) for i in range(nd)]
+        if not args.no_batch:
+            jobs["batch"] = [("sized", (H, W, 1000 + i))
+                             for i, (H, W) in enumerate(scenes.batch_shapes())]
+        if not args.quick:
+            jobs["plain640"] = [("640", 1 + i) for i in range(8)]
+            jobs["diff"] = [("640", 2000 + i) for i in range(16)]
+    flat = [j for js in jobs.values() for j in js]
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    workers = max(1, min(16, int(cores or 1), len(flat)))
+    log(f"generating {len(flat)} host frames ({', '.join(f'{k}: {len(v)}' for k, v in jobs.items())}) "
+        f"on {workers} processes, before any GPU use")
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        out = list(ex.map(_gen, flat, chunksize=1))
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    res, i = {}, 0
+    for k, js in jobs.items():
+        res[k] = out[i:i + len(js)]
+        i += len(js)
+    return res
+
+
 def kernel_hash(sources=None) -> str:
     """The measured kernels' sources (the forward kernels' by default) and the
     flags they are compiled with."""
@@ -133,9 +184,11 @@ class Ring:
                                  normals=self.normals[j], mask=self.masks[j],
                                  stats=self.stats[j], stream=stream, **kw)
 
-    def time(self, kw, steps, warmup, eager=False, hot=False):
+    def time(self, kw, steps, warmup, eager=False, hot=False, min_passes=10):
         """ms per launch over `steps` launches (graph replay of one pass over
-        the ring unless eager; hot: the same buffer every launch)."""
+        the ring unless eager; hot: the same buffer every launch).  A graph
+        run times whole passes over the ring, at least min_passes of them, so
+        that the timed window spans milliseconds whatever `steps` asks."""
         torch = self.torch
         ring = 1 if hot else self.ring
         stream = torch.cuda.Stream()
@@ -150,8 +203,8 @@ class Ring:
                 for i in range(ring):
                     self.launch(i, kw, torch.cuda.current_stream())
             torch.cuda.synchronize()
-            steps = max(steps // ring, 1) * ring
-            warmup = max(warmup // ring, 1) * ring
+            steps = max(-(-steps // ring), min_passes) * ring
+            warmup = max(-(-warmup // ring), 1) * ring
 
         def run(n):
             if graph is not None:
@@ -164,7 +217,7 @@ class Ring:
         with torch.cuda.stream(stream):
             run(warmup)
         torch.cuda.synchronize()
-        self.stats.zero_()
+        self.stats.fill_(-1)   # every launch stores its frame's counts over this
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -258,11 +311,10 @@ def achievable_rates(torch, bn, reps=5):
     return out
 
 
-def run_plain(args, torch, bn, scenes):
+def run_plain(args, torch, bn, inputs):
     ring_n = args.ring
-    ndistinct = min(args.distinct, ring_n)
-    log(f"generating {ndistinct} distinct 1920x1080 scenes (seeds 2..{1 + ndistinct})")
-    scs = [scenes.frame_1920x1080(seed=2 + i) for i in range(ndistinct)]
+    scs = inputs["plain"]
+    ndistinct = len(scs)
     ring = Ring(torch, bn, scs, ring_n)
     H, W = ring.H, ring.W
     px = H * W
@@ -270,14 +322,14 @@ def run_plain(args, torch, bn, scenes):
     ref = parity_check(ring, kw, args.alpha, args.mode, args.tau)
     ms_step, steps, warm, graphed = ring.time(kw, args.steps, args.warmup, eager=args.eager)
     st = ring.stats.cpu().numpy()
-    passes = steps // ring_n
-    want = [passes * int(c) for c in ref["counts"]]
-    if graphed and st[0, :3].tolist() != want:
-        raise SystemExit(f"per-frame counts wrong after timing: {st[0, :3].tolist()} != {want}")
+    want = [int(c) for c in ref["counts"]] + [0]
+    if st[0].tolist() != want:
+        raise SystemExit(f"per-frame counts wrong after timing: {st[0].tolist()} != {want}")
     traffic = load_traffic("plain1080", px)
     extra = {}
     if not args.quick:
-        hot_ms, _, _, _ = ring.time(kw, args.steps // 4, args.warmup // 4, hot=True)
+        hot_ms, _, _, _ = ring.time(kw, args.steps // 4, args.warmup // 4, hot=True,
+                                    min_passes=100)
         extra["hot_cache"] = {"value": px / (hot_ms * 1e-3) / 1e6, "unit": "Mpix/s",
                               "note": "one frame buffer relaunched: the 256 MB last-level "
                                       "cache holds it, not an HBM figure"}
@@ -287,7 +339,7 @@ def run_plain(args, torch, bn, scenes):
                                ("multiscale", 3, 3)):
             mkw = dict(alpha=alpha, mode=args.mode, tau=args.tau, method=name, scales=K)
             parity_check(ring, mkw, alpha, args.mode, args.tau, name, K)
-            mms, msteps, _, _ = ring.time(mkw, args.steps // 2, args.warmup // 2)
+            mms, msteps, _, _ = ring.time(mkw, args.steps // 2, args.warmup // 2, min_passes=5)
             methods.append({"method": name, "alpha": alpha, "scales": K, "steps": msteps,
                             "ms_per_step": mms, "value": px / (mms * 1e-3) / 1e6,
                             "unit": "Mpix/s", "roofline": roofline(px, mms)})
@@ -295,7 +347,7 @@ def run_plain(args, torch, bn, scenes):
         extra["methods"] = methods
         # the small plain configuration: 640x480, a ring of 256 buffers
         # (1.6 GB, beyond the last-level cache), one launch per frame
-        scs640 = [scenes.frame_640x480(seed=1 + i) for i in range(8)]
+        scs640 = inputs["plain640"]
         r640 = Ring(torch, bn, scs640, 256)
         kw640 = dict(alpha=args.alpha, mode=args.mode, tau=args.tau)
         parity_check(r640, kw640, args.alpha, args.mode, args.tau)
@@ -336,13 +388,9 @@ def run_plain(args, torch, bn, scenes):
     return out
 
 
-def run_batch(args, torch, bn, scenes):
+def run_batch(args, torch, bn, inputs):
     """The 256-frame mixed batch, one graph launch over all tiles per step."""
-    workers = min(16, os.cpu_count() or 1)
-    log(f"generating the 256-frame mixed batch ({workers} workers)")
-    t0 = time.perf_counter()
-    frames_h = scenes.batch_frames(seed0=1000, workers=workers)
-    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    frames_h = inputs["batch"]
     dev = torch.device("cuda:0")
     frames = [bn.BatchFrame(torch.from_numpy(s.depth).to(dev), s.fx, s.fy, s.cx, s.cy)
               for s in frames_h]
@@ -366,7 +414,7 @@ def run_batch(args, torch, bn, scenes):
             raise SystemExit(f"batched frame {k} disagrees with the oracle")
     log("batched parity sample ok")
     for fr in frames:
-        fr.stats.zero_()
+        fr.stats.fill_(-1)   # every run stores each frame's counts over this
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -380,8 +428,8 @@ def run_batch(args, torch, bn, scenes):
     ms = start.elapsed_time(end) / steps
     ref0 = oracle.normals_f32(frames_h[0].depth, frames_h[0].fx, frames_h[0].fy,
                               frames_h[0].cx, frames_h[0].cy, args.alpha, args.mode, args.tau)
-    got0 = frames[0].stats[:3].cpu().tolist()
-    if got0 != [steps * int(c) for c in ref0["counts"]]:
+    got0 = frames[0].stats.cpu().tolist()
+    if got0 != [int(c) for c in ref0["counts"]] + [0]:
         raise SystemExit("batched counts wrong after timing")
     plan.close()
     plain = None
@@ -446,7 +494,7 @@ def plain_launches(args, torch, bn, frames, stream, px):
 SETS = 6   # buffer sets the differentiation timings cycle over
 
 
-def run_diff(args, torch, bn, scenes):
+def run_diff(args, torch, bn, inputs):
     """Differentiation: 16 x 640x480 frames (seeds 2000..2015) as one stack.
     The adjoint kernel over the stack (one launch), the forward over the
     stack, the adjoint as 16 single-frame launches for comparison, and one
@@ -454,8 +502,7 @@ def run_diff(args, torch, bn, scenes):
     depth, backward through the adjoint)."""
     import numpy as np
     import oracle
-    log("generating the 16-frame differentiation batch (seeds 2000..2015)")
-    scs = [scenes.frame_640x480(seed=2000 + i) for i in range(16)]
+    scs = inputs["diff"]
     dev = torch.device("cuda:0")
     n, H, W = len(scs), 480, 640
     px = H * W
@@ -579,16 +626,11 @@ class _PoolFrame:
                         self.cx, self.cy, 0, 0, 0)
 
 
-def run_serve(args, torch, bn, scenes, capacity_mpix_s):
+def run_serve(args, torch, bn, inputs, capacity_mpix_s):
     """Poisson request streams over the serving sizes at fractions of the
     batched capacity measured in the same run; device-resident inputs."""
     import numpy as np
-    workers = min(5, os.cpu_count() or 1)
-    log("generating one frame per serving size (seeds 3000..3004)")
-    import concurrent.futures as cf
-    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-        frames_h = list(ex.map(scenes._sized_job, [(H, W, 3000 + k, {})
-                                                  for k, (H, W) in enumerate(scenes.SERVE_SIZES)]))
+    frames_h = inputs["serve"]
     # 16 device copies of each frame, each depth scaled by its own factor in
     # [0.98, 1.02], so that requests read 1 GB of distinct depth (more than
     # the 256 MB last-level cache holds); outputs live in the server's slots
@@ -674,9 +716,11 @@ def main():
               "multi-GPU path; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    # host frames first: nothing below this line may fork
+    inputs = generate_inputs(args)
+
     import torch
     import paper_2209_08241_amd as bn
-    from synth import scenes
 
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
@@ -690,7 +734,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.workload == "batch":
-        b = run_batch(args, torch, bn, scenes)
+        b = run_batch(args, torch, bn, inputs)
         out = {"metric": "normals Mpix/s (batched launch)", "value": b["value"],
                "unit": "Mpix/s", "steps": b["steps"], "warmup": args.batch_warmup,
                "ms_per_step": b["ms_per_step"],
@@ -698,21 +742,20 @@ def main():
                           "tau": args.tau, "pixels": b["pixels"]},
                "roofline": b["roofline"], "cpu_baseline": None}
         if not args.no_cpu_baseline:
-            from synth import scenes as sc
-            sample = sc.batch_frames(seed0=1000, indices=[0, 64, 160, 224])
+            sample = [inputs["batch"][i] for i in (0, 64, 160, 224)]
             out["cpu_baseline"] = cpu_baseline(sample, args.alpha, args.mode, args.tau,
                                                args.cpu_seconds)
     else:
-        out = run_plain(args, torch, bn, scenes)
+        out = run_plain(args, torch, bn, inputs)
         if not args.no_batch:
-            b = run_batch(args, torch, bn, scenes)
+            b = run_batch(args, torch, bn, inputs)
             out["batched"] = {k: b[k] for k in ("workload", "value", "unit", "ms_per_step",
                                                 "steps", "pixels", "tiles", "workgroups",
                                                 "roofline", "same_frames_plain_launches")}
             if not args.no_serve:
-                out["serving"] = run_serve(args, torch, bn, scenes, b["value"])
+                out["serving"] = run_serve(args, torch, bn, inputs, b["value"])
         if not args.quick:
-            out["differentiation"] = run_diff(args, torch, bn, scenes)
+            out["differentiation"] = run_diff(args, torch, bn, inputs)
     line = {
         "metric": out["metric"],
         "value": out["value"],
@@ -741,6 +784,10 @@ def main():
               "single_launch_us", "cpu_oracle_all_cores"):
         if k in out:
             line[k] = out[k]
+    import multiprocessing
+    left = multiprocessing.active_children()
+    if left:
+        log(f"child processes still alive at the end: {[c.pid for c in left]}")
     print(json.dumps(line), flush=True)
 
 

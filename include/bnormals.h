@@ -100,7 +100,7 @@
 extern "C" {
 #endif
 
-#define BN_VERSION 2
+#define BN_VERSION 3
 
 /* status codes */
 #define BN_OK 0
@@ -126,7 +126,7 @@ extern "C" {
 #define BN_METHOD_MULTISCALE 2
 
 /* flags */
-#define BN_FLAG_COUNTS_OVERWRITE 1u /* counts replace n_valid/n_boundary/n_invalid */
+#define BN_FLAG_COUNTS_ACCUMULATE 1u /* counts are added to n_valid/n_boundary/n_invalid */
 
 /* limits */
 #define BN_MAX_ALPHA 8
@@ -135,6 +135,7 @@ extern "C" {
 #define BN_SMALL_BATCH 16
 #define BN_MAX_WIDTH 65536
 #define BN_MAX_PIXELS (1LL << 28)
+#define BN_MAX_STREAMS 32 /* streams per device with a count work area */
 
 typedef struct bn_params {
     int32_t alpha;     /* stencil pixel distance, 1..BN_MAX_ALPHA (Section 3.1) */
@@ -145,35 +146,40 @@ typedef struct bn_params {
                           tuning: every variant writes identical output */
     int32_t method;    /* BN_METHOD_*; 0 = the paper's four-pair estimator */
     int32_t scales;    /* BN_METHOD_MULTISCALE: K, 1..BN_MAX_SCALES; others: 0 or 1 */
-    uint32_t flags;    /* 0 or BN_FLAG_COUNTS_OVERWRITE */
+    uint32_t flags;    /* 0 or BN_FLAG_COUNTS_ACCUMULATE */
     uint32_t reserved; /* 0 */
 } bn_params;          /* 32 bytes; a zeroed structure plus alpha, mode and tau
                          selects the paper's method */
 
-/* Per-frame pixel counts by code, plus the device workspace the library uses
- * to reduce them inside the launch that produces them.
+/* Per-frame pixel counts by code (16 bytes, 4-byte aligned, device memory).
  *
- * The counts are ADDED to n_valid / n_boundary / n_invalid, or, with
- * BN_FLAG_COUNTS_OVERWRITE in params->flags, REPLACE them (no zeroing
- * needed between calls).  Before the first use the caller zeroes the whole
- * structure (e.g. hipMemset of sizeof(bn_frame_stats) bytes); every call
- * leaves `work` zero again, so a structure can be reused indefinitely.  Two
- * calls that overlap in time must not share one structure.  Place it at a
- * 128-byte aligned address (else the calls return BN_ERR_INVALID_ARG): the
- * workspace is one 128-byte cache line per reduction slot. */
-#define BN_STATS_SLOTS 32
+ * A call that is given one STORES the frame's counts in it (n_invalid =
+ * pixels - n_valid - n_boundary, reserved = 0), or, with
+ * BN_FLAG_COUNTS_ACCUMULATE in params->flags, ADDS them to the three
+ * counters (for totals over many calls; the caller zeroes them first).  No
+ * other bytes are written.
+ *
+ * The counts are reduced inside the launch that produces them, on a device
+ * work area that the library owns (never in this structure): the
+ * single-frame and stack calls take the work area of the calling stream -
+ * one per (device, stream), from a fixed pool of BN_MAX_STREAMS per device
+ * held by the library until the process ends (a call on a further stream
+ * returns BN_ERR_UNSUPPORTED) - and a batch plan owns one per frame of its
+ * capacity.  Calls on one stream run one after another, so they share its
+ * work area safely; a launch captured into a graph keeps the work area of
+ * the stream it was captured on, so its replays must not overlap other calls
+ * on that stream (or replays of other graphs captured on it). */
 typedef struct bn_frame_stats {
     uint32_t n_valid;
     uint32_t n_boundary;
     uint32_t n_invalid;
     uint32_t reserved;
-    uint64_t work[14 + 16 * BN_STATS_SLOTS]; /* library-internal, keep zero */
-} bn_frame_stats;                             /* 4224 bytes */
+} bn_frame_stats; /* 16 bytes */
 
 /* One frame of a batch.  depth: [height][depth_stride] binary32, row-major,
  * depth_stride >= width (elements), 4-byte aligned.  normals:
  * [height][width][3] binary32, dense, 4-byte aligned.  mask: [height][width]
- * uint8, dense.  stats: nullable, 128-byte aligned. */
+ * uint8, dense.  stats: nullable, 4-byte aligned. */
 typedef struct bn_frame {
     const float *depth;
     int32_t height;
@@ -194,14 +200,15 @@ typedef struct bn_frame {
  *             pointer, read during the call)
  *   normals   [height][width][3] binary32 out
  *   mask      [height][width] uint8 out (BN_VALID / BN_BOUNDARY / BN_INVALID)
- *   stats     one bn_frame_stats (zeroed before first use), counts added
- *             (nullable)
+ *   stats     one bn_frame_stats: the frame's counts, stored (or added, with
+ *             BN_FLAG_COUNTS_ACCUMULATE); nullable
  * height or width 0: nothing to do, BN_OK.  Limits: width <= BN_MAX_WIDTH,
  * height*width <= BN_MAX_PIXELS.  Returns BN_OK, BN_ERR_INVALID_ARG,
- * BN_ERR_UNSUPPORTED (alpha > BN_MAX_ALPHA, scales > BN_MAX_SCALES, or a
+ * BN_ERR_UNSUPPORTED (alpha > BN_MAX_ALPHA, scales > BN_MAX_SCALES, a
  * forced variant that the method or the buffers' layout does not allow:
  * the multi-scale method takes the vector variants only when alpha * scales
- * <= 16) or BN_ERR_DEVICE.
+ * <= 16; or counts asked on more than BN_MAX_STREAMS streams of the device)
+ * or BN_ERR_DEVICE.
  */
 int bn_estimate_normals(const float *depth, int32_t height, int32_t width,
                         int64_t depth_stride, float fx, float fy, float cx, float cy,
@@ -237,9 +244,8 @@ int bn_normals_vjp(const float *depth, int32_t height, int32_t width, int64_t de
  *                height * depth_stride
  *   intrinsics   host array of n bn_intrinsics, read during the call
  *   normals      [n][height][width][3] out;  mask [n][height][width] out
- *   stats        [n] bn_frame_stats (each zeroed before first use;
- *                nullable), counts added or (BN_FLAG_COUNTS_OVERWRITE)
- *                stored per frame
+ *   stats        [n] bn_frame_stats, frame k's counts stored in entry k
+ *                (added with BN_FLAG_COUNTS_ACCUMULATE); nullable
  *   grad_normals [n][height][width][3];  grad_depth [n][height][width] out
  * 1 <= n <= BN_MAX_STACK (n = 0, height 0 or width 0: nothing to do).
  * params->variant: 0 (vector tiles when the layout allows them, which
@@ -278,8 +284,7 @@ int bn_normals_vjp_stack(const float *depth, int32_t n, int32_t height, int32_t 
  * All frames share `params` (alpha, mode, tau, method, scales, flags;
  * params->variant must be 0);
  * each frame has its own size, stride, intrinsics and outputs, and its
- * counts go to its own bn_frame_stats (zeroed before first use) or nowhere
- * (stats = NULL).  Each frame's outputs are identical to those of
+ * counts go to its own bn_frame_stats or nowhere (stats = NULL).  Each frame's outputs are identical to those of
  * bn_estimate_normals on that frame.
  *
  * bn_batch_plan_create: validates every frame (the checks of
@@ -355,7 +360,7 @@ int bn_autotune_entries(void);
  * depth in host memory, a copy of the depth (4 B/px) - fits in the HBM
  * budget; admission starts the host-to-device copy of a host depth on a
  * copy stream (a device depth is used in place).  Launches store each
- * request's counts (BN_FLAG_COUNTS_OVERWRITE is implied).  Whenever fewer than max_batches_in_flight launches are
+ * request's counts (BN_FLAG_COUNTS_ACCUMULATE is ignored).  Whenever fewer than max_batches_in_flight launches are
  * queued on the GPU, all admitted requests whose input is on the device (up
  * to max_batch) form one batched launch (bn_batch_plan) on a compute
  * stream.  New requests are therefore admitted and copied while earlier
@@ -477,21 +482,6 @@ int bn_angle_mse(const float *normals_a, const uint8_t *mask_a, const float *nor
 int bn_plane_fit_normals(const float *depth, int32_t height, int32_t width, int64_t depth_stride,
                          float fx, float fy, float cx, float cy, int32_t radius, float *normals,
                          uint8_t *mask, void *stream);
-
-/*
- * Bandwidth probes: what this GPU's HBM delivers to plain streaming kernels,
- * the achievable reference beside the published peak.  Device pointers,
- * asynchronous on `stream`, nothing allocated.
- * bn_stream_copy: bytes (a multiple of 16, 16-byte aligned buffers) from src
- *   to dst with 16-byte non-temporal loads and stores.
- * bn_stream_pattern: the estimator's traffic without its arithmetic: reads
- *   4 B of depth and writes 12 B of normals and 1 B of code per pixel
- *   through the same LDS staging; pixels a multiple of 1024, depth and
- *   normals 16-byte and mask 4-byte aligned.  Output values are meaningless.
- */
-int bn_stream_copy(void *dst, const void *src, uint64_t bytes, void *stream);
-int bn_stream_pattern(const float *depth, float *normals, uint8_t *mask, uint64_t pixels,
-                      void *stream);
 
 /* Number of kernel variants of the plain entry point, and a name for each
  * id 1..count (NULL for an unknown id). */

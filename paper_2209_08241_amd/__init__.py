@@ -37,26 +37,35 @@ class Params(ctypes.Structure):
 
 
 METHODS = {"four_pair": 0, "pair_removal": 1, "multiscale": 2}
-FLAG_COUNTS_OVERWRITE = 1
+FLAG_COUNTS_ACCUMULATE = 1
 
 
-STATS_SLOTS = 32
-STATS_BYTES = 16 + 8 * (14 + 16 * STATS_SLOTS)   # sizeof(bn_frame_stats) = 4224
-STATS_WORDS = STATS_BYTES // 4
+STATS_BYTES = 16                 # sizeof(bn_frame_stats)
+STATS_WORDS = STATS_BYTES // 4   # n_valid, n_boundary, n_invalid, reserved
 
 
 class FrameStats(ctypes.Structure):
     _fields_ = [("n_valid", ctypes.c_uint32), ("n_boundary", ctypes.c_uint32),
-                ("n_invalid", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("work", ctypes.c_uint64 * (14 + 16 * STATS_SLOTS))]
+                ("n_invalid", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 def new_stats(n: Optional[int] = None, device="cuda"):
-    """Zeroed bn_frame_stats storage: int32 [STATS_WORDS] (or [n, STATS_WORDS]).
-    Words 0..2 are the VALID / BOUNDARY / INVALID counts."""
+    """bn_frame_stats storage: int32 [STATS_WORDS] (or [n, STATS_WORDS]),
+    zeroed.  Words 0..2 are the VALID / BOUNDARY / INVALID counts."""
     import torch
     shape = (STATS_WORDS,) if n is None else (n, STATS_WORDS)
     return torch.zeros(shape, dtype=torch.int32, device=device)
+
+
+def _check_stats(stats, shape, device):
+    """A stats tensor the C ABI can write: int32, contiguous, on the depth's
+    device, of exactly `shape` (so no write lands past its end)."""
+    import torch
+    if not isinstance(stats, torch.Tensor) or stats.dtype != torch.int32 or \
+            tuple(stats.shape) != tuple(shape) or not stats.is_contiguous() or \
+            stats.device != device:
+        raise ValueError(f"stats must be a contiguous int32 tensor of shape {tuple(shape)} on "
+                         f"{device} (bn_frame_stats is {STATS_WORDS} words)")
 
 
 class Frame(ctypes.Structure):
@@ -183,13 +192,15 @@ def variants() -> Sequence[Tuple[int, str]]:
 
 
 def make_params(alpha: int = 2, mode="rel", tau: float = 4.0, variant: int = 0,
-                method="four_pair", scales: int = 0, overwrite_counts: bool = False) -> Params:
+                method="four_pair", scales: int = 0, accumulate_counts: bool = False) -> Params:
     """bn_params: method is "four_pair" (the paper's estimator), "pair_removal"
-    or "multiscale" (with `scales` = K offsets alpha, 2 alpha, .., K alpha)."""
+    or "multiscale" (with `scales` = K offsets alpha, 2 alpha, .., K alpha);
+    accumulate_counts adds each call's counts to the stats instead of
+    storing them."""
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     me = METHODS[method] if isinstance(method, str) else int(method)
     return Params(int(alpha), m, float(tau), int(variant), me, int(scales),
-                  FLAG_COUNTS_OVERWRITE if overwrite_counts else 0, 0)
+                  FLAG_COUNTS_ACCUMULATE if accumulate_counts else 0, 0)
 
 
 def _stream_handle(stream) -> int:
@@ -211,16 +222,15 @@ def _check_depth(depth):
 
 def estimate_normals(depth, fx: float, fy: float, cx: float, cy: float, alpha: int = 2,
                      mode="rel", tau: float = 4.0, *, variant: int = 0, method="four_pair",
-                     scales: int = 0, overwrite_counts: bool = False,
+                     scales: int = 0, accumulate_counts: bool = False,
                      normals=None, mask=None, stats=None, want_stats: bool = True,
                      stream=None):
     """Normals [H,W,3] float32, codes [H,W] uint8 and counts for one frame.
 
-    `stats` (an int32 tensor of STATS_WORDS holding a zero-initialised
-    bn_frame_stats; words 0..2 are the VALID / BOUNDARY / INVALID counts) is
-    accumulated into when given (replaced with overwrite_counts); otherwise
-    a zeroed one is allocated when want_stats.  Returns (normals, mask,
-    stats_or_None).
+    `stats` (an int32 tensor of STATS_WORDS, a bn_frame_stats; words 0..2
+    are the VALID / BOUNDARY / INVALID counts) receives the frame's counts
+    (added to it with accumulate_counts); without one, one is allocated when
+    want_stats.  Returns (normals, mask, stats_or_None).
     """
     import torch
     _check_depth(depth)
@@ -237,11 +247,9 @@ def estimate_normals(depth, fx: float, fy: float, cx: float, cy: float, alpha: i
         raise ValueError("normals must be a contiguous float32 [H, W, 3] tensor")
     if not (mask.is_contiguous() and mask.shape == (H, W) and mask.dtype == torch.uint8):
         raise ValueError("mask must be a contiguous uint8 [H, W] tensor")
-    if stats is not None and (stats.numel() != STATS_WORDS or stats.dtype != torch.int32
-                              or not stats.is_contiguous() or stats.data_ptr() % 128):
-        raise ValueError(f"stats must be a contiguous, 128-byte aligned int32 tensor of "
-                         f"{STATS_WORDS} elements (bn_frame_stats)")
-    p = make_params(alpha, mode, tau, variant, method, scales, overwrite_counts)
+    if stats is not None:
+        _check_stats(stats, (STATS_WORDS,), dev)
+    p = make_params(alpha, mode, tau, variant, method, scales, accumulate_counts)
     stride = depth.stride(0) if H > 0 else W
     rc = lib().bn_estimate_normals(
         ctypes.c_void_p(depth.data_ptr()), H, W, stride, fx, fy, cx, cy, ctypes.byref(p),
@@ -283,7 +291,7 @@ def _stack_strides(depth):
 
 def estimate_normals_stack(depth, intrinsics, alpha: int = 2, mode="rel", tau: float = 4.0, *,
                            variant: int = 0, method="four_pair", scales: int = 0,
-                           overwrite_counts: bool = False, normals=None, mask=None, stats=None,
+                           accumulate_counts: bool = False, normals=None, mask=None, stats=None,
                            want_stats: bool = True, stream=None):
     """n frames of one size in one launch (bn_estimate_normals_stack).
 
@@ -307,11 +315,9 @@ def estimate_normals_stack(depth, intrinsics, alpha: int = 2, mode="rel", tau: f
         raise ValueError("normals must be a contiguous float32 [n, H, W, 3] tensor")
     if not (mask.is_contiguous() and mask.shape == (n, H, W) and mask.dtype == torch.uint8):
         raise ValueError("mask must be a contiguous uint8 [n, H, W] tensor")
-    if stats is not None and (stats.shape != (n, STATS_WORDS) or stats.dtype != torch.int32
-                              or not stats.is_contiguous() or stats.data_ptr() % 128):
-        raise ValueError("stats must be a contiguous, 128-byte aligned int32 tensor "
-                         f"[n, {STATS_WORDS}]")
-    p = make_params(alpha, mode, tau, variant, method, scales, overwrite_counts)
+    if stats is not None:
+        _check_stats(stats, (n, STATS_WORDS), dev)
+    p = make_params(alpha, mode, tau, variant, method, scales, accumulate_counts)
     row, frame = _stack_strides(depth)
     rc = lib().bn_estimate_normals_stack(
         ctypes.c_void_p(depth.data_ptr()), n, H, W, row, frame, arr, ctypes.byref(p),
@@ -355,6 +361,16 @@ class BatchFrame:
                                                               device=dev)
         if stats is None and want_stats:
             stats = new_stats(device=dev)
+        if stats is not None:
+            _check_stats(stats, (STATS_WORDS,), dev)
+        if not (self.normals.is_contiguous() and tuple(self.normals.shape) == (H, W, 3) and
+                self.normals.dtype == torch.float32 and self.normals.device == dev):
+            raise ValueError("normals must be a contiguous float32 [H, W, 3] tensor on the "
+                             "depth's device")
+        if not (self.mask.is_contiguous() and tuple(self.mask.shape) == (H, W) and
+                self.mask.dtype == torch.uint8 and self.mask.device == dev):
+            raise ValueError("mask must be a contiguous uint8 [H, W] tensor on the depth's "
+                             "device")
         self.stats = stats
 
     def _c(self) -> Frame:
@@ -368,11 +384,11 @@ class BatchPlan:
     """A bn_batch_plan: every frame of the list in one graph launch."""
 
     def __init__(self, frames, alpha: int = 2, mode="rel", tau: float = 4.0, *,
-                 method="four_pair", scales: int = 0, overwrite_counts: bool = False):
+                 method="four_pair", scales: int = 0, accumulate_counts: bool = False):
         L = lib()
         self._frames = list(frames)
         arr = (Frame * len(self._frames))(*[f._c() for f in self._frames])
-        self.params = make_params(alpha, mode, tau, 0, method, scales, overwrite_counts)
+        self.params = make_params(alpha, mode, tau, 0, method, scales, accumulate_counts)
         h = ctypes.c_void_p()
         rc = L.bn_batch_plan_create(arr, len(self._frames), ctypes.byref(self.params),
                                     ctypes.byref(h))
@@ -479,6 +495,16 @@ def autotune_entries() -> int:
 # differentiation
 # ---------------------------------------------------------------------------
 
+def _check_grad_depth(grad_depth, shape, device):
+    """The adjoint writes prod(shape) dense floats: refuse anything else."""
+    import torch
+    if not (isinstance(grad_depth, torch.Tensor) and grad_depth.is_contiguous() and
+            tuple(grad_depth.shape) == tuple(shape) and grad_depth.dtype == torch.float32 and
+            grad_depth.device == device):
+        raise ValueError(f"grad_depth must be a contiguous float32 tensor of shape "
+                         f"{tuple(shape)} on {device}")
+
+
 def normals_vjp(depth, fx, fy, cx, cy, grad_normals, alpha: int = 2, mode="rel",
                 tau: float = 4.0, grad_depth=None, stream=None):
     """d(sum normals . grad_normals)/d depth with every pixel's code held
@@ -492,6 +518,7 @@ def normals_vjp(depth, fx, fy, cx, cy, grad_normals, alpha: int = 2, mode="rel",
     g = g.contiguous()
     if grad_depth is None:
         grad_depth = torch.empty((H, W), dtype=torch.float32, device=depth.device)
+    _check_grad_depth(grad_depth, (H, W), depth.device)
     p = make_params(alpha, mode, tau, 0)
     stride = depth.stride(0) if H > 0 else W
     rc = lib().bn_normals_vjp(ctypes.c_void_p(depth.data_ptr()), H, W, stride, fx, fy, cx, cy,
@@ -516,9 +543,7 @@ def normals_vjp_stack(depth, intrinsics, grad_normals, alpha: int = 2, mode="rel
     g = g.contiguous()
     if grad_depth is None:
         grad_depth = torch.empty((n, H, W), dtype=torch.float32, device=depth.device)
-    if not (grad_depth.is_contiguous() and grad_depth.shape == (n, H, W)
-            and grad_depth.dtype == torch.float32):
-        raise ValueError("grad_depth must be a contiguous float32 [n, H, W] tensor")
+    _check_grad_depth(grad_depth, (n, H, W), depth.device)
     arr = _intrinsics_array(intrinsics, n)
     p = make_params(alpha, mode, tau, 0)
     row, frame = _stack_strides(depth)

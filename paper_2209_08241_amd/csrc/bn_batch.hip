@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(80))) void k
 
 // Sums of the wavefront counts: workgroup (f, c) takes chunk c of
 // kCountChunk tiles of frame f.  A frame of one chunk adds its totals to its
-// bn_frame_stats (or stores them, BN_FLAG_COUNTS_OVERWRITE) at once; the
+// bn_frame_stats (or adds them, BN_FLAG_COUNTS_ACCUMULATE) at once; the
 // chunks of a larger frame combine through the in-launch reduction of the
 // plain kernels, on the plan's work area for the frame, so that one huge
 // frame is not summed by a single workgroup.
@@ -277,7 +277,7 @@ struct bn_batch_plan {
     SmallKernelFn small_fn = nullptr;
     // one count work area per frame of the capacity, zero between launches
     // (the small lists' in-kernel reductions, the large frames' count sums)
-    bn_frame_stats *work = nullptr;
+    WorkArea *work = nullptr;
     uint32_t count_chunks = 1;             // grid.y of the count sums
     hipGraph_t sgraph = nullptr;
     hipGraphExec_t sexec = nullptr;
@@ -332,7 +332,7 @@ uint32_t grid_for(uint64_t tiles, int cus, uint32_t blocks_per_cu) {
 
 // Host image of the descriptors of `frames` (already validated) in `base`.
 int build_table(const bn_frame *frames, int32_t n, const bn_params *p, int32_t capacity,
-                uint32_t grid, bn_frame_stats *work, uint32_t *count_chunks, void *base) {
+                uint32_t grid, WorkArea *work, uint32_t *count_chunks, void *base) {
     auto *hdr = static_cast<BatchHeader *>(base);
     auto *fr = reinterpret_cast<BatchFrame *>(hdr + 1);
     auto *tf = reinterpret_cast<uint32_t *>(static_cast<char *>(base) + table_offset(capacity));
@@ -581,7 +581,7 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
         }
     }
     // the counts' work areas, one per frame of the capacity, zero from here on
-    const size_t work_bytes = sizeof(bn_frame_stats) * (size_t)n_frames;
+    const size_t work_bytes = sizeof(WorkArea) * (size_t)n_frames;
     if (hipMalloc(&pl->work, work_bytes) != hipSuccess) {
         free_plan(pl);
         return BN_ERR_OOM;

@@ -34,7 +34,7 @@ int check_params_args(const bn_params *p) {
     } else {
         return BN_ERR_INVALID_ARG;
     }
-    if ((p->flags & ~BN_FLAG_COUNTS_OVERWRITE) != 0u || p->reserved != 0u)
+    if ((p->flags & ~BN_FLAG_COUNTS_ACCUMULATE) != 0u || p->reserved != 0u)
         return BN_ERR_INVALID_ARG;
     return BN_OK;
 }
@@ -59,8 +59,7 @@ int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, f
 }
 
 int check_stats_arg(const bn_frame_stats *stats) {
-    // the in-launch reduction works on 128-byte lines of the structure
-    return ((uintptr_t)stats % 128) ? BN_ERR_INVALID_ARG : BN_OK;
+    return ((uintptr_t)stats % 4) ? BN_ERR_INVALID_ARG : BN_OK;
 }
 
 static bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
@@ -129,7 +128,7 @@ void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int
     f.normals = normals;
     f.mask = mask;
     f.stats = stats;
-    f.work = stats;
+    f.work = nullptr;
     f.stride = stride;
     f.H = H;
     f.W = W;
@@ -148,7 +147,7 @@ void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int
     f.npix = (uint32_t)H * (uint32_t)W;
     f.alpha = p->alpha;
     f.scales = p->method == BN_METHOD_MULTISCALE ? p->scales : 1;
-    f.overwrite = (p->flags & BN_FLAG_COUNTS_OVERWRITE) ? 1u : 0u;
+    f.overwrite = (p->flags & BN_FLAG_COUNTS_ACCUMULATE) ? 0u : 1u;
     f.inv_gpr = 1.0 / (double)f.gpr;
 }
 
@@ -175,6 +174,10 @@ int bn_estimate_normals(const float *depth, int32_t height, int32_t width, int64
     FrameArgs f;
     fill_frame_args(f, depth, height, width, depth_stride, fx, fy, cx, cy, params, normals, mask,
                     stats, variant_info(v)->px_per_item);
+    if (stats) {
+        rc = stream_work_areas((hipStream_t)stream, &f.work);
+        if (rc != BN_OK) return rc;
+    }
     hipError_t e = launch_plain(v, params->method, f, (hipStream_t)stream);
     return e == hipSuccess ? BN_OK : BN_ERR_DEVICE;
 }

@@ -23,13 +23,23 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;  // 4 wave64 per workgroup
 
+// The in-launch reduction's device words for one frame (library-owned; zero
+// between launches): line 0 holds the level-2 word, lines 1..kSlots the
+// level-1 slot words, one 128-byte line each so that the slots' atomics
+// proceed in parallel.
+constexpr uint32_t kSlots = 32;
+struct WorkArea {
+    unsigned long long w[16 * (kSlots + 1)];
+};
+static_assert(sizeof(WorkArea) == 4224, "33 lines of 128 bytes");
+
 // Everything a kernel needs to process one frame.
 struct FrameArgs {
     const float *depth;
     float *normals;
     uint8_t *mask;
     bn_frame_stats *stats;  // the counts' destination (nullable)
-    bn_frame_stats *work;   // the in-launch reduction's words (stats, or a scratch copy)
+    WorkArea *work;         // the in-launch reduction's words (library-owned)
     int64_t stride;   // depth row stride, elements
     int32_t H, W;
     float fx, fy, cx, cy;
@@ -42,7 +52,7 @@ struct FrameArgs {
     uint32_t npix;    // H * W
     int32_t alpha;    // integer alpha (multi-scale offsets)
     int32_t scales;   // K of the multi-scale method
-    uint32_t overwrite;  // 1: counts replace the stats counters, 0: added
+    uint32_t overwrite;  // 1: counts replace the stats counters, 0: added (accumulate)
     double inv_gpr;   // 1.0 / gpr
 };
 
@@ -79,7 +89,7 @@ struct FramePointersGlobal {
     BN_GLOBAL float *normals;
     BN_GLOBAL uint8_t *mask;
     BN_GLOBAL bn_frame_stats *stats;
-    BN_GLOBAL bn_frame_stats *work;
+    BN_GLOBAL WorkArea *work;
 };
 
 static_assert(sizeof(FramePointersGlobal) == 40 && offsetof(FrameArgs, work) == 32,
@@ -91,7 +101,7 @@ __device__ __forceinline__ void frame_pointers_global(FrameArgs &f, const FrameA
     f.normals = (float *)g.normals;
     f.mask = (uint8_t *)g.mask;
     f.stats = (bn_frame_stats *)g.stats;
-    f.work = (bn_frame_stats *)g.work;
+    f.work = (WorkArea *)g.work;
 }
 
 // Arguments of frame k of a stack.
@@ -421,35 +431,33 @@ __device__ __forceinline__ uint32_t wave_count(bool pred) {
 //
 // A frame's pixels are split into `nparts` parts (workgroups or tiles).  Each
 // part contributes its VALID and BOUNDARY counts with ONE relaxed 64-bit
-// atomic add on the word of slot (part % BN_STATS_SLOTS), each slot on its
-// own 128-byte line of a bn_frame_stats used as the work area (the caller's,
-// or a zeroed scratch copy when the destination may hold anything) so that
-// the adds of different slots proceed in parallel.  The word packs the counts and an
-// arrival ticket, so the value the atomic returns holds every earlier
-// contribution: the last arrival of a slot (ticket = parts in the slot - 1)
-// knows the slot total without any fence or reload.  It clears the slot and
-// forwards the total the same way to the level-2 word; the last of those
-// adds (or stores) the frame totals in the destination's counters (INVALID =
-// pixels - VALID - BOUNDARY) and clears the level-2 word.  The work area is
-// therefore zero again after every launch.
+// atomic add on the word of slot (part % kSlots) of the frame's WorkArea,
+// each slot on its own 128-byte line so that the adds of different slots
+// proceed in parallel.  The word packs the counts and an arrival ticket, so
+// the value the atomic returns holds every earlier contribution: the last
+// arrival of a slot (ticket = parts in the slot - 1) knows the slot total
+// without any fence or reload.  It clears the slot and forwards the total
+// the same way to the level-2 word; the last of those stores (or adds) the
+// frame totals in the destination's counters (INVALID = pixels - VALID -
+// BOUNDARY) and clears the level-2 word.  The work area is therefore zero
+// again after every launch.
 //
 // Level 1 word: VALID [0,24) | BOUNDARY [24,48) | ticket [48,64)
 //   (a slot holds fewer than 2^24 pixels and 2^16 parts for frames of at
 //    most 2^28 pixels and parts of at most 2^12 pixels).
 // Level 2 word: VALID [0,29) | BOUNDARY [29,58) | ticket [58,64)
-//   (at most 2^28 pixels, at most BN_STATS_SLOTS = 32 arrivals).
+//   (at most 2^28 pixels, at most kSlots = 32 arrivals).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long *stats_word(bn_frame_stats *st, uint32_t slot) {
-    // slot 0..31: level 1 (lines 1..32); BN_STATS_SLOTS: level 2 (header line)
-    return reinterpret_cast<unsigned long long *>(
-        slot < BN_STATS_SLOTS ? &st->work[14 + 16 * slot] : &st->work[0]);
+__device__ __forceinline__ unsigned long long *stats_word(WorkArea *wa, uint32_t slot) {
+    // slot 0..kSlots-1: level 1 (lines 1..kSlots); kSlots: level 2 (line 0)
+    return &wa->w[slot < kSlots ? 16 * (slot + 1) : 0];
 }
 
 // First half: the level-1 atomic.  Its result is used only in the second
 // half, so the caller can place other work (the output stores) in between
 // and hide the atomic's round trip behind it.
 struct CountTicket {
-    bn_frame_stats *work;
+    WorkArea *work;
     bn_frame_stats *out;
     unsigned long long *w1;
     unsigned long long mine1;
@@ -457,16 +465,16 @@ struct CountTicket {
     uint32_t ns, nparts, npix, overwrite;
 };
 
-__device__ __forceinline__ CountTicket count_issue(bn_frame_stats *work, bn_frame_stats *out,
+__device__ __forceinline__ CountTicket count_issue(WorkArea *work, bn_frame_stats *out,
                                                    uint32_t part, uint32_t nparts,
                                                    uint32_t nvalid, uint32_t nboundary,
                                                    uint32_t npix, uint32_t overwrite) {
     CountTicket k;
     k.overwrite = overwrite;
-    const uint32_t s = part % BN_STATS_SLOTS;
+    const uint32_t s = part % kSlots;
     k.work = work;
     k.out = out;
-    k.ns = nparts / BN_STATS_SLOTS + (s < nparts % BN_STATS_SLOTS ? 1u : 0u);
+    k.ns = nparts / kSlots + (s < nparts % kSlots ? 1u : 0u);
     k.nparts = nparts;
     k.npix = npix;
     k.w1 = stats_word(work, s);
@@ -475,13 +483,14 @@ __device__ __forceinline__ CountTicket count_issue(bn_frame_stats *work, bn_fram
     return k;
 }
 
-// Frame totals into the counters: added, or (overwrite) stored.
+// Frame totals into the counters: stored (with reserved = 0), or added.
 __device__ __forceinline__ void put_counts(bn_frame_stats *st, uint32_t vt, uint32_t bt,
                                            uint32_t npix, uint32_t overwrite) {
     if (overwrite) {
         st->n_valid = vt;
         st->n_boundary = bt;
         st->n_invalid = npix - vt - bt;
+        st->reserved = 0u;
     } else {
         atomicAdd(&st->n_valid, vt);
         atomicAdd(&st->n_boundary, bt);
@@ -495,9 +504,8 @@ __device__ __forceinline__ void count_finish(const CountTicket &k) {
     atomicExch(k.w1, 0ull);
     const uint32_t vs = (uint32_t)(tot1 & 0xffffffull);
     const uint32_t bs = (uint32_t)((tot1 >> 24) & 0xffffffull);
-    const uint32_t nactive =
-        k.nparts < (uint32_t)BN_STATS_SLOTS ? k.nparts : (uint32_t)BN_STATS_SLOTS;
-    unsigned long long *w2 = stats_word(k.work, BN_STATS_SLOTS);
+    const uint32_t nactive = k.nparts < kSlots ? k.nparts : kSlots;
+    unsigned long long *w2 = stats_word(k.work, kSlots);
     const unsigned long long mine2 =
         (unsigned long long)vs | ((unsigned long long)bs << 29) | (1ull << 58);
     const unsigned long long old2 = atomicAdd(w2, mine2);
@@ -509,7 +517,7 @@ __device__ __forceinline__ void count_finish(const CountTicket &k) {
     put_counts(k.out, vt, bt, k.npix, k.overwrite);
 }
 
-__device__ __forceinline__ void reduce_counts(bn_frame_stats *work, bn_frame_stats *out,
+__device__ __forceinline__ void reduce_counts(WorkArea *work, bn_frame_stats *out,
                                               uint32_t part, uint32_t nparts, uint32_t nvalid,
                                               uint32_t nboundary, uint32_t npix,
                                               uint32_t overwrite) {

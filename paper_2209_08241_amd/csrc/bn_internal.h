@@ -29,15 +29,20 @@ const VariantInfo *variant_info(int v);
 int check_params_args(const bn_params *p);
 int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, float fx,
                      float fy, float cx, float cy, const float *normals, const uint8_t *mask);
-// A bn_frame_stats pointer: NULL or 128-byte aligned.
+// A bn_frame_stats pointer: NULL or 4-byte aligned.
 int check_stats_arg(const bn_frame_stats *stats);
+// The count work areas (BN_MAX_STACK of them) of the current device's
+// `stream` (bn_workspace.hip); BN_ERR_UNSUPPORTED beyond BN_MAX_STREAMS
+// streams of a device.
+int stream_work_areas(hipStream_t stream, WorkArea **out);
 // True when the frame can use the 4-pixel vector tiles.
 bool vec4_layout(const float *depth, int32_t W, int64_t stride, const float *normals,
                  const uint8_t *mask);
 // True when the method can take vector tiles (multi-scale: alpha * scales
 // <= kMsVecReach).
 bool method_has_vec4(const bn_params *p);
-// Per-frame kernel arguments (derived constants included).
+// Per-frame kernel arguments (derived constants included); work = NULL (the
+// caller sets the count work area when stats is given).
 void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t stride,
                      float fx, float fy, float cx, float cy, const bn_params *p, float *normals,
                      uint8_t *mask, bn_frame_stats *stats, int px_per_item);

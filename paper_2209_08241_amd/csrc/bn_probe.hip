@@ -6,6 +6,7 @@
 //     same LDS staging as the vector tiles (three contiguous KiB per
 //     wavefront) and 4 bytes of "codes" out.
 #include "bn_internal.h"
+#include "bn_probe.h"
 #include "bn_tiles.h"
 #include "bnormals.h"
 

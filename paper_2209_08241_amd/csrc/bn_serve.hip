@@ -156,7 +156,7 @@ class HipBackend : public Backend {
     int init(size_t budget, int32_t max_batch, int32_t in_flight, const bn_params &params) {
         params_ = params;
         // each request's counts are its own: the batch stores them
-        params_.flags |= BN_FLAG_COUNTS_OVERWRITE;
+        params_.flags &= ~BN_FLAG_COUNTS_ACCUMULATE;
         max_batch_ = max_batch;
         plans_.assign((size_t)in_flight + 1, nullptr);
         if (hipMalloc(&arena_, budget ? budget : 1) != hipSuccess) return BN_ERR_OOM;

@@ -124,6 +124,10 @@ extern "C" int bn_estimate_normals_stack(const float *depth, int32_t n, int32_t 
     }
     StackFn fn = stack_kernel(params->method, params->alpha, params->scales, vec);
     if (!fn) return BN_ERR_UNSUPPORTED;
+    if (stats) {
+        rc = stream_work_areas((hipStream_t)stream, &s.f.work);
+        if (rc != BN_OK) return rc;
+    }
     s.vec = vec ? 1u : 0u;
     s.tiles_per_frame = (s.f.nitems + kBlock - 1) / kBlock;
     const uint64_t grid = (uint64_t)s.tiles_per_frame * s.n;

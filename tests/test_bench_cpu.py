@@ -53,3 +53,18 @@ def test_one_gpu_only():
 def test_adjoint_summary_hashes_the_adjoint_sources():
     assert bench.kernel_hash(bench.ADJOINT_SOURCES) != bench.kernel_hash()
     assert "bn_adjoint.hip" in bench.ADJOINT_SOURCES
+
+
+def test_inputs_generated_up_front_and_pool_joined():
+    """Every host frame comes from one process pool that is shut down before
+    the function returns (so no child outlives it, and nothing forks after
+    the GPU is initialised)."""
+    import argparse
+    import multiprocessing
+    args = argparse.Namespace(workload="plain1080", distinct=2, ring=32, no_batch=True,
+                              no_serve=True, quick=True)
+    inp = bench.generate_inputs(args)
+    assert list(inp) == ["plain"] and len(inp["plain"]) == 2
+    assert [s.seed for s in inp["plain"]] == [2, 3]
+    assert inp["plain"][0].depth.shape == (1080, 1920)
+    assert multiprocessing.active_children() == []

@@ -35,13 +35,13 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(bn.Params) == 32
-    assert ctypes.sizeof(bn.FrameStats) == bn.STATS_BYTES == 4224
+    assert ctypes.sizeof(bn.FrameStats) == bn.STATS_BYTES == 16 and bn.STATS_WORDS == 4
     assert ctypes.sizeof(bn.Frame) == 64
 
 
 def test_version_and_status_strings():
     L = bn.lib()
-    assert L.bn_version() == 2
+    assert L.bn_version() == 3
     for s in range(5):
         assert L.bn_status_string(s)
     assert L.bn_status_string(99) == b"unknown status"
@@ -86,8 +86,8 @@ def test_flags_and_reserved_checked():
     p.flags = 2
     assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, p, 0x20000,
                                    0x30000, 0) == bn.BN_ERR_INVALID_ARG
-    p = bn.make_params(overwrite_counts=True)
-    assert p.flags == bn.FLAG_COUNTS_OVERWRITE
+    p = bn.make_params(accumulate_counts=True)
+    assert p.flags == bn.FLAG_COUNTS_ACCUMULATE
     p.reserved = 1
     assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, p, 0x20000,
                                    0x30000, 0) == bn.BN_ERR_INVALID_ARG
@@ -178,7 +178,7 @@ def test_alignment_checked_before_launch():
     assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, p, 0x20001, 0x30000,
                                    0) == bn.BN_ERR_INVALID_ARG
     assert bn.raw_estimate_normals(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, p, 0x20000, 0x30000,
-                                   0x40040) == bn.BN_ERR_INVALID_ARG
+                                   0x40042) == bn.BN_ERR_INVALID_ARG
 
 
 def test_stack_argument_errors():
@@ -220,3 +220,32 @@ def test_stack_argument_errors():
         bn.BN_ERR_UNSUPPORTED
     assert adj(3, 8, 8, 8, 64, good, params=bn.make_params(variant=1)) == bn.BN_ERR_UNSUPPORTED
     assert adj(3, 8, 8, 8, 64, good, gd=0x30002) == bn.BN_ERR_INVALID_ARG
+
+
+def test_binding_refuses_short_or_wrong_stats():
+    """bn_frame_stats is 4 words; the binding refuses any tensor the C ABI
+    could write past (shorter, strided, wrong type) before any call."""
+    import torch
+    cpu = torch.device("cpu")
+    bn._check_stats(torch.zeros(4, dtype=torch.int32), (4,), cpu)
+    bn._check_stats(torch.zeros(3, 4, dtype=torch.int32), (3, 4), cpu)
+    for bad, shape in ((torch.zeros(3, dtype=torch.int32), (4,)),
+                       (torch.zeros(8, dtype=torch.int32)[::2], (4,)),
+                       (torch.zeros(4, dtype=torch.int64), (4,)),
+                       (torch.zeros(2, 4, dtype=torch.int32), (3, 4)),
+                       (torch.zeros(12, dtype=torch.int32), (3, 4)),
+                       (torch.zeros(4, 8, dtype=torch.int32)[:, :4], (4, 4))):
+        with pytest.raises(ValueError):
+            bn._check_stats(bad, shape, cpu)
+
+
+def test_binding_refuses_bad_grad_depth():
+    """The adjoint writes H*W dense floats: the binding refuses a gradient
+    buffer of another shape, type or layout before any call."""
+    import torch
+    cpu = torch.device("cpu")
+    bn._check_grad_depth(torch.zeros(6, 8), (6, 8), cpu)
+    for bad in (torch.zeros(5, 8), torch.zeros(6, 8, dtype=torch.float64),
+                torch.zeros(8, 6).t(), torch.zeros(48), None):
+        with pytest.raises(ValueError):
+            bn._check_grad_depth(bad, (6, 8), cpu)

@@ -119,8 +119,9 @@ def test_update_and_repeat():
                 continue
             ref = oracle.normals_f32(d, fr.fx, fr.fy, fr.cx, fr.cy, 2, "rel", 4.0)
             st = fr.stats.cpu()
-            assert st[:3].tolist() == [3 * int(c) for c in ref["counts"]]
-            assert not st[4:].any()
+            # each run stores the frame's counts (not added up over the runs)
+            assert st[:3].tolist() == [int(c) for c in ref["counts"]]
+            assert int(st[3]) == 0
         # a different, shorter list through the same plan (same graph)
         new = [scenes.sized_frame(240, 320, seed=77), scenes.sized_frame(480, 640, seed=78)]
         nf = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in new]
@@ -229,7 +230,8 @@ def test_small_lists(method, alpha, K):
     """Lists of at most 16 frames carry their descriptors in the kernel
     arguments and reduce their counts in the same kernel: outputs and counts
     equal the plain launches, through the graph and through plain launches,
-    and repeated runs add the counts (the scratch work areas return to zero)."""
+    and repeated runs with the accumulate flag add the counts (the work
+    areas return to zero)."""
     import torch
     rng = np.random.default_rng(alpha * 10 + K)
     sizes = [(97, 131), (240, 320), (0, 8), (33, 64), (480, 640), (5, 7)]
@@ -244,7 +246,8 @@ def test_small_lists(method, alpha, K):
             frames.append(bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy))
     for n in (1, 4, len(frames)):
         sub = frames[:n]
-        with bn.BatchPlan(sub, alpha, "rel", 4.0, method=method, scales=K) as plan:
+        with bn.BatchPlan(sub, alpha, "rel", 4.0, method=method, scales=K,
+                          accumulate_counts=True) as plan:
             for how in ("run", "launch"):
                 for f in sub:
                     f.stats.zero_()
@@ -257,13 +260,13 @@ def test_small_lists(method, alpha, K):
 
 def test_small_and_table_lists_through_one_plan():
     """One plan alternates between lists above and below the small-list
-    limit; every list's outputs equal the plain launches, and a list of 16
-    frames with the overwrite flag stores its counts."""
+    limit; every list's outputs equal the plain launches, and every list
+    stores its counts over whatever the stats held."""
     import torch
     pool = [scenes.sized_frame(H, W, seed=400 + k) for k, (H, W) in
             enumerate([(120, 160), (97, 131), (240, 320), (64, 64)] * 6)]
     frames = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in pool]
-    with bn.BatchPlan(frames, 2, "rel", 4.0, overwrite_counts=True) as plan:
+    with bn.BatchPlan(frames, 2, "rel", 4.0) as plan:
         for n, how in ((3, "launch"), (24, "run"), (16, "run"), (17, "launch"), (1, "run"),
                        (24, "launch"), (2, "launch")):
             sub = frames[:n]
@@ -271,7 +274,7 @@ def test_small_and_table_lists_through_one_plan():
             for f in sub:
                 f.normals.fill_(5.0)
                 f.mask.fill_(7)
-                f.stats.fill_(3)   # overwritten counts; garbage elsewhere is not read
+                f.stats.fill_(3)   # stored over: counts and reserved word
             getattr(plan, how)()
             torch.cuda.synchronize()
             info = plan.info()
@@ -282,28 +285,29 @@ def test_small_and_table_lists_through_one_plan():
                 n_, m_, st_ = _plain_outputs(f, 2, "rel", 4.0)
                 assert torch.equal(f.normals.view(torch.int32), n_.view(torch.int32)), (n, k)
                 assert torch.equal(f.mask, m_), (n, k)
-                assert f.stats[:3].tolist() == st_[:3].tolist(), (n, k)
+                assert f.stats.tolist() == st_.tolist(), (n, k)
 
 
 def test_large_frame_counts_in_chunks():
     """A frame of more than 4096 tiles has its counts summed in chunks that
     combine through the plan's work area: counts equal the plain launch's,
-    added over repeated runs and stored with the overwrite flag."""
+    stored by default and added over repeated runs with the accumulate
+    flag."""
     import torch
     big = scenes.sized_frame(3072, 4096, seed=700)
     small = [scenes.sized_frame(40, 64, seed=701 + k) for k in range(16)]
     frames = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in [big] + small]
     want = [_plain_outputs(f, 2, "rel", 4.0)[2][:3].tolist() for f in frames]
-    for overwrite in (False, True):
-        with bn.BatchPlan(frames, 2, "rel", 4.0, overwrite_counts=overwrite) as plan:
+    for accumulate in (True, False):
+        with bn.BatchPlan(frames, 2, "rel", 4.0, accumulate_counts=accumulate) as plan:
             for f in frames:
                 f.stats.zero_()
             for how in ("run", "launch", "run"):
                 getattr(plan, how)()
             torch.cuda.synchronize()
-            times = 1 if overwrite else 3
+            times = 3 if accumulate else 1
             for k, f in enumerate(frames):
-                assert f.stats[:3].tolist() == [times * c for c in want[k]], (overwrite, k)
+                assert f.stats[:3].tolist() == [times * c for c in want[k]], (accumulate, k)
     n, m, _ = _plain_outputs(frames[0], 2, "rel", 4.0)
     assert torch.equal(frames[0].normals.view(torch.int32), n.view(torch.int32))
     assert torch.equal(frames[0].mask, m)

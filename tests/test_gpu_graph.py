@@ -14,7 +14,7 @@ def test_plain_launches_replayed_from_a_graph():
     import torch
     s = scenes.frame_640x480(seed=1)
     d = torch.from_numpy(s.depth).cuda()
-    n, m, st = bn.estimate_normals(d, *s.intrinsics, 2, overwrite_counts=True)
+    n, m, st = bn.estimate_normals(d, *s.intrinsics, 2)
     torch.cuda.synchronize()
     ref = (n.clone(), m.clone(), st[:3].clone())
     n2 = torch.full_like(n, 7.0)
@@ -24,10 +24,11 @@ def test_plain_launches_replayed_from_a_graph():
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
         bn.estimate_normals(d, *s.intrinsics, 2, normals=n2, mask=m2, stats=st2,
-                            overwrite_counts=True, stream=torch.cuda.current_stream())
+                            stream=torch.cuda.current_stream())
     for rep in range(4):
         n2.fill_(float(rep))            # eager work between replays
         m2.fill_(200 + rep)
+        st2.fill_(-1)
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
@@ -43,10 +44,10 @@ def test_batch_plan_runs_repeatedly_with_eager_work_between():
               for s in frames_h]
     refs = []
     for s, f in zip(frames_h, frames):
-        n, m, st = bn.estimate_normals(f.depth, s.fx, s.fy, s.cx, s.cy, 2, overwrite_counts=True)
+        n, m, st = bn.estimate_normals(f.depth, s.fx, s.fy, s.cx, s.cy, 2)
         refs.append((n, m, st[:3].clone()))
     torch.cuda.synchronize()
-    with bn.BatchPlan(frames, 2, "rel", 4.0, overwrite_counts=True) as plan:
+    with bn.BatchPlan(frames, 2, "rel", 4.0) as plan:
         for rep in range(4):
             for f in frames:
                 f.normals.fill_(float(rep))

@@ -28,7 +28,7 @@ def f1080():
 def test_library_is_native():
     import torch
     assert torch.cuda.is_available()
-    assert bn.lib().bn_version() == 2
+    assert bn.lib().bn_version() == 3
     names = dict(bn.variants())
     assert names[1] == "scalar" and names[2] == "vec4"
 
@@ -154,20 +154,31 @@ def test_deterministic_and_variant_invariant(f1080):
         assert np.array_equal(st, s0)
 
 
-def test_stats_accumulate(f640):
+def test_stats_store_and_accumulate(f640):
+    """Counts are stored by default (over whatever the 16 bytes held, the
+    reserved word included) and added with the accumulate flag; every
+    variant, repeated calls on one stream (whose work area each call leaves
+    zero) and a second stream give the same counts."""
     import torch
     s = f640
     d = to_gpu(s.depth)
-    ref = oracle.normals_f32(s.depth, *s.intrinsics, 2)
+    ref = [int(c) for c in oracle.normals_f32(s.depth, *s.intrinsics, 2)["counts"]]
+    side = torch.cuda.Stream()
     for variant in [0] + ALL_VARIANTS:
-        st = bn.new_stats()
+        st = torch.full((4,), -5, dtype=torch.int32, device="cuda")
         for _ in range(3):
             bn.estimate_normals(d, *s.intrinsics, 2, stats=st, variant=variant)
         torch.cuda.synchronize()
-        h = st.cpu()
-        assert h[:3].tolist() == [3 * int(c) for c in ref["counts"]]
-        # the reduction workspace is left zero
-        assert not h[4:].any()
+        assert st.cpu().tolist() == ref + [0], f"variant {variant}: stored counts"
+        acc = bn.new_stats()
+        for _ in range(3):
+            bn.estimate_normals(d, *s.intrinsics, 2, stats=acc, variant=variant,
+                                accumulate_counts=True)
+        with torch.cuda.stream(side):
+            bn.estimate_normals(d, *s.intrinsics, 2, stats=acc, variant=variant,
+                                accumulate_counts=True, stream=side)
+        torch.cuda.synchronize()
+        assert acc.cpu().tolist() == [4 * c for c in ref] + [0], f"variant {variant}: added"
 
 
 def test_argument_errors():

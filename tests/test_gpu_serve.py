@@ -1,13 +1,17 @@
-"""Serving on the GPU: every request's result is the same as the frame's
-result alone (bit for bit), whatever it was batched with, including under
-budget pressure; the Poisson load generator completes."""
+"""Serving on the GPU: every request's result matches the FP64 oracle on its
+frame (masks and counts bit-exact, normals within 1e-5 per component) and is
+the same as the frame's result alone (bit for bit), whatever it was batched
+with, for device and host depth, every serving size (4096x3072 included),
+every method and under budget pressure; the Poisson load generator
+completes."""
 import ctypes
 
 import numpy as np
 import pytest
 
+import oracle
 import paper_2209_08241_amd as bn
-from gpu_util import log
+from gpu_util import assert_parity, log
 from synth import scenes
 
 pytestmark = pytest.mark.gpu
@@ -20,6 +24,14 @@ def serve_frames():
     for k, (H, W) in enumerate(scenes.SERVE_SIZES):
         out.append(scenes.sized_frame(H, W, seed=3000 + k))
     return out
+
+
+@pytest.fixture(scope="module")
+def oracle_refs(serve_frames):
+    """The oracle on every serving size (four-pair, alpha 2, REL tau 4)."""
+    log("oracle on the serving sizes")
+    return [oracle.normals_f32(s.depth, s.fx, s.fy, s.cx, s.cy, 2, "rel", 4.0)
+            for s in serve_frames]
 
 
 def alone(s, depth_t):
@@ -43,7 +55,7 @@ def check_same(a, b, what):
     assert np.array_equal(a[2].astype(np.int64), b[2].astype(np.int64)), f"{what}: counts differ"
 
 
-def test_results_are_the_same_alone_and_in_the_mix(serve_frames):
+def test_results_are_the_same_alone_and_in_the_mix(serve_frames, oracle_refs):
     import torch
     dev = [torch.from_numpy(s.depth).cuda() for s in serve_frames]
     host = [torch.from_numpy(s.depth).pin_memory() for s in serve_frames]
@@ -64,10 +76,17 @@ def test_results_are_the_same_alone_and_in_the_mix(serve_frames):
             info = srv.wait(rid, 60.0)
             assert info["state"] == bn.REQ_DONE, info
             H, W = serve_frames[k].depth.shape
-            check_same(served(info, H, W), refs[k], f"request {rid} size {W}x{H} host={on_host}")
+            got = served(info, H, W)
+            what = f"request {rid} size {W}x{H} host={on_host}"
+            assert_parity(oracle_refs[k], got[0], got[1], got[2], what=what + " vs oracle")
+            check_same(got, refs[k], what)
             srv.release(rid)
         st = srv.stats()
         log(f"mix: {st['batches']} launches, largest {st['max_batch_seen']} frames")
+        # every size, the 4096x3072 frame included, went through the server
+        assert set(k for _, k, _ in reqs) == set(range(len(serve_frames)))
+        assert any(h for _, k, h in reqs if k == big) and any(not h for _, k, h in reqs
+                                                              if k == big)
         assert st["completed"] == 40 and st["bytes_in_use"] == 0
         assert st["max_batch_seen"] > 1      # some requests were launched together
 
@@ -89,7 +108,7 @@ def test_burst_is_batched(serve_frames):
             assert st["max_batch_seen"] <= max_batch
 
 
-def test_budget_pressure_queues_but_completes(serve_frames):
+def test_budget_pressure_queues_but_completes(serve_frames, oracle_refs):
     import torch
     dev = [torch.from_numpy(s.depth).cuda() for s in serve_frames]
     refs = [alone(s, d) for s, d in zip(serve_frames, dev)]
@@ -106,7 +125,9 @@ def test_budget_pressure_queues_but_completes(serve_frames):
             info = srv.wait(rid, 60.0)
             assert info["state"] == bn.REQ_DONE
             H, W = serve_frames[k].depth.shape
-            check_same(served(info, H, W), refs[k], f"request {rid}")
+            got = served(info, H, W)
+            assert_parity(oracle_refs[k], got[0], got[1], got[2], what=f"request {rid} vs oracle")
+            check_same(got, refs[k], f"request {rid}")
             srv.release(rid)
         st = srv.stats()
         assert st["peak_bytes_in_use"] <= budget and st["completed"] == 12
@@ -127,22 +148,37 @@ def test_poisson_load_completes(serve_frames):
 
 @pytest.mark.parametrize("method,alpha,K", [("pair_removal", 2, 0), ("multiscale", 1, 3),
                                            ("multiscale", 3, 4)])
-def test_methods_served_equal_alone(serve_frames, method, alpha, K):
+def test_methods_served_match_oracle_and_alone(serve_frames, method, alpha, K):
+    """Each method's server, on every serving size (4096x3072 included),
+    device and host depth: every request matches the oracle and its plain
+    launch."""
     import torch
-    frames = serve_frames[:4]
+    frames = serve_frames
     dev = [torch.from_numpy(s.depth).cuda() for s in frames]
-    refs = []
+    host = [torch.from_numpy(s.depth).pin_memory() for s in frames]
+    refs, orefs = [], []
     for s, d in zip(frames, dev):
         n, m, st = bn.estimate_normals(d, s.fx, s.fy, s.cx, s.cy, alpha, "rel", 4.0,
                                        method=method, scales=K)
         torch.cuda.synchronize()
         refs.append((n.cpu().numpy(), m.cpu().numpy(), st.cpu().numpy()[:3]))
+        orefs.append(oracle.variant_f32(s.depth, s.fx, s.fy, s.cx, s.cy, alpha, "rel", 4.0,
+                                        method=method, scales=K))
+    nf = len(frames)
     with bn.Server(4 << 30, max_batch=8, max_batches_in_flight=2, alpha=alpha, method=method,
                    scales=K) as srv:
-        reqs = [(srv.submit(dev[k % 4], frames[k % 4].fx, frames[k % 4].fy, frames[k % 4].cx,
-                            frames[k % 4].cy), k % 4) for k in range(12)]
-        for rid, k in reqs:
-            info = srv.wait(rid, timeout=30.0)
+        reqs = []
+        for k in range(2 * nf):
+            s = frames[k % nf]
+            on_host = k >= nf
+            rid = srv.submit(host[k % nf] if on_host else dev[k % nf], s.fx, s.fy, s.cx, s.cy)
+            reqs.append((rid, k % nf, on_host))
+        for rid, k, on_host in reqs:
+            info = srv.wait(rid, timeout=60.0)
+            assert info["state"] == bn.REQ_DONE, info
             H, W = frames[k].depth.shape
-            check_same(served(info, H, W), refs[k], f"{method} request {rid}")
+            got = served(info, H, W)
+            what = f"{method} request {rid} {W}x{H} host={on_host}"
+            assert_parity(orefs[k], got[0], got[1], got[2], what=what + " vs oracle")
+            check_same(got, refs[k], what)
             srv.release(rid)

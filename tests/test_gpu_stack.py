@@ -118,7 +118,7 @@ def test_stack_of_64_and_of_1():
     _assert_stack_equals_single(one, _stack(one), 2, "rel", 4.0)
 
 
-def test_stack_counts_add_or_overwrite():
+def test_stack_counts_store_or_accumulate():
     import torch
     frames = _frames(3, 240, 320, seed=60)
     d = _stack(frames)
@@ -128,13 +128,13 @@ def test_stack_counts_add_or_overwrite():
         want.append(_single(d[k], s, 2, "rel", 4.0)[2][:3].tolist())
     st = bn.new_stats(3, device="cuda")
     for _ in range(2):
-        bn.estimate_normals_stack(d, intr, stats=st)
+        bn.estimate_normals_stack(d, intr, stats=st, accumulate_counts=True)
     torch.cuda.synchronize()
     assert st[:, :3].tolist() == [[2 * c for c in w] for w in want]
-    bn.estimate_normals_stack(d, intr, stats=st, overwrite_counts=True)
+    st.fill_(-3)
+    bn.estimate_normals_stack(d, intr, stats=st)
     torch.cuda.synchronize()
-    assert st[:, :3].tolist() == want
-    assert not st[:, 4:].any()   # the reduction's workspace is clear again
+    assert st.tolist() == [w + [0] for w in want]
 
 
 @pytest.mark.parametrize("alpha", [1, 2, 3])

@@ -1,7 +1,7 @@
 """GPU parity of the pair-removal and multi-scale methods against the
 oracle (masks and counts bit-exact, normals within 1e-5 per component), the
 batched form of each against its plain form (bit for bit), and the
-overwrite flag of the counts."""
+store / accumulate semantics of the counts."""
 import numpy as np
 import pytest
 
@@ -174,8 +174,8 @@ def test_batch_equals_plain(method, alpha, K):
 
 
 @pytest.mark.parametrize("method,K", [("four_pair", 0), (PR, 0), (MS, 2)])
-def test_counts_overwrite_flag(f640, method, K):
-    """Added by default, replaced with BN_FLAG_COUNTS_OVERWRITE (plain and
+def test_counts_store_and_accumulate_flag(f640, method, K):
+    """Stored by default, added with BN_FLAG_COUNTS_ACCUMULATE (plain and
     batched)."""
     import torch
     s = f640
@@ -184,17 +184,16 @@ def test_counts_overwrite_flag(f640, method, K):
     want = [int(c) for c in ref["counts"]]
     st = bn.new_stats(device="cuda")
     for _ in range(3):
-        bn.estimate_normals(d, *s.intrinsics, 2, method=method, scales=K, stats=st)
+        bn.estimate_normals(d, *s.intrinsics, 2, method=method, scales=K, stats=st,
+                            accumulate_counts=True)
     torch.cuda.synchronize()
     assert st[:3].cpu().tolist() == [3 * c for c in want]
     for _ in range(3):
-        bn.estimate_normals(d, *s.intrinsics, 2, method=method, scales=K, stats=st,
-                            overwrite_counts=True)
+        bn.estimate_normals(d, *s.intrinsics, 2, method=method, scales=K, stats=st)
     torch.cuda.synchronize()
     assert st[:3].cpu().tolist() == want
     fr = bn.BatchFrame(d, *s.intrinsics)
-    with bn.BatchPlan([fr], 2, "rel", 4.0, method=method, scales=K,
-                      overwrite_counts=True) as plan:
+    with bn.BatchPlan([fr], 2, "rel", 4.0, method=method, scales=K) as plan:
         for _ in range(3):
             plan.run()
         torch.cuda.synchronize()
