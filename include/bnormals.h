@@ -326,6 +326,29 @@ int bn_batch_plan_info(const bn_batch_plan *plan, int64_t *n_pixels, int64_t *n_
 void bn_batch_plan_destroy(bn_batch_plan *plan);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * small-list launch of bn_batch_launch without a plan.  Allocates nothing
+ * (no hipMalloc / hipFree, no allocating library routine): the frame
+ * descriptors travel in the kernel arguments and the per-frame count work
+ * areas are a fixed array in device memory, BN_NOALLOC_MAX_FRAMES areas of
+ * 4224 bytes (67.6 KB), which each GPU the library runs on holds until the
+ * process ends.
+ *   frames_host  [n_frames] frames as for a plan (device pointers, validated
+ *                as by bn_batch_plan_create), 1 <= n_frames <=
+ *                BN_NOALLOC_MAX_FRAMES (more: BN_ERR_UNSUPPORTED)
+ *   params       as for a plan (variant 0)
+ * Each frame's outputs and counts are those of bn_estimate_normals.  Two
+ * kernels on `stream`: a fill kernel that zeroes the work areas, then the
+ * batch.  Every call on a GPU shares that GPU's array (it keeps the last
+ * call's contents), so calls that overlap in time on one GPU - on different
+ * streams, or graph replays - race and must not be issued.
+ */
+#define BN_NOALLOC_MAX_FRAMES 16
+int bn_estimate_normals_batch_noalloc(const bn_frame *frames_host, int32_t n_frames,
+                                      const bn_params *params, void *stream);
+
+/*
  * Autotuning.  Choices are kept per process in a table keyed by GPU
  * architecture, alpha and frame-size class (bit length of the pixel count);
  * when the environment variable BN_AUTOTUNE_CACHE names a file, the table

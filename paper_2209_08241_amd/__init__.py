@@ -163,6 +163,9 @@ def _bind_batch(L) -> None:
     L.bn_batch_launch.restype = ctypes.c_int
     L.bn_batch_plan_destroy.argtypes = [vp]
     L.bn_batch_plan_destroy.restype = None
+    L.bn_estimate_normals_batch_noalloc.argtypes = [ctypes.POINTER(Frame), i32,
+                                                    ctypes.POINTER(Params), vp]
+    L.bn_estimate_normals_batch_noalloc.restype = ctypes.c_int
     L.bn_batch_plan_autotune.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
     L.bn_batch_plan_autotune.restype = ctypes.c_int
     L.bn_autotune_plain.argtypes = [i32, i32, ctypes.POINTER(Params), ctypes.POINTER(i32),
@@ -453,6 +456,25 @@ class BatchPlan:
         import torch
         torch.cuda.synchronize()
         self.close()
+
+
+NOALLOC_MAX_FRAMES = 16   # BN_NOALLOC_MAX_FRAMES
+
+
+def estimate_normals_batch_noalloc(frames, alpha: int = 2, mode="rel", tau: float = 4.0, *,
+                                   method="four_pair", scales: int = 0,
+                                   accumulate_counts: bool = False, stream=None) -> None:
+    """At most NOALLOC_MAX_FRAMES BatchFrames in one launch through
+    bn_estimate_normals_batch_noalloc, which allocates nothing (its count
+    work areas are a fixed device array shared by every call on the GPU:
+    calls must not overlap in time)."""
+    frames = list(frames)
+    arr = (Frame * max(len(frames), 1))(*[f._c() for f in frames])
+    p = make_params(alpha, mode, tau, 0, method, scales, accumulate_counts)
+    rc = lib().bn_estimate_normals_batch_noalloc(arr, len(frames), ctypes.byref(p),
+                                                 ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_estimate_normals_batch_noalloc")
 
 
 # ---------------------------------------------------------------------------

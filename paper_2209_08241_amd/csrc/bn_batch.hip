@@ -26,6 +26,7 @@
 // This is the latency path of a server's small batches.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "bn_device.h"
@@ -367,20 +368,21 @@ int build_table(const bn_frame *frames, int32_t n, const bn_params *p, int32_t c
     return BN_OK;
 }
 
-// The kernel-argument image of a small list (already validated).
-void build_small(bn_batch_plan *pl, const bn_frame *frames, int32_t n) {
-    SmallBatch &sb = pl->small;
+// The kernel-argument image of a small list (already validated); frame k
+// reduces its counts on work[k].
+void fill_small(SmallBatch &sb, const bn_frame *frames, int32_t n, const bn_params *params,
+                WorkArea *work) {
     std::memset(&sb, 0, sizeof(sb));
     uint32_t tiles = 0;
     for (int k = 0; k < kSmallFrames; ++k) sb.tile_begin[k] = UINT32_MAX;
     for (int32_t k = 0; k < n; ++k) {
         const bn_frame &s = frames[k];
-        const bool vec = frame_vec(s, &pl->params);
+        const bool vec = frame_vec(s, params);
         uint32_t nt = 0;
         if (s.height > 0 && s.width > 0) {
             fill_frame_args(sb.f[k], s.depth, s.height, s.width, s.depth_stride, s.fx, s.fy, s.cx,
-                            s.cy, &pl->params, s.normals, s.mask, s.stats, vec ? 4 : 1);
-            sb.f[k].work = pl->work + k;
+                            s.cy, params, s.normals, s.mask, s.stats, vec ? 4 : 1);
+            sb.f[k].work = work + k;
             nt = (sb.f[k].nitems + kBlock - 1) / kBlock;
         }
         sb.tile_begin[k] = tiles;
@@ -390,6 +392,10 @@ void build_small(bn_batch_plan *pl, const bn_frame *frames, int32_t n) {
     }
     sb.nframes = (uint32_t)n;
     sb.ntiles = tiles;
+}
+
+void build_small(bn_batch_plan *pl, const bn_frame *frames, int32_t n) {
+    fill_small(pl->small, frames, n, &pl->params, pl->work);
 }
 
 hipKernelNodeParams kernel_params(void *func, dim3 grid, void **args) {
@@ -809,3 +815,72 @@ int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_bloc
 void bn_batch_plan_destroy(bn_batch_plan *plan) { free_plan(plan); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The allocation-free batched launch: the small-list kernel of
+// bn_batch_launch, with its count work areas in a fixed device array
+// instead of a plan's allocation.
+// ---------------------------------------------------------------------------
+namespace {
+
+// One count work area per frame of a list of at most BN_NOALLOC_MAX_FRAMES;
+// each GPU holds its own copy until the process ends.
+__device__ __align__(256) WorkArea scratch[BN_NOALLOC_MAX_FRAMES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+WorkArea *g_scratch[kMaxDevices];  // scratch's device address, per device
+
+__global__ __launch_bounds__(256) void k_clear_words(unsigned long long *p, uint32_t words) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < words) p[i] = 0ull;
+}
+
+// scratch's address on the current device, looked up once per device with
+// that device current (the array's name is only a host-side stand-in).
+int scratch_for_current_device(WorkArea **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BN_ERR_DEVICE;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return BN_ERR_DEVICE;
+        g_scratch[dev] = static_cast<WorkArea *>(p);
+    }
+    *out = g_scratch[dev];
+    return BN_OK;
+}
+
+}  // namespace
+
+extern "C" int bn_estimate_normals_batch_noalloc(const bn_frame *frames_host, int32_t n_frames,
+                                                 const bn_params *params, void *stream) {
+    if (!frames_host || n_frames < 1) return BN_ERR_INVALID_ARG;
+    int rc = check_params_args(params);
+    if (rc != BN_OK) return rc;
+    if (n_frames > BN_NOALLOC_MAX_FRAMES) return BN_ERR_UNSUPPORTED;
+    if (params->variant != VAR_AUTO) return BN_ERR_UNSUPPORTED;
+    SmallKernelFn fn = small_kernel(params->method, params->alpha, params->scales);
+    if (!fn) return BN_ERR_UNSUPPORTED;
+    uint64_t tiles = 0, pixels = 0;
+    rc = count_frames(frames_host, n_frames, params, &tiles, &pixels);
+    if (rc != BN_OK) return rc;
+    if (tiles == 0) return BN_OK;  // only empty frames
+    WorkArea *work = nullptr;
+    rc = scratch_for_current_device(&work);
+    if (rc != BN_OK) return rc;
+    SmallBatch sb;
+    fill_small(sb, frames_host, n_frames, params, work);
+    hipStream_t s = (hipStream_t)stream;
+    // the work areas must start at zero: a fill kernel (graph-capture safe)
+    const uint32_t words = (uint32_t)((size_t)n_frames * sizeof(WorkArea) / 8);
+    hipLaunchKernelGGL(k_clear_words, dim3((words + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long *>(work), words);
+    if (hipGetLastError() != hipSuccess) return BN_ERR_DEVICE;
+    void *args[1] = {(void *)&sb};
+    return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(sb.ntiles), dim3(kBlock), args,
+                           0, s) == hipSuccess
+               ? BN_OK
+               : BN_ERR_DEVICE;
+}

@@ -249,3 +249,19 @@ def test_binding_refuses_bad_grad_depth():
                 torch.zeros(8, 6).t(), torch.zeros(48), None):
         with pytest.raises(ValueError):
             bn._check_grad_depth(bad, (6, 8), cpu)
+
+
+def test_noalloc_argument_errors_before_launch():
+    """bn_estimate_normals_batch_noalloc validates before any HIP call."""
+    L = bn.lib()
+    p = bn.make_params()
+    fr = (bn.Frame * 17)(*[bn.Frame(0x10000, 8, 8, 8, 500.0, 500.0, 3.5, 3.5, 0x20000,
+                                    0x30000, 0)] * 17)
+    call = L.bn_estimate_normals_batch_noalloc
+    assert call(None, 1, ctypes.byref(p), None) == bn.BN_ERR_INVALID_ARG
+    assert call(fr, 0, ctypes.byref(p), None) == bn.BN_ERR_INVALID_ARG
+    assert call(fr, 17, ctypes.byref(p), None) == bn.BN_ERR_UNSUPPORTED
+    assert call(fr, 2, ctypes.byref(bn.make_params(alpha=0)), None) == bn.BN_ERR_INVALID_ARG
+    assert call(fr, 2, ctypes.byref(bn.make_params(variant=2)), None) == bn.BN_ERR_UNSUPPORTED
+    bad = (bn.Frame * 1)(bn.Frame(0x10000, 8, 8, 7, 500.0, 500.0, 3.5, 3.5, 0x20000, 0x30000, 0))
+    assert call(bad, 1, ctypes.byref(p), None) == bn.BN_ERR_INVALID_ARG
