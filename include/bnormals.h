@@ -354,21 +354,27 @@ int bn_estimate_normals_batch_noalloc(const bn_frame *frames_host, int32_t n_fra
  * when the environment variable BN_AUTOTUNE_CACHE names a file, the table
  * is loaded from it on first use and saved to it after each tuning.
  *
- * bn_autotune_plain: times every kernel variant of bn_estimate_normals on
- *   a ring of scratch frames of height x width (allocated and freed here,
- *   about 512 MiB) and records the fastest; later calls with params->variant
- *   == 0 on frames of that size class use it.  Synchronous.
- * bn_batch_plan_autotune: times the plan's launch with the flat grid (one
- *   workgroup per tile; *best_blocks_per_cu = 0) and with 2, 4 and 8
- *   persistent workgroups per compute unit, keeps the fastest for this plan
+ * bn_autotune_plain: times every kernel variant (tile shape) of
+ *   bn_estimate_normals that the method and layout allow - scalar or vector
+ *   work items; workgroups of 256, 128 or 64 threads; one, two or four tiles
+ *   per workgroup or a software-pipelined pair - on a ring of scratch frames
+ *   of height x width (allocated and freed here, about 512 MiB, a synthetic
+ *   scene with steps, noise and holes) and records the fastest; later calls
+ *   with params->variant == 0 on frames of that size class use it.
+ *   Synchronous.
+ * bn_batch_plan_autotune: times the plan's launch over its grid shapes - a
+ *   flat grid of one tile per workgroup (*best_shape = 0), of two or four
+ *   consecutive tiles per workgroup (-2, -4), or 2, 4 or 8 persistent
+ *   workgroups per compute unit (2, 4, 8) - keeps the fastest for this plan
  *   and records it for new plans of the same size class.  It RUNS the plan
- *   (outputs are rewritten, counts accumulate): zero the counts afterwards.
+ *   (outputs and counts are rewritten; with BN_FLAG_COUNTS_ACCUMULATE the
+ *   counts accumulate).
  * bn_autotune_save / _load: write / read the table as JSON.
  * bn_autotune_reset: forget every entry.  bn_autotune_entries: table size.
  */
 int bn_autotune_plain(int32_t height, int32_t width, const bn_params *params,
                       int32_t *best_variant, float *best_us);
-int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_blocks_per_cu,
+int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_shape,
                            float *best_us);
 int bn_autotune_save(const char *path);
 int bn_autotune_load(const char *path);

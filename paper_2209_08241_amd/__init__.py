@@ -426,9 +426,10 @@ class BatchPlan:
         self._frames = frames
 
     def autotune(self, stream=None):
-        """Time the flat grid (one workgroup per tile) and 2/4/8 persistent
-        workgroups per CU, keep the fastest (runs the plan: counts
-        accumulate).  Returns (workgroups per CU or 0 for flat, microseconds)."""
+        """Time the plan's grid shapes - a flat grid of 1, 2 or 4 tiles per
+        workgroup (shape 0, -2, -4) or 2, 4, 8 persistent workgroups per CU
+        (shape 2, 4, 8) - and keep the fastest (runs the plan).  Returns
+        (shape, microseconds)."""
         best, us = ctypes.c_int32(), ctypes.c_float()
         rc = lib().bn_batch_plan_autotune(self._h, ctypes.c_void_p(_stream_handle(stream)),
                                           ctypes.byref(best), ctypes.byref(us))

@@ -1,6 +1,9 @@
-// Autotuner: measured choice of the plain kernel variant per (method, alpha,
-// frame size class) and of the grid shape (flat, or persistent workgroups
-// per compute unit) of batch plans.  Choices live in a process-wide table keyed by the GPU
+// Autotuner: measured choice of the plain kernel's tile shape (variant:
+// scalar or vector work items; 64, 128 or 256 threads per workgroup; one,
+// two or four tiles per workgroup, or a software-pipelined pair) per (method,
+// alpha, frame size class), and of the grid shape of batch plans (a flat
+// grid of one, two or four tiles per workgroup, or 2, 4 or 8 persistent
+// workgroups per compute unit).  Choices live in a process-wide table keyed by the GPU
 // architecture name; the table can be saved to and loaded from a small JSON
 // file, and is loaded from $BN_AUTOTUNE_CACHE on first use when that is set.
 #include <cstdio>
@@ -23,7 +26,7 @@ struct Entry {
     int method;
     int alpha;
     int cls;    // bit length of the pixel count
-    int value;  // variant id or workgroups per CU
+    int value;  // variant id, or batch grid shape (-1, -2, -4 flat; k > 0 persistent)
     float us;
 };
 
@@ -129,7 +132,7 @@ int tuned_plain_variant(int method, int alpha, uint64_t pixels) {
     return e ? e->value : 0;
 }
 
-int tuned_batch_blocks_per_cu(int method, int alpha, uint64_t pixels) {
+int tuned_batch_shape(int method, int alpha, uint64_t pixels) {
     std::lock_guard<std::mutex> g(g_mu);
     ensure_env_loaded_locked();
     if (g_table.empty()) return 0;
@@ -150,6 +153,28 @@ void record_tuning(int kind, int method, int alpha, uint64_t pixels, int value, 
 using namespace bn;
 
 namespace {
+
+// Timing frames with the cost structure of real scenes: a tilted, rippled
+// surface 1.5 - 3 m away with step edges, depth noise growing as z^2 and 2%
+// holes, so that every branch of each method is taken where it would be.
+__global__ __launch_bounds__(256) void k_tune_scene(float *d, int32_t H, int32_t W,
+                                                    uint32_t seed) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    if (i >= (uint64_t)H * (uint64_t)W) return;
+    const uint32_t y = (uint32_t)(i / (uint32_t)W), x = (uint32_t)(i % (uint32_t)W);
+    float z = 2.2f + 0.3f * __sinf(0.011f * (float)x + (float)seed) +
+              0.2f * __cosf(0.017f * (float)y) + 0.0002f * (float)x;
+    if ((x / 131u + y / 97u + seed) % 4u == 0u) z -= 0.6f;  // step edges
+    uint32_t h = x * 0x9e3779b1u ^ (y + 0x7f4a7c15u * (seed + 1u)) * 0x85ebca77u;
+    h ^= h >> 15;
+    h *= 0x2c1b3c6du;
+    h ^= h >> 12;
+    // noise of spread 0.001 z^2 (sum of two uniforms, mean 0)
+    const float u = (float)(h & 0xffffu) * (1.0f / 65536.0f) +
+                    (float)((h >> 16) & 0x7fffu) * (1.0f / 32768.0f) - 1.0f;
+    z += 0.001f * z * z * 1.7f * u;
+    d[i] = (h % 50u == 7u) ? 0.0f : z;  // 2% holes
+}
 
 struct Scratch {
     std::vector<void *> ptrs;
@@ -191,11 +216,9 @@ int bn_autotune_plain(int32_t height, int32_t width, const bn_params *params, in
         n[k] = static_cast<float *>(s.alloc(px * 12));
         m[k] = static_cast<uint8_t *>(s.alloc(px));
         if (!d[k] || !n[k] || !m[k]) return BN_ERR_OOM;
-        // a fronto plane at 1.5 m: every pixel takes the full arithmetic path
-        const float v = 1.5f;
-        uint32_t bits;
-        std::memcpy(&bits, &v, 4);
-        if (hipMemsetD32(d[k], (int)bits, px) != hipSuccess) return BN_ERR_DEVICE;
+        hipLaunchKernelGGL(k_tune_scene, dim3((uint32_t)((px + 255) / 256)), dim3(256), 0,
+                           nullptr, d[k], height, width, (uint32_t)k);
+        if (hipGetLastError() != hipSuccess) return BN_ERR_DEVICE;
     }
     if (hipMemset(st, 0, sizeof(bn_frame_stats) * ring) != hipSuccess) return BN_ERR_DEVICE;
     hipEvent_t e0, e1;

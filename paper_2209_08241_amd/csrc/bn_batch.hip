@@ -252,7 +252,8 @@ struct bn_batch_plan {
     int32_t capacity = 0;          // frames
     uint64_t tile_capacity = 0;    // entries of the tile -> frame table
     int cus = 0;
-    uint32_t blocks_per_cu = 0;    // 0: flat grid
+    int32_t shape = 0;             // grid shape (kFlat, -2, -4: tiles per workgroup; k > 0:
+                                   // k persistent workgroups per compute unit)
     uint32_t grid = 0;
     size_t buf_bytes = 0;
     // device buffer and two pinned host images of it:
@@ -288,7 +289,7 @@ struct bn_batch_plan {
 
 namespace {
 
-constexpr uint32_t kFlat = 0;  // blocks_per_cu value of the flat shape
+constexpr int32_t kFlat = 0;  // shape of the flat grid, one tile per workgroup
 
 size_t table_offset(int32_t capacity) {
     return sizeof(BatchHeader) + sizeof(BatchFrame) * (size_t)capacity;
@@ -326,9 +327,15 @@ int count_frames(const bn_frame *frames, int32_t n, const bn_params *p, uint64_t
     return BN_OK;
 }
 
-uint32_t grid_for(uint64_t tiles, int cus, uint32_t blocks_per_cu) {
-    if (blocks_per_cu == kFlat) return tiles ? (uint32_t)tiles : 1u;
-    return (uint32_t)cus * blocks_per_cu;
+// Workgroups of a grid shape: shape <= 0 is a flat grid of max(1, -shape)
+// consecutive tiles per workgroup; shape > 0 is `shape` persistent
+// workgroups per compute unit.
+uint32_t grid_for(uint64_t tiles, int cus, int32_t shape) {
+    if (shape <= 0) {
+        const uint64_t per = shape < -1 ? (uint64_t)(-shape) : 1u;
+        return tiles ? (uint32_t)((tiles + per - 1) / per) : 1u;
+    }
+    return (uint32_t)cus * (uint32_t)shape;
 }
 
 // Host image of the descriptors of `frames` (already validated) in `base`.
@@ -575,9 +582,9 @@ int bn_batch_plan_create(const bn_frame *frames_host, int32_t n_frames, const bn
     pl->cus = cus;
     // the grid shape tuned for this alpha and batch size class, if recorded
     // (the table stores the flat shape as -1)
-    const int tuned = tuned_batch_blocks_per_cu(params->method, params->alpha, pixels);
-    pl->blocks_per_cu = tuned > 0 ? (uint32_t)tuned : kFlat;
-    pl->grid = grid_for(tiles, cus, pl->blocks_per_cu);
+    const int tuned = tuned_batch_shape(params->method, params->alpha, pixels);
+    pl->shape = tuned == -1 ? kFlat : tuned;
+    pl->grid = grid_for(tiles, cus, pl->shape);
     pl->total_tiles = tiles;
     pl->total_pixels = pixels;
     for (int k = 0; k < 2; ++k) {
@@ -637,7 +644,7 @@ int bn_batch_plan_update(bn_batch_plan *plan, const bn_frame *frames_host, int32
         return BN_OK;
     }
     plan->small_mode = false;
-    const uint32_t grid = grid_for(tiles, plan->cus, plan->blocks_per_cu);
+    const uint32_t grid = grid_for(tiles, plan->cus, plan->shape);
     if (tiles > 0 && (tiles + grid - 1) / grid > 4096) return BN_ERR_UNSUPPORTED;
     if (tiles > plan->tile_capacity) {
         // a larger tile table: wait for every use of the old buffers first
@@ -730,18 +737,18 @@ int bn_batch_plan_info(const bn_batch_plan *plan, int64_t *n_pixels, int64_t *n_
 
 // Re-grid the plan: new chunk and workgroup count in the graph's kernel
 // arguments (they take effect at the next run).
-static int set_grid(bn_batch_plan *plan, uint32_t blocks_per_cu, hipStream_t stream) {
+static int set_grid(bn_batch_plan *plan, int32_t shape, hipStream_t stream) {
     (void)stream;
-    const uint32_t grid = grid_for(plan->hdr.ntiles, plan->cus, blocks_per_cu);
+    const uint32_t grid = grid_for(plan->hdr.ntiles, plan->cus, shape);
     const uint32_t chunk = plan->hdr.ntiles ? (plan->hdr.ntiles + grid - 1) / grid : 0;
     if (chunk > 4096) return BN_ERR_UNSUPPORTED;
-    plan->blocks_per_cu = blocks_per_cu;
+    plan->shape = shape;
     plan->grid = grid;
     plan->hdr.chunk = chunk;
     return refresh_node(plan);
 }
 
-int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_blocks_per_cu,
+int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_shape,
                            float *best_us) {
     if (!plan || !plan->exec) return BN_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
@@ -764,16 +771,16 @@ int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_bloc
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc != BN_OK) return rc;
-        if (best_blocks_per_cu) *best_blocks_per_cu = 0;
+        if (best_shape) *best_shape = kFlat;
         if (best_us) *best_us = 1000.f * ms / reps;
         return BN_OK;
     }
-    const uint32_t cands[] = {kFlat, 2, 4, 8};
-    uint32_t best = 0;
+    const int32_t cands[] = {kFlat, -2, -4, 2, 4, 8};
+    int32_t best = kFlat;
     bool found = false;
     float best_t = 1e30f;
     int rc = BN_OK;
-    for (uint32_t c : cands) {
+    for (int32_t c : cands) {
         rc = set_grid(plan, c, s);
         if (rc == BN_ERR_UNSUPPORTED) continue;
         if (rc != BN_OK) break;
@@ -807,7 +814,7 @@ int bn_batch_plan_autotune(bn_batch_plan *plan, void *stream, int32_t *best_bloc
     // the table stores the flat shape as -1 (0 means "nothing recorded")
     record_tuning(1, plan->params.method, plan->params.alpha, plan->total_pixels,
                   best == kFlat ? -1 : (int)best, best_t);
-    if (best_blocks_per_cu) *best_blocks_per_cu = (int32_t)best;
+    if (best_shape) *best_shape = best;
     if (best_us) *best_us = best_t;
     return BN_OK;
 }

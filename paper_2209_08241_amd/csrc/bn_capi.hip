@@ -83,6 +83,11 @@ static bool method_variant_ok(const bn_params *p, int v, const float *depth, int
     const VariantInfo *vi = variant_info(v);
     if (!vi) return false;
     if (vi->px_per_item == 4 && !method_has_vec4(p)) return false;
+    // the pipelined pair of tiles and the small workgroups serve the
+    // five-tap methods
+    if ((v == VAR_VEC4_P2 || v == VAR_VEC4_W128 || v == VAR_VEC4_W64) &&
+        p->method == BN_METHOD_MULTISCALE)
+        return false;
     return variant_ok(v, depth, W, stride, normals, mask);
 }
 

@@ -241,16 +241,35 @@ __device__ __forceinline__ PixelOut eval_pixel(bool inside, float d1, float d2, 
 // four-pair m, taken in its closed form (d1 cancels exactly there, while the
 // rounded sum of the pairs can lose it to cancellation).
 // ---------------------------------------------------------------------------
-struct PairVec {
-    float mx, my, mz;  // mz: negated third component
-    float q;
-    uint32_t keep;     // 1 when the pair passes the test
-    uint32_t ok;       // 1 when q is a finite number >= FLT_MIN
+// The binary32 test of one pair, in the order written above: bit 0 set when
+// the pair passes (keep), bit 1 when its q is a finite number >= FLT_MIN.
+__device__ __forceinline__ uint32_t pair_keep_ok(float A, float B, float C, float xc, float yc,
+                                                 const FrameArgs &f) {
+    const float mx = f.fx * A;
+    const float my = f.fy * B;
+    const float xa = xc * A;
+    const float yb = yc * B;
+    const float t3 = xa + yb;
+    const float w = f.af * C;
+    const float mz = t3 + w;
+    const float mx2 = mx * mx;
+    const float my2 = my * my;
+    const float mz2 = mz * mz;
+    const float q = (mx2 + my2) + mz2;
+    const float ww = w * w;
+    const float hrel = f.tt * ww;
+    const float h = f.rel ? hrel : f.hconst;
+    return (q > h ? 0u : 1u) | (q_ok(q) << 1);
+}
+
+// The pair's vector (mx, my, mz), the same operations as its test.
+struct PairM {
+    float mx, my, mz;
 };
 
-__device__ __forceinline__ PairVec pair_vec(float A, float B, float C, float xc, float yc,
-                                            const FrameArgs &f) {
-    PairVec r;
+__device__ __forceinline__ PairM pair_m(float A, float B, float C, float xc, float yc,
+                                        const FrameArgs &f) {
+    PairM r;
     r.mx = f.fx * A;
     r.my = f.fy * B;
     const float xa = xc * A;
@@ -258,18 +277,43 @@ __device__ __forceinline__ PairVec pair_vec(float A, float B, float C, float xc,
     const float t3 = xa + yb;
     const float w = f.af * C;
     r.mz = t3 + w;
+    return r;
+}
+
+// The four-pair closed form m and q (the sequence of eval_terms, no test).
+struct ClosedM {
+    float mx, my, mz, q;
+};
+
+__device__ __forceinline__ ClosedM closed_m(float d2, float d3, float d4, float d5, float xc,
+                                            float yc, const FrameArgs &f) {
+    const float P = d2 - d4;
+    const float S = d2 + d4;
+    const float Q = d3 - d5;
+    const float T = d3 + d5;
+    const float a = T * P;
+    const float b = S * Q;
+    const float c = S * T;
+    ClosedM r;
+    r.mx = f.fx * a;
+    r.my = f.fy * b;
+    const float xa = xc * a;
+    const float yb = yc * b;
+    const float t3 = xa + yb;
+    const float w = f.af * c;
+    r.mz = t3 + w;
     const float mx2 = r.mx * r.mx;
     const float my2 = r.my * r.my;
     const float mz2 = r.mz * r.mz;
     r.q = (mx2 + my2) + mz2;
-    const float ww = w * w;
-    const float hrel = f.tt * ww;
-    const float h = f.rel ? hrel : f.hconst;
-    r.keep = r.q > h ? 0u : 1u;
-    r.ok = q_ok(r.q);
     return r;
 }
 
+// Pair removal.  First the four tests only (no pair vector stays live), then
+// the closed form; the sum of the passing pairs - needed only where some
+// pair fails, which most wavefronts never see - recomputes those pairs'
+// vectors behind a wavefront-uniform branch.  The same operations in the
+// same order as a single pass, so the same bits.
 __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, float d2, float d3,
                                                      float d4, float d5, float xc, float yc,
                                                      const FrameArgs &f) {
@@ -278,41 +322,46 @@ __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, floa
     const float e4 = d4 - d1;
     const float e5 = d5 - d1;
     // (h, v) = (2, 3), (4, 3), (4, 5), (2, 5); sh, sv = ++, -+, --, +-
-    const PairVec p0 = pair_vec(e2 * d3, d2 * e3, d2 * d3, xc, yc, f);
-    const PairVec p1 = pair_vec(-(e4 * d3), d4 * e3, d4 * d3, xc, yc, f);
-    const PairVec p2 = pair_vec(-(e4 * d5), -(d4 * e5), d4 * d5, xc, yc, f);
-    const PairVec p3 = pair_vec(e2 * d5, -(d2 * e5), d2 * d5, xc, yc, f);
-    const bool all = (p0.keep & p1.keep & p2.keep & p3.keep) != 0u;
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f, Qs = 0.0f;
-    // the sum of the passing pairs serves only pixels where some pair
-    // fails; most wavefronts have none and skip it (a uniform branch)
-    if (__any(!all)) {
-        sx = sx + (p0.keep ? p0.mx : 0.0f);
-        sy = sy + (p0.keep ? p0.my : 0.0f);
-        sz = sz + (p0.keep ? p0.mz : 0.0f);
-        sx = sx + (p1.keep ? p1.mx : 0.0f);
-        sy = sy + (p1.keep ? p1.my : 0.0f);
-        sz = sz + (p1.keep ? p1.mz : 0.0f);
-        sx = sx + (p2.keep ? p2.mx : 0.0f);
-        sy = sy + (p2.keep ? p2.my : 0.0f);
-        sz = sz + (p2.keep ? p2.mz : 0.0f);
-        sx = sx + (p3.keep ? p3.mx : 0.0f);
-        sy = sy + (p3.keep ? p3.my : 0.0f);
-        sz = sz + (p3.keep ? p3.mz : 0.0f);
-        const float sx2 = sx * sx;
-        const float sy2 = sy * sy;
-        const float sz2 = sz * sz;
-        Qs = (sx2 + sy2) + sz2;
-    }
+    const uint32_t r0 = pair_keep_ok(e2 * d3, d2 * e3, d2 * d3, xc, yc, f);
+    const uint32_t r1 = pair_keep_ok(-(e4 * d3), d4 * e3, d4 * d3, xc, yc, f);
+    const uint32_t r2 = pair_keep_ok(-(e4 * d5), -(d4 * e5), d4 * d5, xc, yc, f);
+    const uint32_t r3 = pair_keep_ok(e2 * d5, -(d2 * e5), d2 * d5, xc, yc, f);
+    const uint32_t keep = (r0 & 1u) | ((r1 & 1u) << 1) | ((r2 & 1u) << 2) | ((r3 & 1u) << 3);
+    const bool all = keep == 0xfu;
     // all four pass: the four-pair closed form, in which d1 cancels exactly
-    const PixelTerms t = eval_terms(inside, d1, d2, d3, d4, d5, xc, yc, f);
-    sx = all ? t.mx : sx;
-    sy = all ? t.my : sy;
-    sz = all ? t.mz : sz;
-    const float Q = all ? t.q : Qs;
+    const ClosedM c = closed_m(d2, d3, d4, d5, xc, yc, f);
+    float sx = c.mx, sy = c.my, sz = c.mz, Q = c.q;
+    if (__any(!all)) {
+        // the passing pairs summed in pair order from +0
+        float tx = 0.0f, ty = 0.0f, tz = 0.0f;
+        const PairM p0 = pair_m(e2 * d3, d2 * e3, d2 * d3, xc, yc, f);
+        tx = tx + ((keep & 1u) ? p0.mx : 0.0f);
+        ty = ty + ((keep & 1u) ? p0.my : 0.0f);
+        tz = tz + ((keep & 1u) ? p0.mz : 0.0f);
+        const PairM p1 = pair_m(-(e4 * d3), d4 * e3, d4 * d3, xc, yc, f);
+        tx = tx + ((keep & 2u) ? p1.mx : 0.0f);
+        ty = ty + ((keep & 2u) ? p1.my : 0.0f);
+        tz = tz + ((keep & 2u) ? p1.mz : 0.0f);
+        const PairM p2 = pair_m(-(e4 * d5), -(d4 * e5), d4 * d5, xc, yc, f);
+        tx = tx + ((keep & 4u) ? p2.mx : 0.0f);
+        ty = ty + ((keep & 4u) ? p2.my : 0.0f);
+        tz = tz + ((keep & 4u) ? p2.mz : 0.0f);
+        const PairM p3 = pair_m(e2 * d5, -(d2 * e5), d2 * d5, xc, yc, f);
+        tx = tx + ((keep & 8u) ? p3.mx : 0.0f);
+        ty = ty + ((keep & 8u) ? p3.my : 0.0f);
+        tz = tz + ((keep & 8u) ? p3.mz : 0.0f);
+        const float tx2 = tx * tx;
+        const float ty2 = ty * ty;
+        const float tz2 = tz * tz;
+        const float Qs = (tx2 + ty2) + tz2;
+        sx = all ? sx : tx;
+        sy = all ? sy : ty;
+        sz = all ? sz : tz;
+        Q = all ? Q : Qs;
+    }
     const bool ok = ((inside ? 1u : 0u) & tap_ok(d1) & tap_ok(d2) & tap_ok(d3) & tap_ok(d4) &
-                     tap_ok(d5) & p0.ok & p1.ok & p2.ok & p3.ok) != 0u;
-    const bool any = (p0.keep | p1.keep | p2.keep | p3.keep) != 0u;
+                     tap_ok(d5) & (r0 >> 1) & (r1 >> 1) & (r2 >> 1) & (r3 >> 1)) != 0u;
+    const bool any = keep != 0u;
     PixelOut o;
     o.code = !ok ? (uint32_t)BN_INVALID
                  : (!any ? (uint32_t)BN_BOUNDARY
@@ -524,10 +573,11 @@ __device__ __forceinline__ void reduce_counts(WorkArea *work, bn_frame_stats *ou
     count_finish(count_issue(work, out, part, nparts, nvalid, nboundary, npix, overwrite));
 }
 
-// Block-wide sum of wave-uniform counts (one workgroup barrier): the totals,
-// valid in thread 0 only.
+// Block-wide sum of wave-uniform counts over a workgroup of TB threads (one
+// workgroup barrier): the totals, valid in thread 0 only.
+template <int TB = kBlock>
 __device__ __forceinline__ void block_sum(uint32_t cv, uint32_t cb, uint32_t &v, uint32_t &b) {
-    __shared__ uint32_t s_cnt[kBlock / 64][2];
+    __shared__ uint32_t s_cnt[TB / 64][2];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
     if (lane == 0) {
@@ -539,7 +589,7 @@ __device__ __forceinline__ void block_sum(uint32_t cv, uint32_t cb, uint32_t &v,
     b = 0;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) {
+        for (int w = 0; w < TB / 64; ++w) {
             v += s_cnt[w][0];
             b += s_cnt[w][1];
         }

@@ -13,7 +13,10 @@ enum Variant {
     VAR_VEC4 = 2,     // 4 pixels per thread, 16-byte vector loads/stores
     VAR_VEC4_G2 = 3,  // 2 groups of 4 pixels per thread
     VAR_VEC4_G4 = 4,  // 4 groups of 4 pixels per thread
-    VAR_COUNT = 4
+    VAR_VEC4_P2 = 5,  // 2 groups of 4 pixels per thread, second tile's loads ahead
+    VAR_VEC4_W128 = 6,  // 4 pixels per thread, workgroups of 128 threads
+    VAR_VEC4_W64 = 7,   // 4 pixels per thread, workgroups of 64 threads
+    VAR_COUNT = 7
 };
 
 struct VariantInfo {
@@ -21,6 +24,7 @@ struct VariantInfo {
     const char *name;
     int px_per_item;        // pixels per work item (1 or 4)
     int groups_per_thread;  // work items per thread
+    int block;              // threads per workgroup
 };
 
 const VariantInfo *variant_info(int v);
@@ -61,7 +65,9 @@ bool batch_plan_uploads(const bn_batch_plan *plan);
 
 // Autotuning table (bn_autotune.hip): 0 when nothing is recorded.
 int tuned_plain_variant(int method, int alpha, uint64_t pixels);
-int tuned_batch_blocks_per_cu(int method, int alpha, uint64_t pixels);
+// batch grid shape as recorded: -1 flat, -2 / -4 flat with 2 / 4 tiles per
+// workgroup, k > 0 persistent workgroups per compute unit
+int tuned_batch_shape(int method, int alpha, uint64_t pixels);
 void record_tuning(int kind, int method, int alpha, uint64_t pixels, int value, float us);
 
 // Launch one frame with the given variant and method.  FrameArgs.gpr /

@@ -54,6 +54,26 @@ __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
     if (f.stats) block_counts(f, blk, gridDim.x, cv, cb);
 }
 
+// Vector kernel, two tiles per workgroup, software-pipelined (the second
+// tile's loads in flight during the first tile's arithmetic and stores); the
+// five-tap methods only.
+template <int A, int M>
+__global__ __launch_bounds__(kBlock) void k_vec4p(FrameArgs f) {
+    __shared__ TileLds lds;
+    const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
+    vec4_tile_pair_counted<A, M>(f, 2 * blk, 2 * blk + 1, blk, gridDim.x, lds);
+}
+
+// Vector kernel with workgroups of TB = 64 or 128 threads (tiles of 256 or
+// 512 pixels): more, smaller workgroups for small frames; the five-tap
+// methods only.
+template <int A, int M, int TB>
+__global__ __launch_bounds__(TB) void k_vec4w(FrameArgs f) {
+    __shared__ TileLdsT<TB> lds;
+    const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
+    vec4_tile_counted<A, M, TB>(f, blk, blk, gridDim.x, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Launch table
 // ---------------------------------------------------------------------------
@@ -80,6 +100,9 @@ template <int A, int M> struct ScalarK { static constexpr KernelFn fn = k_scalar
 template <int A, int M> struct Vec4G1 { static constexpr KernelFn fn = k_vec4<A, 1, M>; };
 template <int A, int M> struct Vec4G2 { static constexpr KernelFn fn = k_vec4<A, 2, M>; };
 template <int A, int M> struct Vec4G4 { static constexpr KernelFn fn = k_vec4<A, 4, M>; };
+template <int A, int M> struct Vec4P2 { static constexpr KernelFn fn = k_vec4p<A, M>; };
+template <int A, int M> struct Vec4W128 { static constexpr KernelFn fn = k_vec4w<A, M, 128>; };
+template <int A, int M> struct Vec4W64 { static constexpr KernelFn fn = k_vec4w<A, M, 64>; };
 
 template <int M>
 static KernelFn plain_kernel(int variant, int alpha) {
@@ -88,15 +111,27 @@ static KernelFn plain_kernel(int variant, int alpha) {
         case VAR_VEC4: return AlphaTable<Vec4G1, M>::get(alpha);
         case VAR_VEC4_G2: return AlphaTable<Vec4G2, M>::get(alpha);
         case VAR_VEC4_G4: return AlphaTable<Vec4G4, M>::get(alpha);
+        case VAR_VEC4_P2:
+            if constexpr (!is_multiscale(M)) return AlphaTable<Vec4P2, M>::get(alpha);
+            return nullptr;
+        case VAR_VEC4_W128:
+            if constexpr (!is_multiscale(M)) return AlphaTable<Vec4W128, M>::get(alpha);
+            return nullptr;
+        case VAR_VEC4_W64:
+            if constexpr (!is_multiscale(M)) return AlphaTable<Vec4W64, M>::get(alpha);
+            return nullptr;
     }
     return nullptr;
 }
 
 const VariantInfo kVariants[] = {
-    {VAR_SCALAR, "scalar", 1, 1},
-    {VAR_VEC4, "vec4", 4, 1},
-    {VAR_VEC4_G2, "vec4x2", 4, 2},
-    {VAR_VEC4_G4, "vec4x4", 4, 4},
+    {VAR_SCALAR, "scalar", 1, 1, kBlock},
+    {VAR_VEC4, "vec4", 4, 1, kBlock},
+    {VAR_VEC4_G2, "vec4x2", 4, 2, kBlock},
+    {VAR_VEC4_G4, "vec4x4", 4, 4, kBlock},
+    {VAR_VEC4_P2, "vec4p2", 4, 2, kBlock},
+    {VAR_VEC4_W128, "vec4w128", 4, 1, 128},
+    {VAR_VEC4_W64, "vec4w64", 4, 1, 64},
 };
 
 const VariantInfo *variant_info(int v) {
@@ -122,10 +157,10 @@ hipError_t launch_plain(int variant, int method, const FrameArgs &f, hipStream_t
                  : plain_kernel<kMultiScale>(variant, f.alpha);
     }
     if (!fn) return hipErrorInvalidValue;
-    const uint64_t per_block = (uint64_t)kBlock * vi->groups_per_thread;
+    const uint64_t per_block = (uint64_t)vi->block * vi->groups_per_thread;
     const uint64_t nblocks = (f.nitems + per_block - 1) / per_block;
     if (nblocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(kBlock), 0, stream, f);
+    hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(vi->block), 0, stream, f);
     return hipGetLastError();
 }
 

@@ -16,11 +16,15 @@
 
 namespace bn {
 
-// LDS staging area of one tile: 3 float4 (12 floats) per vector work item,
-// or 3 floats per scalar work item; wavefront w owns v[192w .. 192w+191].
-struct TileLds {
-    f4 v[3 * kBlock];
+// LDS staging area of one tile of TB work items: 3 float4 (12 floats) per
+// vector work item, or 3 floats per scalar work item; wavefront w owns
+// v[192w .. 192w+191].  Tiles are kBlock = 256 work items except in the
+// plain kernels' smaller-workgroup variants (TB = 64 or 128).
+template <int TB = kBlock>
+struct TileLdsT {
+    f4 v[3 * TB];
 };
+using TileLds = TileLdsT<kBlock>;
 
 // Orders this wavefront's LDS accesses for the compiler; the hardware
 // already executes them in order.  Emits no wait instruction.
@@ -47,14 +51,34 @@ struct Vec4Out {
     bool live;
 };
 
-template <int A, int M>
-__device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec4Out &o) {
+// Methods whose tile writes each pixel's normal into the wavefront's LDS
+// slice as soon as it is computed, instead of holding the 12 floats of the
+// thread's four pixels in registers until the stores (pair removal: its
+// per-pixel working set would otherwise push the kernel past 64 VGPRs, below
+// eight wavefronts per SIMD).
+template <int M>
+constexpr bool kEarlyStage = M == kPairRemoval;
+
+// The loads of a vector work item, kept apart from its arithmetic so that a
+// workgroup can issue one tile's loads before another tile's arithmetic.
+// edge[k]: lane 0's float4 k to the left of the wavefront's row segment,
+// lane 63's float4 k to the right (other lanes: unused).
+template <int A>
+struct Vec4In {
+    f4 c, up, dn;
+    f4 edge[Win<A>::R];
+    uint32_t y, x0;
+    bool live, rows_in;
+};
+
+template <int A, int TB = kBlock>
+__device__ __forceinline__ void vec4_load(const FrameArgs &f, uint32_t tile, Vec4In<A> &in) {
     constexpr int R = Win<A>::R;
     const uint32_t t = threadIdx.x;
     const uint32_t lane = t & 63u;
-    const uint32_t i = tile * kBlock + t;
+    const uint32_t i = tile * TB + t;
     const bool live = i < f.nitems;
-    o.live = live;
+    in.live = live;
     // Every load is unconditional: a lane past the frame's last item takes
     // the last item's position, and a row A above or below that leaves the
     // frame is replaced by row y itself.  What such a load brings in only
@@ -63,17 +87,41 @@ __device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec
     const uint32_t il = live ? i : f.nitems - 1u;
     const uint32_t y = row_of(il, f.inv_gpr);
     const uint32_t x0 = (il - y * f.gpr) * 4u;
+    in.y = y;
+    in.x0 = x0;
     const float *rp = f.depth + (int64_t)y * f.stride;
-    const bool rows_in = live & (y >= (uint32_t)A) & (y + A < (uint32_t)f.H);
+    in.rows_in = live & (y >= (uint32_t)A) & (y + A < (uint32_t)f.H);
     const int64_t su = y >= (uint32_t)A ? (int64_t)A * f.stride : 0;
     const int64_t sd = y + A < (uint32_t)f.H ? (int64_t)A * f.stride : 0;
-    const f4 c = *reinterpret_cast<const f4 *>(rp + x0);
-    const f4 up = *reinterpret_cast<const f4 *>(rp - su + x0);
-    const f4 dn = *reinterpret_cast<const f4 *>(rp + sd + x0);
+    in.c = *reinterpret_cast<const f4 *>(rp + x0);
+    in.up = *reinterpret_cast<const f4 *>(rp - su + x0);
+    in.dn = *reinterpret_cast<const f4 *>(rp + sd + x0);
+    // the first / last lane of the wave loads the float4s its neighbours
+    // cannot pass it (clamped into the row)
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+        in.edge[k - 1] = f4{0.f, 0.f, 0.f, 0.f};
+        if (lane == 0) in.edge[k - 1] = *reinterpret_cast<const f4 *>(rp + max((int)x0 - 4 * k, 0));
+        if (lane == 63)
+            in.edge[k - 1] = *reinterpret_cast<const f4 *>(rp + min((int)x0 + 4 * k, f.W - 4));
+    }
+}
+
+// The arithmetic of a vector work item from its loads.  Every lane of the
+// workgroup must call this (DPP lane shifts).
+template <int A, int M, int TB = kBlock>
+__device__ __forceinline__ void vec4_compute(const FrameArgs &f, const Vec4In<A> &in, Vec4Out &o,
+                                             TileLdsT<TB> &lds) {
+    constexpr int R = Win<A>::R;
+    const uint32_t t = threadIdx.x;
+    const uint32_t lane = t & 63u;
+    o.live = in.live;
+    const uint32_t y = in.y, x0 = in.x0;
+    const f4 c = in.c, up = in.up, dn = in.dn;
     // Row window x0-4R .. x0+4+4R-1.  Neighbouring float4s come from the
-    // adjacent lanes; the first / last lane of the wave loads its missing
-    // float4 itself (clamped into the row).  Values taken across a row end
-    // only feed border pixels, which are INVALID whatever they hold.
+    // adjacent lanes; the first / last lane of the wave takes its loaded
+    // edge.  Values taken across a row end only feed border pixels, which
+    // are INVALID whatever they hold.
     float row[Win<A>::N];
     row[4 * R + 0] = c.x;
     row[4 * R + 1] = c.y;
@@ -84,8 +132,8 @@ __device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec
     for (int k = 1; k <= R; ++k) {
         lk = from_left(lk);
         rk = from_right(rk);
-        if (lane == 0) lk = *reinterpret_cast<const f4 *>(rp + max((int)x0 - 4 * k, 0));
-        if (lane == 63) rk = *reinterpret_cast<const f4 *>(rp + min((int)x0 + 4 * k, f.W - 4));
+        if (lane == 0) lk = in.edge[k - 1];
+        if (lane == 63) rk = in.edge[k - 1];
         row[4 * (R - k) + 0] = lk.x;
         row[4 * (R - k) + 1] = lk.y;
         row[4 * (R - k) + 2] = lk.z;
@@ -99,20 +147,37 @@ __device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec
     const float dnv[4] = {dn.x, dn.y, dn.z, dn.w};
     const float yc = (float)y - f.cy;
     uint32_t codes = 0;
+    // early staging: this lane's 12 floats of the wavefront's LDS slice
+    float *st = reinterpret_cast<float *>(lds.v + 192 * (t >> 6)) + 12 * lane;
+    if (kEarlyStage<M>) wave_lds_sync();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const uint32_t x = x0 + j;
-        const bool inside = rows_in & (x >= (uint32_t)A) & (x + A < (uint32_t)f.W);
+        const bool inside = in.rows_in & (x >= (uint32_t)A) & (x + A < (uint32_t)f.W);
         const float xc = (float)x - f.cx;
         const int cI = 4 * R + j;
         const PixelOut p = eval_method<M>(inside, row[cI], row[cI + A], dnv[j], row[cI - A],
                                           upv[j], xc, yc, f);
-        o.nv[3 * j + 0] = p.nx;
-        o.nv[3 * j + 1] = p.ny;
-        o.nv[3 * j + 2] = p.nz;
+        if (kEarlyStage<M>) {
+            st[3 * j + 0] = p.nx;
+            st[3 * j + 1] = p.ny;
+            st[3 * j + 2] = p.nz;
+        } else {
+            o.nv[3 * j + 0] = p.nx;
+            o.nv[3 * j + 1] = p.ny;
+            o.nv[3 * j + 2] = p.nz;
+        }
         codes |= p.code << (8 * j);
     }
     o.codes = codes;
+}
+
+template <int A, int M, int TB = kBlock>
+__device__ __forceinline__ void vec4_eval(const FrameArgs &f, uint32_t tile, Vec4Out &o,
+                                          TileLdsT<TB> &lds) {
+    Vec4In<A> in;
+    vec4_load<A, TB>(f, tile, in);
+    vec4_compute<A, M, TB>(f, in, o, lds);
 }
 
 // Multi-scale vector tile (alpha * scales <= REACH): the taps lie right of and
@@ -195,11 +260,12 @@ __device__ __forceinline__ void vec4_eval_ms(const FrameArgs &f, uint32_t tile, 
 
 // The vector tile of method M.
 template <int A, int M>
-__device__ __forceinline__ void vec4_eval_method(const FrameArgs &f, uint32_t tile, Vec4Out &o) {
+__device__ __forceinline__ void vec4_eval_method(const FrameArgs &f, uint32_t tile, Vec4Out &o,
+                                                 TileLds &lds) {
     if constexpr (is_multiscale(M)) {
         vec4_eval_ms<A, M == kMultiScaleLong ? kMsVecReach : kMsShortReach>(f, tile, o);
     } else {
-        vec4_eval<A, M>(f, tile, o);
+        vec4_eval<A, M>(f, tile, o, lds);
     }
 }
 
@@ -207,21 +273,24 @@ __device__ __forceinline__ void vec4_eval_method(const FrameArgs &f, uint32_t ti
 // normal floats through the wavefront's LDS slice with contiguous 16-byte
 // stores (lane l holds groups 3l..3l+2 of the slice; store k writes
 // float4s 64k .. 64k+63 of it, one contiguous KiB).
-__device__ __forceinline__ void vec4_write(const FrameArgs &f, uint32_t tile, TileLds &lds,
+template <int M, int TB = kBlock>
+__device__ __forceinline__ void vec4_write(const FrameArgs &f, uint32_t tile, TileLdsT<TB> &lds,
                                            const Vec4Out &o) {
     const uint32_t t = threadIdx.x;
     const uint32_t lane = t & 63u;
-    const uint32_t i = tile * kBlock + t;
+    const uint32_t i = tile * TB + t;
     const float *nv = o.nv;
     if (o.live) __builtin_nontemporal_store(o.codes, reinterpret_cast<uint32_t *>(f.mask) + i);
     const uint32_t w = t >> 6;
     f4 *slice = lds.v + 192 * w;
+    if (!kEarlyStage<M>) {
+        wave_lds_sync();
+        slice[3 * lane + 0] = f4{nv[0], nv[1], nv[2], nv[3]};
+        slice[3 * lane + 1] = f4{nv[4], nv[5], nv[6], nv[7]};
+        slice[3 * lane + 2] = f4{nv[8], nv[9], nv[10], nv[11]};
+    }
     wave_lds_sync();
-    slice[3 * lane + 0] = f4{nv[0], nv[1], nv[2], nv[3]};
-    slice[3 * lane + 1] = f4{nv[4], nv[5], nv[6], nv[7]};
-    slice[3 * lane + 2] = f4{nv[8], nv[9], nv[10], nv[11]};
-    wave_lds_sync();
-    const uint32_t g0 = tile * kBlock + 64 * w;  // first group of this wavefront
+    const uint32_t g0 = tile * TB + 64 * w;  // first group of this wavefront
     if (g0 < f.nitems) {
         const uint32_t n = 3 * min(64u, f.nitems - g0);
         f4 *out = reinterpret_cast<f4 *>(f.normals) + 3 * (int64_t)g0;
@@ -342,8 +411,8 @@ __device__ __forceinline__ void run_tile(const FrameArgs &f, bool vec, uint32_t 
                                          uint32_t &cv, uint32_t &cb) {
     if (vec) {
         Vec4Out o;
-        vec4_eval_method<A, M>(f, tile, o);
-        vec4_write(f, tile, lds, o);
+        vec4_eval_method<A, M>(f, tile, o, lds);
+        vec4_write<M>(f, tile, lds, o);
         if (f.stats) vec4_count(o, cv, cb);
     } else {
         ScalarOut r;
@@ -356,24 +425,72 @@ __device__ __forceinline__ void run_tile(const FrameArgs &f, bool vec, uint32_t 
 // One vector tile with its counts, as part `part` of `nparts` of the frame.
 // The counts are known before the stores, so the count atomic goes out first
 // and its round trip overlaps the stores.
-template <int A, int M>
+template <int A, int M, int TB = kBlock>
 __device__ __forceinline__ void vec4_tile_counted(const FrameArgs &f, uint32_t tile,
-                                                  uint32_t part, uint32_t nparts, TileLds &lds) {
+                                                  uint32_t part, uint32_t nparts,
+                                                  TileLdsT<TB> &lds) {
     Vec4Out o;
-    vec4_eval_method<A, M>(f, tile, o);
+    if constexpr (TB == kBlock) {
+        vec4_eval_method<A, M>(f, tile, o, lds);
+    } else {
+        vec4_eval<A, M, TB>(f, tile, o, lds);  // the five-tap methods only
+    }
     CountTicket tk;
     bool have = false;
     uint32_t cv = 0, cb = 0;
     vec4_count(o, cv, cb);
     if (f.stats) {
         uint32_t v, b;
-        block_sum(cv, cb, v, b);
+        block_sum<TB>(cv, cb, v, b);
         if (threadIdx.x == 0) {
             tk = count_issue(f.work, f.stats, part, nparts, v, b, f.npix, f.overwrite);
             have = true;
         }
     }
-    vec4_write(f, tile, lds, o);
+    vec4_write<M, TB>(f, tile, lds, o);
+    if (have) count_finish(tk);
+}
+
+// Two vector tiles of one workgroup, software-pipelined: the second tile's
+// loads are issued before the first tile's arithmetic, so they are in flight
+// while it computes and stores.  (On gfx9 one counter tracks loads and
+// stores in issue order: the wait for the second tile's loads, issued before
+// the first tile's stores, does not wait for those stores.)  The counts of
+// both tiles go out as one part; tile t1 may lie past the frame's end (its
+// lanes are then not live).
+template <int A, int M>
+__device__ __forceinline__ void vec4_tile_pair_counted(const FrameArgs &f, uint32_t t0,
+                                                       uint32_t t1, uint32_t part,
+                                                       uint32_t nparts, TileLds &lds) {
+    Vec4In<A> a, b;
+    vec4_load<A>(f, t0, a);
+    vec4_load<A>(f, t1, b);
+    uint32_t cv = 0, cb = 0;
+    {
+        Vec4Out o;
+        vec4_compute<A, M>(f, a, o, lds);
+        vec4_count(o, cv, cb);
+        // the second tile's loads have been in flight during this
+        // arithmetic: wait for them now, while no store is outstanding (the
+        // counter cannot tell loads from stores, so a wait after the stores
+        // would wait for those too)
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+        vec4_write<M>(f, t0, lds, o);
+    }
+    Vec4Out o;
+    vec4_compute<A, M>(f, b, o, lds);
+    vec4_count(o, cv, cb);
+    CountTicket tk;
+    bool have = false;
+    if (f.stats) {
+        uint32_t v, bb;
+        block_sum(cv, cb, v, bb);
+        if (threadIdx.x == 0) {
+            tk = count_issue(f.work, f.stats, part, nparts, v, bb, f.npix, f.overwrite);
+            have = true;
+        }
+    }
+    vec4_write<M>(f, t1, lds, o);
     if (have) count_finish(tk);
 }
 

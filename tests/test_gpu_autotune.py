@@ -39,10 +39,11 @@ def test_autotune_batch_grid():
     with bn.BatchPlan(frames) as plan:
         k, us = plan.autotune()
         tuned_wg = plan.info()["workgroups"]
-        log(f"batch grid tuned: {k} workgroups per CU, {us:.1f} us")
-        assert k in (0, 2, 4, 8)
+        log(f"batch grid tuned: shape {k}, {us:.1f} us")
+        assert k in (0, -2, -4, 2, 4, 8)
         info = plan.info()
-        assert info["workgroups"] == (info["tiles"] if k == 0 else 256 * k)
+        per = max(1, -k)
+        assert info["workgroups"] == ((info["tiles"] + per - 1) // per if k <= 0 else 256 * k)
         for f in frames:
             f.stats.zero_()
         plan.run()
@@ -55,3 +56,37 @@ def test_autotune_batch_grid():
     with bn.BatchPlan(frames) as plan2:
         assert plan2.info()["workgroups"] == tuned_wg
     bn.autotune_reset()
+
+
+@pytest.mark.parametrize("shape", [-1, -2, -4, 2, 4, 8])
+def test_every_batch_shape_is_bit_identical(tmp_path, shape):
+    """Each grid shape the batch autotuner chooses among, forced through a
+    recorded table entry, gives the plain launches' outputs bit for bit."""
+    import json
+    import torch
+    frs = scenes.batch_frames(seed0=1000, indices=range(0, 256, 8))
+    frames = [bn.BatchFrame(to_gpu(s.depth), s.fx, s.fy, s.cx, s.cy) for s in frs]
+    px = sum(s.depth.size for s in frs)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    entry = {"arch": arch, "kind": "batch", "method": 0, "alpha": 2, "class": px.bit_length(),
+             "value": shape, "us": 1.0}
+    path = tmp_path / "shape.json"
+    path.write_text('{"entries": [\n ' + json.dumps(entry) + "\n]}\n")
+    bn.autotune_reset()
+    bn.autotune_load(str(path))
+    try:
+        with bn.BatchPlan(frames) as plan:
+            info = plan.info()
+            per = max(1, -shape)
+            want_wg = (info["tiles"] + per - 1) // per if shape < 0 else 256 * shape
+            assert info["workgroups"] == want_wg, (shape, info)
+            plan.run()
+            torch.cuda.synchronize()
+            for k, f in enumerate(frames):
+                n, m, st = bn.estimate_normals(f.depth, f.fx, f.fy, f.cx, f.cy, 2)
+                torch.cuda.synchronize()
+                assert torch.equal(f.normals.view(torch.int32), n.view(torch.int32)), (shape, k)
+                assert torch.equal(f.mask, m), (shape, k)
+                assert torch.equal(f.stats, st), (shape, k)
+    finally:
+        bn.autotune_reset()

@@ -12,7 +12,7 @@ from synth import scenes
 
 pytestmark = pytest.mark.gpu
 
-ALL_VARIANTS = [1, 2, 3, 4]
+ALL_VARIANTS = [1, 2, 3, 4, 5, 6, 7]
 
 
 @pytest.fixture(scope="module")

@@ -44,7 +44,7 @@ def check(depth, fx, fy, cx, cy, alpha, mode, tau, method, scales=0, variant=0, 
 
 @pytest.mark.parametrize("alpha", [1, 2, 3, 8])
 @pytest.mark.parametrize("mode,tau", [("rel", 4.0), ("rel", 1.5), ("abs", 1e-3), ("none", 1.0)])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_pair_removal_640(f640, alpha, mode, tau, variant):
     log(f"pair removal 640x480 alpha={alpha} {mode} {tau} variant={variant}")
     s = f640
@@ -68,6 +68,12 @@ def test_multiscale_640(f640, alpha, K, mode, tau):
         got = run(s.depth, *s.intrinsics, alpha, mode, tau, MS, K, variant)
         for a, b in zip(got, scalar):
             assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), f"v={variant}"
+    # the pipelined pair of tiles and the small workgroups serve the five-tap
+    # methods only
+    for v in (5, 6, 7):
+        with pytest.raises(bn.BnError) as e:
+            run(s.depth, *s.intrinsics, alpha, mode, tau, MS, K, v)
+        assert e.value.status == bn.BN_ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("alpha,K", [(3, 3), (2, 5), (8, 2), (1, 8), (3, 6), (8, 3), (5, 4)])
