@@ -318,6 +318,13 @@ def run_plain(args, torch, bn, inputs):
     ring = Ring(torch, bn, scs, ring_n)
     H, W = ring.H, ring.W
     px = H * W
+    tuned = None
+    if args.variant == 0:
+        # the autotuner's choice of tile shape for this frame size, taken by
+        # variant 0 (the library's choice) from here on
+        tv, tus = bn.autotune_plain(H, W, args.alpha, args.mode, args.tau)
+        tuned = {"variant": dict(bn.variants())[tv], "autotune_us": tus}
+        log(f"autotuned plain {W}x{H}: {tuned['variant']} ({tus:.2f} us in its own ring)")
     kw = dict(alpha=args.alpha, mode=args.mode, tau=args.tau, variant=args.variant)
     ref = parity_check(ring, kw, args.alpha, args.mode, args.tau)
     ms_step, steps, warm, graphed = ring.time(kw, args.steps, args.warmup, eager=args.eager)
@@ -338,9 +345,11 @@ def run_plain(args, torch, bn, inputs):
         for name, alpha, K in (("pair_removal", args.alpha, 0), ("multiscale", 1, 3),
                                ("multiscale", 3, 3)):
             mkw = dict(alpha=alpha, mode=args.mode, tau=args.tau, method=name, scales=K)
+            mv, _ = bn.autotune_plain(H, W, alpha, args.mode, args.tau, method=name, scales=K)
             parity_check(ring, mkw, alpha, args.mode, args.tau, name, K)
             mms, msteps, _, _ = ring.time(mkw, args.steps // 2, args.warmup // 2, min_passes=5)
             methods.append({"method": name, "alpha": alpha, "scales": K, "steps": msteps,
+                            "variant": dict(bn.variants())[mv],
                             "ms_per_step": mms, "value": px / (mms * 1e-3) / 1e6,
                             "unit": "Mpix/s", "roofline": roofline(px, mms)})
             log(f"{name}: {methods[-1]['value']:.0f} Mpix/s")
@@ -349,6 +358,7 @@ def run_plain(args, torch, bn, inputs):
         # (1.6 GB, beyond the last-level cache), one launch per frame
         scs640 = inputs["plain640"]
         r640 = Ring(torch, bn, scs640, 256)
+        v640, _ = bn.autotune_plain(480, 640, args.alpha, args.mode, args.tau)
         kw640 = dict(alpha=args.alpha, mode=args.mode, tau=args.tau)
         parity_check(r640, kw640, args.alpha, args.mode, args.tau)
         ms640, steps640, _, _ = r640.time(kw640, 2560, 256)
@@ -357,6 +367,7 @@ def run_plain(args, torch, bn, inputs):
                                          "buffers (8 distinct scenes, seeds 1..8)",
                              "value": px640 / (ms640 * 1e-3) / 1e6, "unit": "Mpix/s",
                              "us_per_frame": ms640 * 1e3, "steps": steps640,
+                             "variant": dict(bn.variants())[v640],
                              "roofline": roofline(px640, ms640)}
         log(f"plain 640x480: {ms640 * 1e3:.2f} us per frame")
         del r640
@@ -380,7 +391,8 @@ def run_plain(args, torch, bn, inputs):
                    "frame": "1920x1080", "fx": 1050.0, "alpha": args.alpha,
                    "mask": args.mode, "tau": args.tau, "method": "four_pair",
                    "launch": "hip graph replay" if graphed else "eager",
-                   "variant": args.variant or "auto"},
+                   "variant": tuned["variant"] if tuned else dict(bn.variants())[args.variant],
+                   "variant_from": "autotuner" if tuned else "--variant"},
         "roofline": roofline(px, ms_step, traffic),
         "cpu_baseline": cpu,
     }
@@ -395,9 +407,15 @@ def run_batch(args, torch, bn, inputs):
     frames = [bn.BatchFrame(torch.from_numpy(s.depth).to(dev), s.fx, s.fy, s.cx, s.cy)
               for s in frames_h]
     plan = bn.BatchPlan(frames, alpha=args.alpha, mode=args.mode, tau=args.tau)
+    stream = torch.cuda.Stream()
+    # the autotuner's grid shape for this plan (it runs the plan to time it)
+    shape, shape_us = plan.autotune(stream)
+    shape_name = ("flat, 1 tile per workgroup" if shape == 0 else
+                  f"flat, {-shape} tiles per workgroup" if shape < 0 else
+                  f"{shape} persistent workgroups per CU")
+    log(f"autotuned batch grid: {shape_name} ({shape_us:.1f} us)")
     info = plan.info()
     px = info["pixels"]
-    stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         for _ in range(max(args.batch_warmup, 1)):
             plan.run(stream)
@@ -439,6 +457,7 @@ def run_batch(args, torch, bn, inputs):
         "workload": "256 frames: 64x 320x240, 96x 640x480, 64x 1280x720, 32x 1920x1080 "
                     "(seeds 1000..1255, fx=fy=525*W/640), one graph launch over all tiles",
         "pixels": px, "tiles": info["tiles"], "workgroups": info["workgroups"],
+        "grid_shape": shape_name, "grid_shape_from": "autotuner",
         "value": px / (ms * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_step": ms, "steps": steps,
         "roofline": roofline(px, ms, load_traffic("batch256", px)),
         "same_frames_plain_launches": plain,
@@ -751,7 +770,8 @@ def main():
             b = run_batch(args, torch, bn, inputs)
             out["batched"] = {k: b[k] for k in ("workload", "value", "unit", "ms_per_step",
                                                 "steps", "pixels", "tiles", "workgroups",
-                                                "roofline", "same_frames_plain_launches")}
+                                                "grid_shape", "grid_shape_from", "roofline",
+                                                "same_frames_plain_launches")}
             if not args.no_serve:
                 out["serving"] = run_serve(args, torch, bn, inputs, b["value"])
         if not args.quick:
