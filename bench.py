@@ -61,6 +61,8 @@ def generate_inputs(args) -> dict:
     if args.workload == "batch":
         jobs["batch"] = [("sized", (H, W, 1000 + i))
                          for i, (H, W) in enumerate(scenes.batch_shapes())]
+    elif args.workload == "plain640":
+        jobs["plain640"] = [("640", 1 + i) for i in range(8)]
     else:
         nd = min(args.distinct, args.ring)
         if not args.no_batch and not args.no_serve:
@@ -77,10 +79,12 @@ def generate_inputs(args) -> dict:
     flat = [j for js in jobs.values() for j in js]
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     workers = max(1, min(16, int(cores or 1), len(flat)))
+    kind = "threads" if getattr(args, "gen_threads", False) else "processes"
     log(f"generating {len(flat)} host frames ({', '.join(f'{k}: {len(v)}' for k, v in jobs.items())}) "
-        f"on {workers} processes, before any GPU use")
+        f"on {workers} {kind}, before any GPU use")
     t0 = time.perf_counter()
-    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+    pool = cf.ThreadPoolExecutor if kind == "threads" else cf.ProcessPoolExecutor
+    with pool(max_workers=workers) as ex:
         out = list(ex.map(_gen, flat, chunksize=1))
     log(f"generated in {time.perf_counter() - t0:.1f} s")
     res, i = {}, 0
@@ -311,6 +315,26 @@ def achievable_rates(torch, bn, reps=5):
     return out
 
 
+def run_plain640(args, torch, bn, inputs):
+    """The small plain configuration: 640x480, a ring of 256 buffers (1.6 GB,
+    beyond the last-level cache), one launch per frame, the autotuner's tile
+    shape."""
+    scs640 = inputs["plain640"]
+    r640 = Ring(torch, bn, scs640, 256)
+    v640, _ = bn.autotune_plain(480, 640, args.alpha, args.mode, args.tau)
+    kw640 = dict(alpha=args.alpha, mode=args.mode, tau=args.tau)
+    parity_check(r640, kw640, args.alpha, args.mode, args.tau)
+    ms640, steps640, warm640, _ = r640.time(kw640, 2560, 256)
+    px640 = 640 * 480
+    log(f"plain 640x480: {ms640 * 1e3:.2f} us per frame")
+    del r640
+    return {"workload": "plain 640x480, one launch per frame, ring of 256 buffers (8 distinct "
+                        "scenes, seeds 1..8)",
+            "value": px640 / (ms640 * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_step": ms640,
+            "us_per_frame": ms640 * 1e3, "steps": steps640, "warmup": warm640,
+            "variant": dict(bn.variants())[v640], "roofline": roofline(px640, ms640)}
+
+
 def run_plain(args, torch, bn, inputs):
     ring_n = args.ring
     scs = inputs["plain"]
@@ -354,23 +378,7 @@ def run_plain(args, torch, bn, inputs):
                             "unit": "Mpix/s", "roofline": roofline(px, mms)})
             log(f"{name}: {methods[-1]['value']:.0f} Mpix/s")
         extra["methods"] = methods
-        # the small plain configuration: 640x480, a ring of 256 buffers
-        # (1.6 GB, beyond the last-level cache), one launch per frame
-        scs640 = inputs["plain640"]
-        r640 = Ring(torch, bn, scs640, 256)
-        v640, _ = bn.autotune_plain(480, 640, args.alpha, args.mode, args.tau)
-        kw640 = dict(alpha=args.alpha, mode=args.mode, tau=args.tau)
-        parity_check(r640, kw640, args.alpha, args.mode, args.tau)
-        ms640, steps640, _, _ = r640.time(kw640, 2560, 256)
-        px640 = 640 * 480
-        extra["plain640"] = {"workload": "plain 640x480, one launch per frame, ring of 256 "
-                                         "buffers (8 distinct scenes, seeds 1..8)",
-                             "value": px640 / (ms640 * 1e-3) / 1e6, "unit": "Mpix/s",
-                             "us_per_frame": ms640 * 1e3, "steps": steps640,
-                             "variant": dict(bn.variants())[v640],
-                             "roofline": roofline(px640, ms640)}
-        log(f"plain 640x480: {ms640 * 1e3:.2f} us per frame")
-        del r640
+        extra["plain640"] = run_plain640(args, torch, bn, inputs)
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the oracle for {args.cpu_seconds} s (one thread)")
@@ -705,7 +713,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3200)
     ap.add_argument("--warmup", type=int, default=320)
-    ap.add_argument("--workload", default="plain1080", choices=["plain1080", "batch"])
+    ap.add_argument("--workload", default="plain1080", choices=["plain1080", "batch", "plain640"])
     ap.add_argument("--no-batch", action="store_true", help="skip the batched comparison")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--batch-warmup", type=int, default=10)
@@ -726,6 +734,10 @@ def main():
     ap.add_argument("--serve-in-flight", type=int, default=2)
     ap.add_argument("--quick", action="store_true",
                     help="headline numbers only (no methods, latency, copy or multi-core oracle)")
+    ap.add_argument("--gen-threads", action="store_true",
+                    help="generate the host frames on threads instead of processes (for runs "
+                         "under a profiler, which may initialise the GPU before the program "
+                         "starts: nothing may fork then)")
     ap.add_argument("--calibration-mib", type=int, default=0,
                     help="first run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -752,7 +764,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.workload == "batch":
+    if args.workload == "plain640":
+        p = run_plain640(args, torch, bn, inputs)
+        out = {"metric": "normals Mpix/s (plain single-frame launches)", "value": p["value"],
+               "unit": "Mpix/s", "steps": p["steps"], "warmup": p["warmup"],
+               "ms_per_step": p["ms_per_step"],
+               "config": {"workload": p["workload"], "frame": "640x480", "fx": 525.0,
+                          "alpha": args.alpha, "mask": args.mode, "tau": args.tau,
+                          "variant": p["variant"], "variant_from": "autotuner"},
+               "roofline": p["roofline"], "cpu_baseline": None}
+    elif args.workload == "batch":
         b = run_batch(args, torch, bn, inputs)
         out = {"metric": "normals Mpix/s (batched launch)", "value": b["value"],
                "unit": "Mpix/s", "steps": b["steps"], "warmup": args.batch_warmup,

@@ -4,6 +4,7 @@
     python -m paper_2209_08241_amd.profiling traffic --fetch <dir> --write <dir> \
         --kernel <substring> --pixels <per launch> --workload <name> --out <json> [--cmd "..."]
     python -m paper_2209_08241_amd.profiling launches [--reps N]
+    python -m paper_2209_08241_amd.profiling rings [--reps N] [--calibration-mib M]
     python -m paper_2209_08241_amd.profiling diff [--reps N] [--calibration-mib M]
     python -m paper_2209_08241_amd.profiling valu <counter_collection dir> <out.md> [--cmd "..."]
 
@@ -71,13 +72,14 @@ def _per_dispatch(rows, counter: str):
         did = r.get("Dispatch_Id") or r.get("Dispatch-Id") or r.get("Correlation_Id")
         val = float(r.get("Counter_Value") or r.get("Counter-Value"))
         k = r.get("Kernel_Name") or r.get("Kernel-Name")
+        g = int(r.get("Grid_Size") or r.get("Grid-Size") or 0)
         prev = out.get(did)
-        out[did] = (k, val + (prev[1] if prev else 0.0))
+        out[did] = (k, val + (prev[1] if prev else 0.0), g)
     return out
 
 
-def _kernel_values(disp, needle: str):
-    return [v for (k, v) in disp.values() if needle in k]
+def _kernel_values(disp, needle: str, grid: int = 0):
+    return [v for (k, v, g) in disp.values() if needle in k and (not grid or g == grid)]
 
 
 def _calibration_values(disp, needle: str, count: int):
@@ -89,7 +91,8 @@ def _calibration_values(disp, needle: str, count: int):
 
 def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: str,
             out_json: str, calib_bytes: int, calib_kernel: str, cmd: str = "",
-            calib_count: int = 4, bytes_per_pixel: int = 17, adjoint: bool = False) -> dict:
+            calib_count: int = 4, bytes_per_pixel: int = 17, adjoint: bool = False,
+            grid: int = 0) -> dict:
     sys.path.insert(0, ROOT)
     import bench   # noqa: E402  (the hash bench.py checks)
     f_rows = _csv_rows(fetch_dir, "*counter_collection.csv")
@@ -98,8 +101,8 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: 
     w = _per_dispatch(w_rows, "WRITE_SIZE")
     fc = _calibration_values(f, calib_kernel, calib_count)
     wc = _calibration_values(w, calib_kernel, calib_count)
-    fk = _kernel_values(f, kernel)
-    wk = _kernel_values(w, kernel)
+    fk = _kernel_values(f, kernel, grid)
+    wk = _kernel_values(w, kernel, grid)
     if not (fc and wc and fk and wk):
         raise SystemExit(f"missing dispatches: calib {len(fc)}/{len(wc)}, kernel {len(fk)}/{len(wk)}")
     # copy kernel: reads and writes calib_bytes each
@@ -110,6 +113,7 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: 
     rec = {
         "workload": workload,
         "kernel": kernel,
+        "grid_size": grid or None,
         "pixels_per_launch": pixels,
         "algorithmic_bytes_per_launch": bytes_per_pixel * pixels,
         "hbm_read_bytes_per_launch": rb,
@@ -157,6 +161,75 @@ def launches(reps: int = 20) -> None:
         bn.normals_vjp_stack(pad[:, :, :640], intr, g)
     torch.cuda.synchronize()
     print("launches done", flush=True)
+
+
+def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
+    """The benchmark's single-frame and batched configurations as a program
+    for counter passes: a calibration copy (4 times), then, with the
+    autotuner's tile shapes, `reps` launches over a ring of distinct buffers
+    for each of: four-pair, pair removal, multi-scale (alpha 1, K 3) and
+    (alpha 3, K 3) on 1920x1080; four-pair on 640x480 (a ring of 256); then
+    three runs of the 256-frame mixed batch.  Prints the variant each
+    configuration used (the kernel names the summaries select)."""
+    sys.path.insert(0, ROOT)
+    import concurrent.futures as cf
+    from synth import scenes
+    # host frames first, on threads (under a profiler the GPU runtime may be
+    # initialised before this program starts, so nothing here forks)
+    shapes = scenes.batch_shapes()
+    jobs = [(H, W, 1000 + i, {}) for i, (H, W) in enumerate(shapes)]
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        batch_h = list(ex.map(scenes._sized_job, jobs))
+    f1080 = [scenes.frame_1920x1080(seed=2 + i) for i in range(8)]
+    f640 = [scenes.frame_640x480(seed=1 + i) for i in range(8)]
+    import torch
+    import paper_2209_08241_amd as bn
+    if calibration_mib:
+        src = torch.ones(calibration_mib * (1 << 20) // 4, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    names = dict(bn.variants())
+
+    def ring_of(frames, n):
+        H, W = frames[0].depth.shape
+        d = [torch.from_numpy(frames[i % len(frames)].depth).cuda() for i in range(n)]
+        nm = [torch.empty((H, W, 3), device="cuda") for _ in range(n)]
+        mk = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(n)]
+        st = bn.new_stats(n, device="cuda")
+        return d, nm, mk, st
+
+    d, nm, mk, st = ring_of(f1080, 32)
+    s0 = f1080[0]
+    for method, alpha, K in (("four_pair", 2, 0), ("pair_removal", 2, 0), ("multiscale", 1, 3),
+                             ("multiscale", 3, 3)):
+        v, _ = bn.autotune_plain(1080, 1920, alpha, "rel", 4.0, method=method, scales=K)
+        print(f"1920x1080 {method} alpha {alpha} K {K}: {names[v]}", flush=True)
+        for r in range(reps):
+            j = r % 32
+            bn.estimate_normals(d[j], *s0.intrinsics, alpha, method=method, scales=K,
+                                normals=nm[j], mask=mk[j], stats=st[j])
+        torch.cuda.synchronize()
+    del d, nm, mk, st
+    d, nm, mk, st = ring_of(f640, 256)
+    v, _ = bn.autotune_plain(480, 640, 2, "rel", 4.0)
+    print(f"640x480 four_pair alpha 2: {names[v]}", flush=True)
+    for r in range(max(reps, 256)):
+        j = r % 256
+        bn.estimate_normals(d[j], *f640[0].intrinsics, 2, normals=nm[j], mask=mk[j], stats=st[j])
+    torch.cuda.synchronize()
+    del d, nm, mk, st
+    frames = [bn.BatchFrame(torch.from_numpy(s.depth).cuda(), s.fx, s.fy, s.cx, s.cy)
+              for s in batch_h]
+    with bn.BatchPlan(frames) as plan:
+        shape, _ = plan.autotune()
+        print(f"batch grid shape {shape}", flush=True)
+        for _ in range(3):
+            plan.run()
+        torch.cuda.synchronize()
+    print("rings done", flush=True)
 
 
 # kernel -> (workload, pixels or outputs per dispatch)
@@ -268,6 +341,11 @@ def main():
     p.add_argument("--bytes-per-pixel", type=int, default=17)
     p.add_argument("--adjoint", action="store_true",
                    help="hash the adjoint's sources (bench.ADJOINT_SOURCES)")
+    p.add_argument("--grid", type=int, default=0,
+                   help="only dispatches of this grid size (threads), 0: any")
+    rg = sub.add_parser("rings")
+    rg.add_argument("--reps", type=int, default=64)
+    rg.add_argument("--calibration-mib", type=int, default=1024)
     ln = sub.add_parser("launches")
     ln.add_argument("--reps", type=int, default=20)
     df = sub.add_parser("diff")
@@ -280,6 +358,8 @@ def main():
     a = ap.parse_args()
     if a.what == "launches":
         launches(a.reps)
+    elif a.what == "rings":
+        rings(a.reps, a.calibration_mib)
     elif a.what == "diff":
         diff_launches(a.reps, a.calibration_mib)
     elif a.what == "valu":
@@ -289,7 +369,7 @@ def main():
     else:
         print(json.dumps(traffic(a.fetch, a.write, a.kernel, a.pixels, a.workload, a.out,
                                  a.calib_bytes, a.calib_kernel, a.cmd, a.calib_count,
-                                 a.bytes_per_pixel, a.adjoint), indent=1))
+                                 a.bytes_per_pixel, a.adjoint, a.grid), indent=1))
 
 
 if __name__ == "__main__":
