@@ -95,6 +95,15 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is not built; run `python -m paper_2209_08241_amd.build`")
+        # PyTorch brings up its GPU runtime first: when the library's own calls
+        # come first in a process (an autotuning call before any tensor is on
+        # the device, say), PyTorch's later initialisation finds no GPU
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
         L.bn_estimate_normals.argtypes = [vp, i32, i32, i64, f32, f32, f32, f32,

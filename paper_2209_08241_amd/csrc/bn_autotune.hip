@@ -226,13 +226,20 @@ int bn_autotune_plain(int32_t height, int32_t width, const bn_params *params, in
         return BN_ERR_DEVICE;
     const float cx = 0.5f * (float)(width - 1), cy = 0.5f * (float)(height - 1);
     const float f = 525.0f * (float)width / 640.0f;
+    // The library's default variant is kept unless another one is faster by
+    // more than kMargin (choices within run-to-run noise would otherwise flip
+    // between runs).
+    constexpr float kMargin = 0.97f;
+    const int dflt = (method_has_vec4(params) && vec4_layout(d[0], width, width, n[0], m[0]))
+                         ? (int)VAR_VEC4
+                         : (int)VAR_SCALAR;
     int best = 0;
-    float best_t = 1e30f;
+    float best_t = 1e30f, dflt_t = 1e30f;
+    const int reps = ring * ((px < (1u << 20)) ? 8 : 3);
     for (int v = 1; v <= (int)VAR_COUNT; ++v) {
         bn_params p = *params;
         p.variant = (uint32_t)v;
         if (!bn_variant_supported(v, d[0], height, width, width, n[0], m[0])) continue;
-        const int reps = ring * ((px < (1u << 20)) ? 8 : 3);
         bool ok = true;
         for (int k = 0; k < ring && ok; ++k)  // warm-up
             ok = bn_estimate_normals(d[k], height, width, width, f, f, cx, cy, &p, n[k], m[k],
@@ -253,10 +260,15 @@ int bn_autotune_plain(int32_t height, int32_t width, const bn_params *params, in
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         const float us = 1000.f * ms / (float)reps;
+        if (v == dflt) dflt_t = us;
         if (us < best_t) {
             best_t = us;
             best = v;
         }
+    }
+    if (best && best != dflt && dflt_t < 1e30f && best_t > kMargin * dflt_t) {
+        best = dflt;
+        best_t = dflt_t;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -166,11 +166,12 @@ def launches(reps: int = 20) -> None:
 def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
     """The benchmark's single-frame and batched configurations as a program
     for counter passes: a calibration copy (4 times), then, with the
-    autotuner's tile shapes, `reps` launches over a ring of distinct buffers
-    for each of: four-pair, pair removal, multi-scale (alpha 1, K 3) and
-    (alpha 3, K 3) on 1920x1080; four-pair on 640x480 (a ring of 256); then
-    three runs of the 256-frame mixed batch.  Prints the variant each
-    configuration used (the kernel names the summaries select)."""
+    library's default tile shapes (the autotuner cannot time anything under
+    a counter profiler, which serialises every dispatch), `reps` launches
+    over a ring of distinct buffers for each of: four-pair, pair removal,
+    multi-scale (alpha 1, K 3) and (alpha 3, K 3) on 1920x1080; four-pair on
+    640x480 (a ring of 256); then three runs of the 256-frame mixed batch
+    (flat grid)."""
     sys.path.insert(0, ROOT)
     import concurrent.futures as cf
     from synth import scenes
@@ -191,7 +192,6 @@ def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    names = dict(bn.variants())
 
     def ring_of(frames, n):
         H, W = frames[0].depth.shape
@@ -205,8 +205,7 @@ def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
     s0 = f1080[0]
     for method, alpha, K in (("four_pair", 2, 0), ("pair_removal", 2, 0), ("multiscale", 1, 3),
                              ("multiscale", 3, 3)):
-        v, _ = bn.autotune_plain(1080, 1920, alpha, "rel", 4.0, method=method, scales=K)
-        print(f"1920x1080 {method} alpha {alpha} K {K}: {names[v]}", flush=True)
+        print(f"1920x1080 {method} alpha {alpha} K {K}", flush=True)
         for r in range(reps):
             j = r % 32
             bn.estimate_normals(d[j], *s0.intrinsics, alpha, method=method, scales=K,
@@ -214,8 +213,7 @@ def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
         torch.cuda.synchronize()
     del d, nm, mk, st
     d, nm, mk, st = ring_of(f640, 256)
-    v, _ = bn.autotune_plain(480, 640, 2, "rel", 4.0)
-    print(f"640x480 four_pair alpha 2: {names[v]}", flush=True)
+    print("640x480 four_pair alpha 2", flush=True)
     for r in range(max(reps, 256)):
         j = r % 256
         bn.estimate_normals(d[j], *f640[0].intrinsics, 2, normals=nm[j], mask=mk[j], stats=st[j])
@@ -224,8 +222,6 @@ def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
     frames = [bn.BatchFrame(torch.from_numpy(s.depth).cuda(), s.fx, s.fy, s.cx, s.cy)
               for s in batch_h]
     with bn.BatchPlan(frames) as plan:
-        shape, _ = plan.autotune()
-        print(f"batch grid shape {shape}", flush=True)
         for _ in range(3):
             plan.run()
         torch.cuda.synchronize()
