@@ -321,7 +321,8 @@ def run_plain640(args, torch, bn, inputs):
     shape."""
     scs640 = inputs["plain640"]
     r640 = Ring(torch, bn, scs640, 256)
-    v640, _ = bn.autotune_plain(480, 640, args.alpha, args.mode, args.tau)
+    v640 = (bn.autotune_plain(480, 640, args.alpha, args.mode, args.tau)[0]
+            if not args.no_autotune else bn.default_variant(480, 640, "four_pair", args.alpha, 0))
     kw640 = dict(alpha=args.alpha, mode=args.mode, tau=args.tau)
     parity_check(r640, kw640, args.alpha, args.mode, args.tau)
     ms640, steps640, warm640, _ = r640.time(kw640, 2560, 256)
@@ -332,7 +333,9 @@ def run_plain640(args, torch, bn, inputs):
                         "scenes, seeds 1..8)",
             "value": px640 / (ms640 * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_step": ms640,
             "us_per_frame": ms640 * 1e3, "steps": steps640, "warmup": warm640,
-            "variant": dict(bn.variants())[v640], "roofline": roofline(px640, ms640)}
+            "variant": dict(bn.variants())[v640],
+            "variant_from": "library default" if args.no_autotune else "autotuner",
+            "roofline": roofline(px640, ms640, load_traffic("plain640", px640))}
 
 
 def run_plain(args, torch, bn, inputs):
@@ -343,7 +346,7 @@ def run_plain(args, torch, bn, inputs):
     H, W = ring.H, ring.W
     px = H * W
     tuned = None
-    if args.variant == 0:
+    if args.variant == 0 and not args.no_autotune:
         # the autotuner's choice of tile shape for this frame size, taken by
         # variant 0 (the library's choice) from here on
         tv, tus = bn.autotune_plain(H, W, args.alpha, args.mode, args.tau)
@@ -369,13 +372,17 @@ def run_plain(args, torch, bn, inputs):
         for name, alpha, K in (("pair_removal", args.alpha, 0), ("multiscale", 1, 3),
                                ("multiscale", 3, 3)):
             mkw = dict(alpha=alpha, mode=args.mode, tau=args.tau, method=name, scales=K)
-            mv, _ = bn.autotune_plain(H, W, alpha, args.mode, args.tau, method=name, scales=K)
+            mv = (bn.autotune_plain(H, W, alpha, args.mode, args.tau, method=name, scales=K)[0]
+                  if not args.no_autotune else bn.default_variant(H, W, name, alpha, K))
             parity_check(ring, mkw, alpha, args.mode, args.tau, name, K)
             mms, msteps, _, _ = ring.time(mkw, args.steps // 2, args.warmup // 2, min_passes=5)
             methods.append({"method": name, "alpha": alpha, "scales": K, "steps": msteps,
                             "variant": dict(bn.variants())[mv],
+                            "roofline_traffic_workload": f"{name}_a{alpha}_k{K}_1080",
                             "ms_per_step": mms, "value": px / (mms * 1e-3) / 1e6,
-                            "unit": "Mpix/s", "roofline": roofline(px, mms)})
+                            "unit": "Mpix/s",
+                            "roofline": roofline(px, mms,
+                                                 load_traffic(f"{name}_a{alpha}_k{K}_1080", px))})
             log(f"{name}: {methods[-1]['value']:.0f} Mpix/s")
         extra["methods"] = methods
         extra["plain640"] = run_plain640(args, torch, bn, inputs)
@@ -399,8 +406,12 @@ def run_plain(args, torch, bn, inputs):
                    "frame": "1920x1080", "fx": 1050.0, "alpha": args.alpha,
                    "mask": args.mode, "tau": args.tau, "method": "four_pair",
                    "launch": "hip graph replay" if graphed else "eager",
-                   "variant": tuned["variant"] if tuned else dict(bn.variants())[args.variant],
-                   "variant_from": "autotuner" if tuned else "--variant"},
+                   "variant": (tuned["variant"] if tuned else
+                               dict(bn.variants())[args.variant or
+                                                   bn.default_variant(H, W, "four_pair",
+                                                                      args.alpha, 0)]),
+                   "variant_from": ("autotuner" if tuned else "--variant" if args.variant
+                                    else "library default")},
         "roofline": roofline(px, ms_step, traffic),
         "cpu_baseline": cpu,
     }
@@ -417,7 +428,7 @@ def run_batch(args, torch, bn, inputs):
     plan = bn.BatchPlan(frames, alpha=args.alpha, mode=args.mode, tau=args.tau)
     stream = torch.cuda.Stream()
     # the autotuner's grid shape for this plan (it runs the plan to time it)
-    shape, shape_us = plan.autotune(stream)
+    shape, shape_us = plan.autotune(stream) if not args.no_autotune else (0, 0.0)
     shape_name = ("flat, 1 tile per workgroup" if shape == 0 else
                   f"flat, {-shape} tiles per workgroup" if shape < 0 else
                   f"{shape} persistent workgroups per CU")
@@ -465,7 +476,8 @@ def run_batch(args, torch, bn, inputs):
         "workload": "256 frames: 64x 320x240, 96x 640x480, 64x 1280x720, 32x 1920x1080 "
                     "(seeds 1000..1255, fx=fy=525*W/640), one graph launch over all tiles",
         "pixels": px, "tiles": info["tiles"], "workgroups": info["workgroups"],
-        "grid_shape": shape_name, "grid_shape_from": "autotuner",
+        "grid_shape": shape_name,
+        "grid_shape_from": "library default" if args.no_autotune else "autotuner",
         "value": px / (ms * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_step": ms, "steps": steps,
         "roofline": roofline(px, ms, load_traffic("batch256", px)),
         "same_frames_plain_launches": plain,
@@ -734,6 +746,9 @@ def main():
     ap.add_argument("--serve-in-flight", type=int, default=2)
     ap.add_argument("--quick", action="store_true",
                     help="headline numbers only (no methods, latency, copy or multi-core oracle)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="the library's default tile and grid shapes (for runs under a profiler, "
+                         "whose per-dispatch overhead would decide the autotuner's timings)")
     ap.add_argument("--gen-threads", action="store_true",
                     help="generate the host frames on threads instead of processes (for runs "
                          "under a profiler, which may initialise the GPU before the program "
@@ -771,7 +786,7 @@ def main():
                "ms_per_step": p["ms_per_step"],
                "config": {"workload": p["workload"], "frame": "640x480", "fx": 525.0,
                           "alpha": args.alpha, "mask": args.mode, "tau": args.tau,
-                          "variant": p["variant"], "variant_from": "autotuner"},
+                          "variant": p["variant"], "variant_from": p["variant_from"]},
                "roofline": p["roofline"], "cpu_baseline": None}
     elif args.workload == "batch":
         b = run_batch(args, torch, bn, inputs)

@@ -197,6 +197,16 @@ def _status_string(status: int) -> str:
         return "unknown status"
 
 
+def default_variant(height: int, width: int, method="four_pair", alpha: int = 2,
+                    scales: int = 0) -> int:
+    """The variant the library takes with no autotuning entry, for dense
+    frames of this size (vector tiles when the method and the layout allow
+    them)."""
+    me = METHODS[method] if isinstance(method, str) else int(method)
+    vec_method = me != METHODS["multiscale"] or alpha * max(scales, 1) <= 16
+    return 2 if (vec_method and width % 4 == 0) else 1
+
+
 def variants() -> Sequence[Tuple[int, str]]:
     """(id, name) of every kernel variant of the plain entry point."""
     L = lib()

@@ -284,6 +284,8 @@ def valu_summary(pmc_dir: str, out_md: str, cmd: str = "") -> str:
         if "bn::" not in k:
             continue
         short = k.split("(")[0].replace("void ", "")
+        if short not in _VALU_WHAT:
+            continue  # set-up kernels (work-area clears)
         c = agg.setdefault(short, {})
         name = r.get("Counter_Name") or r.get("Counter-Name")
         c.setdefault(name, []).append(float(r.get("Counter_Value") or r.get("Counter-Value")))

@@ -13,7 +13,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2209_08241_amd", "csrc")
 SOURCES = [os.path.join(CSRC, f) for f in ("bn_serve.hip", "bn_batch.hip", "bn_capi.hip",
-                                           "bn_kernels.hip", "bn_autotune.hip")]
+                                           "bn_kernels.hip", "bn_autotune.hip",
+                                           "bn_workspace.hip")]
 DRIVER = os.path.join(ROOT, "tests", "native", "serve_fake_stress.cpp")
 HIPCC = "/opt/rocm/bin/hipcc"
 BASE = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-ffp-contract=off",
