@@ -107,9 +107,11 @@ def kernel_hash(sources=None) -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, launch_pixels: int, sources=None):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; else None."""
+def load_traffic(workload: str, launch_pixels: int, sources=None, variant=None):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload in this tile shape (variant name; None for kernels without
+    a choice of shape), if it was taken on the current kernel sources; else
+    None."""
     p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(p):
         return None
@@ -119,6 +121,10 @@ def load_traffic(workload: str, launch_pixels: int, sources=None):
         return None
     if rec.get("kernel_hash") != kernel_hash(sources):
         return None
+    if variant and rec.get("variant") != variant:
+        rec = rec.get("other_tile_shapes", {}).get(variant)
+        if rec is None:
+            return None
     return rec.get("hbm_bytes_per_launch")
 
 
@@ -329,13 +335,15 @@ def run_plain640(args, torch, bn, inputs):
     px640 = 640 * 480
     log(f"plain 640x480: {ms640 * 1e3:.2f} us per frame")
     del r640
+    name640 = dict(bn.variants())[v640]
     return {"workload": "plain 640x480, one launch per frame, ring of 256 buffers (8 distinct "
                         "scenes, seeds 1..8)",
             "value": px640 / (ms640 * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_step": ms640,
             "us_per_frame": ms640 * 1e3, "steps": steps640, "warmup": warm640,
-            "variant": dict(bn.variants())[v640],
+            "variant": name640,
             "variant_from": "library default" if args.no_autotune else "autotuner",
-            "roofline": roofline(px640, ms640, load_traffic("plain640", px640))}
+            "roofline": roofline(px640, ms640, load_traffic("plain640", px640,
+                                                            variant=name640))}
 
 
 def run_plain(args, torch, bn, inputs):
@@ -359,7 +367,10 @@ def run_plain(args, torch, bn, inputs):
     want = [int(c) for c in ref["counts"]] + [0]
     if st[0].tolist() != want:
         raise SystemExit(f"per-frame counts wrong after timing: {st[0].tolist()} != {want}")
-    traffic = load_traffic("plain1080", px)
+    used = (tuned["variant"] if tuned else
+            dict(bn.variants())[args.variant or
+                                bn.default_variant(H, W, "four_pair", args.alpha, 0)])
+    traffic = load_traffic("plain1080", px, variant=used)
     extra = {}
     if not args.quick:
         hot_ms, _, _, _ = ring.time(kw, args.steps // 4, args.warmup // 4, hot=True,
@@ -382,7 +393,8 @@ def run_plain(args, torch, bn, inputs):
                             "ms_per_step": mms, "value": px / (mms * 1e-3) / 1e6,
                             "unit": "Mpix/s",
                             "roofline": roofline(px, mms,
-                                                 load_traffic(f"{name}_a{alpha}_k{K}_1080", px))})
+                                                 load_traffic(f"{name}_a{alpha}_k{K}_1080", px,
+                                                              variant=dict(bn.variants())[mv]))})
             log(f"{name}: {methods[-1]['value']:.0f} Mpix/s")
         extra["methods"] = methods
         extra["plain640"] = run_plain640(args, torch, bn, inputs)
@@ -406,10 +418,7 @@ def run_plain(args, torch, bn, inputs):
                    "frame": "1920x1080", "fx": 1050.0, "alpha": args.alpha,
                    "mask": args.mode, "tau": args.tau, "method": "four_pair",
                    "launch": "hip graph replay" if graphed else "eager",
-                   "variant": (tuned["variant"] if tuned else
-                               dict(bn.variants())[args.variant or
-                                                   bn.default_variant(H, W, "four_pair",
-                                                                      args.alpha, 0)]),
+                   "variant": used,
                    "variant_from": ("autotuner" if tuned else "--variant" if args.variant
                                     else "library default")},
         "roofline": roofline(px, ms_step, traffic),

@@ -27,6 +27,7 @@ import csv
 import glob
 import json
 import os
+import re
 import statistics
 import sys
 
@@ -62,6 +63,46 @@ def trace_summary(stats_csv: str, out_md: str, cmd: str = "") -> str:
     return text
 
 
+def trace_by_grid(trace_dir: str, out_md: str, cmd: str = "", pixels=None) -> str:
+    """Per (kernel, grid size) durations of the library's kernels from a
+    rocprofv3 kernel trace: one kernel run on frames of several sizes, or in
+    several tile shapes, shows up as separate rows.  `pixels` maps a grid
+    size (threads) to the pixels one launch covers, for the Mpix/s and
+    GB/s columns (17 algorithmic bytes per pixel)."""
+    rows = _csv_rows(trace_dir, "*kernel_trace.csv")
+    agg: dict = {}
+    meta: dict = {}
+    for r in rows:
+        k = r["Kernel_Name"]
+        if "bn::" not in k:
+            continue
+        short = k.replace("(anonymous namespace)::", "").split("(")[0]
+        short = short.replace("void ", "").replace("bn::", "")
+        key = (short, int(r["Grid_Size_X"]))
+        agg.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        meta[key] = (r["Workgroup_Size_X"], r["VGPR_Count"], r["LDS_Block_Size"])
+    lines = ["# rocprofv3 kernel trace by kernel and grid size", ""]
+    if cmd:
+        lines += ["Command:", "", "```", cmd, "```", ""]
+    lines += ["Durations between each dispatch's start and end timestamps, per kernel and "
+              "grid size (threads).", "",
+              "| kernel | grid | workgroup | VGPRs | LDS bytes | calls | median us | avg us | "
+              "min us | max us | GB/s at median (17 B/px) |",
+              "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for key in sorted(agg, key=lambda k: (-k[1], k[0])):
+        d = sorted(agg[key])
+        med = statistics.median(d)
+        wg, vg, lds = meta[key]
+        px = (pixels or {}).get(key[1])
+        gbs = f"{17 * px / (med * 1e-6) / 1e9:.0f}" if px else ""
+        lines.append(f"| `{key[0]}` | {key[1]} | {wg} | {vg} | {lds} | {len(d)} | {med:.3f} | "
+                     f"{sum(d) / len(d):.3f} | {d[0]:.3f} | {d[-1]:.3f} | {gbs} |")
+    text = "\n".join(lines) + "\n"
+    with open(out_md, "w") as fh:
+        fh.write(text)
+    return text
+
+
 def _per_dispatch(rows, counter: str):
     """{dispatch id: (kernel name, value)} for one counter."""
     out = {}
@@ -89,6 +130,23 @@ def _calibration_values(disp, needle: str, count: int):
     return sorted(_kernel_values(disp, needle), reverse=True)[:count]
 
 
+def tile_shape_of_kernel(kernel: str):
+    """The library's name of the tile shape ("variant") a single-frame kernel
+    runs, from its template name; None for kernels without a choice of shape
+    (the batch and stack kernels, the adjoint)."""
+    m = re.match(r"k_(scalar|vec4|vec4p|vec4w)<([^>]*)>", kernel)
+    if not m:
+        return None
+    kind, targs = m.group(1), [t.strip() for t in m.group(2).split(",")]
+    if kind == "scalar":
+        return "scalar"
+    if kind == "vec4p":
+        return "vec4p2"
+    if kind == "vec4w":
+        return f"vec4w{targs[2]}"
+    return {"1": "vec4", "2": "vec4x2", "4": "vec4x4"}[targs[1]]
+
+
 def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: str,
             out_json: str, calib_bytes: int, calib_kernel: str, cmd: str = "",
             calib_count: int = 4, bytes_per_pixel: int = 17, adjoint: bool = False,
@@ -113,6 +171,7 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: 
     rec = {
         "workload": workload,
         "kernel": kernel,
+        "variant": tile_shape_of_kernel(kernel),
         "grid_size": grid or None,
         "pixels_per_launch": pixels,
         "algorithmic_bytes_per_launch": bytes_per_pixel * pixels,
@@ -129,6 +188,25 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, pixels: int, workload: 
         "kernel_hash": bench.kernel_hash(bench.ADJOINT_SOURCES if adjoint else None),
         "command": cmd,
     }
+    # one file per workload: the first record written (the library's default
+    # tile shape) at the top, the other tile shapes of the same sources under
+    # "other_tile_shapes"
+    old = None
+    if os.path.exists(out_json):
+        try:
+            old = json.load(open(out_json))
+        except ValueError:
+            old = None
+    if (old and old.get("workload") == workload and old.get("kernel_hash") == rec["kernel_hash"]
+            and old.get("variant") != rec["variant"]):
+        shape = {k: rec[k] for k in ("kernel", "grid_size", "hbm_read_bytes_per_launch",
+                                     "hbm_write_bytes_per_launch", "hbm_bytes_per_launch",
+                                     "read_bytes_per_pixel", "write_bytes_per_pixel",
+                                     "dispatches")}
+        old.setdefault("other_tile_shapes", {})[rec["variant"]] = shape
+        rec = old
+    elif old and old.get("kernel_hash") == rec["kernel_hash"] and "other_tile_shapes" in old:
+        rec["other_tile_shapes"] = old["other_tile_shapes"]
     with open(out_json, "w") as fh:
         json.dump(rec, fh, indent=1)
     return rec
@@ -165,13 +243,14 @@ def launches(reps: int = 20) -> None:
 
 def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
     """The benchmark's single-frame and batched configurations as a program
-    for counter passes: a calibration copy (4 times), then, with the
-    library's default tile shapes (the autotuner cannot time anything under
-    a counter profiler, which serialises every dispatch), `reps` launches
+    for counter passes: a calibration copy (4 times), then `reps` launches
     over a ring of distinct buffers for each of: four-pair, pair removal,
-    multi-scale (alpha 1, K 3) and (alpha 3, K 3) on 1920x1080; four-pair on
-    640x480 (a ring of 256); then three runs of the 256-frame mixed batch
-    (flat grid)."""
+    multi-scale (alpha 1, K 3) and (alpha 3, K 3) on 1920x1080, each in the
+    library's default tile shape and then in every other shape the autotuner
+    may choose for it (the autotuner itself cannot time anything under a
+    counter profiler, which serialises every dispatch); four-pair on 640x480
+    in each shape (a ring of 256); then three runs of the 256-frame mixed
+    batch (flat grid)."""
     sys.path.insert(0, ROOT)
     import concurrent.futures as cf
     from synth import scenes
@@ -201,23 +280,32 @@ def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
         st = bn.new_stats(n, device="cuda")
         return d, nm, mk, st
 
+    # the library's default tile shapes first, then every other shape the
+    # autotuner may choose for the configuration
+    names = dict(bn.variants())
+    runs = [("four_pair", 2, 0, 0), ("pair_removal", 2, 0, 0), ("multiscale", 1, 3, 0),
+            ("multiscale", 3, 3, 0)]
+    runs += [("four_pair", 2, 0, v) for v in range(3, 8)]
+    runs += [("pair_removal", 2, 0, v) for v in range(3, 8)]
+    runs += [("multiscale", a, 3, v) for a in (1, 3) for v in (3, 4)]
     d, nm, mk, st = ring_of(f1080, 32)
     s0 = f1080[0]
-    for method, alpha, K in (("four_pair", 2, 0), ("pair_removal", 2, 0), ("multiscale", 1, 3),
-                             ("multiscale", 3, 3)):
-        print(f"1920x1080 {method} alpha {alpha} K {K}", flush=True)
+    for method, alpha, K, v in runs:
+        print(f"1920x1080 {method} alpha {alpha} K {K} {names.get(v, 'default')}", flush=True)
         for r in range(reps):
             j = r % 32
-            bn.estimate_normals(d[j], *s0.intrinsics, alpha, method=method, scales=K,
+            bn.estimate_normals(d[j], *s0.intrinsics, alpha, method=method, scales=K, variant=v,
                                 normals=nm[j], mask=mk[j], stats=st[j])
         torch.cuda.synchronize()
     del d, nm, mk, st
     d, nm, mk, st = ring_of(f640, 256)
-    print("640x480 four_pair alpha 2", flush=True)
-    for r in range(max(reps, 256)):
-        j = r % 256
-        bn.estimate_normals(d[j], *f640[0].intrinsics, 2, normals=nm[j], mask=mk[j], stats=st[j])
-    torch.cuda.synchronize()
+    for v in (0, 3, 4, 5, 6, 7):
+        print(f"640x480 four_pair alpha 2 {names.get(v, 'default')}", flush=True)
+        for r in range(max(reps, 256)):
+            j = r % 256
+            bn.estimate_normals(d[j], *f640[0].intrinsics, 2, variant=v, normals=nm[j],
+                                mask=mk[j], stats=st[j])
+        torch.cuda.synchronize()
     del d, nm, mk, st
     frames = [bn.BatchFrame(torch.from_numpy(s.depth).cuda(), s.fx, s.fy, s.cx, s.cy)
               for s in batch_h]
@@ -349,6 +437,12 @@ def main():
     df = sub.add_parser("diff")
     df.add_argument("--reps", type=int, default=12)
     df.add_argument("--calibration-mib", type=int, default=1024)
+    tg = sub.add_parser("tracegrid")
+    tg.add_argument("trace_dir")
+    tg.add_argument("out_md")
+    tg.add_argument("--cmd", default="")
+    tg.add_argument("--pixels-of", action="append", default=[], metavar="GRID=PIXELS",
+                    help="pixels one launch of this grid size covers (repeatable)")
     v = sub.add_parser("valu")
     v.add_argument("pmc_dir")
     v.add_argument("out_md")
@@ -364,6 +458,9 @@ def main():
         print(valu_summary(a.pmc_dir, a.out_md, a.cmd))
     elif a.what == "trace":
         print(trace_summary(a.stats_csv, a.out_md, a.cmd))
+    elif a.what == "tracegrid":
+        px = {int(g): int(n) for g, n in (x.split("=") for x in a.pixels_of)}
+        print(trace_by_grid(a.trace_dir, a.out_md, a.cmd, px))
     else:
         print(json.dumps(traffic(a.fetch, a.write, a.kernel, a.pixels, a.workload, a.out,
                                  a.calib_bytes, a.calib_kernel, a.cmd, a.calib_count,
