@@ -241,35 +241,16 @@ __device__ __forceinline__ PixelOut eval_pixel(bool inside, float d1, float d2, 
 // four-pair m, taken in its closed form (d1 cancels exactly there, while the
 // rounded sum of the pairs can lose it to cancellation).
 // ---------------------------------------------------------------------------
-// The binary32 test of one pair, in the order written above: bit 0 set when
-// the pair passes (keep), bit 1 when its q is a finite number >= FLT_MIN.
-__device__ __forceinline__ uint32_t pair_keep_ok(float A, float B, float C, float xc, float yc,
-                                                 const FrameArgs &f) {
-    const float mx = f.fx * A;
-    const float my = f.fy * B;
-    const float xa = xc * A;
-    const float yb = yc * B;
-    const float t3 = xa + yb;
-    const float w = f.af * C;
-    const float mz = t3 + w;
-    const float mx2 = mx * mx;
-    const float my2 = my * my;
-    const float mz2 = mz * mz;
-    const float q = (mx2 + my2) + mz2;
-    const float ww = w * w;
-    const float hrel = f.tt * ww;
-    const float h = f.rel ? hrel : f.hconst;
-    return (q > h ? 0u : 1u) | (q_ok(q) << 1);
-}
-
-// The pair's vector (mx, my, mz), the same operations as its test.
-struct PairM {
+// The binary32 vector of one pair and its test, in the order written above.
+// keep: the pair passes; ok: its q is a finite number >= FLT_MIN.
+struct PairT {
     float mx, my, mz;
+    bool keep, ok;
 };
 
-__device__ __forceinline__ PairM pair_m(float A, float B, float C, float xc, float yc,
+__device__ __forceinline__ PairT pair_t(float A, float B, float C, float xc, float yc,
                                         const FrameArgs &f) {
-    PairM r;
+    PairT r;
     r.mx = f.fx * A;
     r.my = f.fy * B;
     const float xa = xc * A;
@@ -277,6 +258,15 @@ __device__ __forceinline__ PairM pair_m(float A, float B, float C, float xc, flo
     const float t3 = xa + yb;
     const float w = f.af * C;
     r.mz = t3 + w;
+    const float mx2 = r.mx * r.mx;
+    const float my2 = r.my * r.my;
+    const float mz2 = r.mz * r.mz;
+    const float q = (mx2 + my2) + mz2;
+    const float ww = w * w;
+    const float hrel = f.tt * ww;
+    const float h = f.rel ? hrel : f.hconst;
+    r.keep = !(q > h);
+    r.ok = __builtin_amdgcn_classf(q, 0x100);
     return r;
 }
 
@@ -309,11 +299,15 @@ __device__ __forceinline__ ClosedM closed_m(float d2, float d3, float d4, float 
     return r;
 }
 
-// Pair removal.  First the four tests only (no pair vector stays live), then
-// the closed form; the sum of the passing pairs - needed only where some
-// pair fails, which most wavefronts never see - recomputes those pairs'
-// vectors behind a wavefront-uniform branch.  The same operations in the
-// same order as a single pass, so the same bits.
+// Pair removal.  The four pairs' vectors and tests, then the closed form;
+// where some pair fails (a wavefront-uniform branch) the passing pairs'
+// vectors are summed in pair order from +0.  Each step of that sum is
+// fma(k, m_p, t) with k = 1 for a passing pair and 0 for a failing one: for a
+// passing pair that is t + m_p rounded once, as the plain sum; for a failing
+// one it adds a zero, which leaves every t of the sum unchanged (t is never
+// -0: it starts as k m_0 + (+0)).  A failing pair whose vector is not finite
+// has a q that is not finite either, and then the pixel is INVALID whatever
+// the sum holds.
 __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, float d2, float d3,
                                                      float d4, float d5, float xc, float yc,
                                                      const FrameArgs &f) {
@@ -322,34 +316,32 @@ __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, floa
     const float e4 = d4 - d1;
     const float e5 = d5 - d1;
     // (h, v) = (2, 3), (4, 3), (4, 5), (2, 5); sh, sv = ++, -+, --, +-
-    const uint32_t r0 = pair_keep_ok(e2 * d3, d2 * e3, d2 * d3, xc, yc, f);
-    const uint32_t r1 = pair_keep_ok(-(e4 * d3), d4 * e3, d4 * d3, xc, yc, f);
-    const uint32_t r2 = pair_keep_ok(-(e4 * d5), -(d4 * e5), d4 * d5, xc, yc, f);
-    const uint32_t r3 = pair_keep_ok(e2 * d5, -(d2 * e5), d2 * d5, xc, yc, f);
-    const uint32_t keep = (r0 & 1u) | ((r1 & 1u) << 1) | ((r2 & 1u) << 2) | ((r3 & 1u) << 3);
-    const bool all = keep == 0xfu;
+    const PairT p0 = pair_t(e2 * d3, d2 * e3, d2 * d3, xc, yc, f);
+    const PairT p1 = pair_t(-(e4 * d3), d4 * e3, d4 * d3, xc, yc, f);
+    const PairT p2 = pair_t(-(e4 * d5), -(d4 * e5), d4 * d5, xc, yc, f);
+    const PairT p3 = pair_t(e2 * d5, -(d2 * e5), d2 * d5, xc, yc, f);
+    const bool all = p0.keep && p1.keep && p2.keep && p3.keep;
+    const bool any = p0.keep || p1.keep || p2.keep || p3.keep;
     // all four pass: the four-pair closed form, in which d1 cancels exactly
     const ClosedM c = closed_m(d2, d3, d4, d5, xc, yc, f);
     float sx = c.mx, sy = c.my, sz = c.mz, Q = c.q;
     if (__any(!all)) {
-        // the passing pairs summed in pair order from +0
-        float tx = 0.0f, ty = 0.0f, tz = 0.0f;
-        const PairM p0 = pair_m(e2 * d3, d2 * e3, d2 * d3, xc, yc, f);
-        tx = tx + ((keep & 1u) ? p0.mx : 0.0f);
-        ty = ty + ((keep & 1u) ? p0.my : 0.0f);
-        tz = tz + ((keep & 1u) ? p0.mz : 0.0f);
-        const PairM p1 = pair_m(-(e4 * d3), d4 * e3, d4 * d3, xc, yc, f);
-        tx = tx + ((keep & 2u) ? p1.mx : 0.0f);
-        ty = ty + ((keep & 2u) ? p1.my : 0.0f);
-        tz = tz + ((keep & 2u) ? p1.mz : 0.0f);
-        const PairM p2 = pair_m(-(e4 * d5), -(d4 * e5), d4 * d5, xc, yc, f);
-        tx = tx + ((keep & 4u) ? p2.mx : 0.0f);
-        ty = ty + ((keep & 4u) ? p2.my : 0.0f);
-        tz = tz + ((keep & 4u) ? p2.mz : 0.0f);
-        const PairM p3 = pair_m(e2 * d5, -(d2 * e5), d2 * d5, xc, yc, f);
-        tx = tx + ((keep & 8u) ? p3.mx : 0.0f);
-        ty = ty + ((keep & 8u) ? p3.my : 0.0f);
-        tz = tz + ((keep & 8u) ? p3.mz : 0.0f);
+        const float k0 = p0.keep ? 1.0f : 0.0f;
+        const float k1 = p1.keep ? 1.0f : 0.0f;
+        const float k2 = p2.keep ? 1.0f : 0.0f;
+        const float k3 = p3.keep ? 1.0f : 0.0f;
+        float tx = __builtin_fmaf(k0, p0.mx, 0.0f);
+        float ty = __builtin_fmaf(k0, p0.my, 0.0f);
+        float tz = __builtin_fmaf(k0, p0.mz, 0.0f);
+        tx = __builtin_fmaf(k1, p1.mx, tx);
+        ty = __builtin_fmaf(k1, p1.my, ty);
+        tz = __builtin_fmaf(k1, p1.mz, tz);
+        tx = __builtin_fmaf(k2, p2.mx, tx);
+        ty = __builtin_fmaf(k2, p2.my, ty);
+        tz = __builtin_fmaf(k2, p2.mz, tz);
+        tx = __builtin_fmaf(k3, p3.mx, tx);
+        ty = __builtin_fmaf(k3, p3.my, ty);
+        tz = __builtin_fmaf(k3, p3.mz, tz);
         const float tx2 = tx * tx;
         const float ty2 = ty * ty;
         const float tz2 = tz * tz;
@@ -359,9 +351,8 @@ __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, floa
         sz = all ? sz : tz;
         Q = all ? Q : Qs;
     }
-    const bool ok = ((inside ? 1u : 0u) & tap_ok(d1) & tap_ok(d2) & tap_ok(d3) & tap_ok(d4) &
-                     tap_ok(d5) & (r0 >> 1) & (r1 >> 1) & (r2 >> 1) & (r3 >> 1)) != 0u;
-    const bool any = keep != 0u;
+    const bool ok = inside && (tap_ok(d1) & tap_ok(d2) & tap_ok(d3) & tap_ok(d4) & tap_ok(d5)) &&
+                    p0.ok && p1.ok && p2.ok && p3.ok;
     PixelOut o;
     o.code = !ok ? (uint32_t)BN_INVALID
                  : (!any ? (uint32_t)BN_BOUNDARY
@@ -457,10 +448,10 @@ __device__ __forceinline__ PixelOut eval_pixel_multiscale(bool inside, const flo
 // source receives 0.  Every lane of the wave must execute these.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float from_left(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_right(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ f4 from_left(f4 v) {
     return f4{from_left(v.x), from_left(v.y), from_left(v.z), from_left(v.w)};
