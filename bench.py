@@ -31,6 +31,20 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_PIXEL = 17          # 4 B depth in, 12 B normal + 1 B code out
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E, AMD published peak
+# Unpacked binary32 VALU instructions: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one operation each: FMA contraction is off and packed FP32 is not used).
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def alu_ops_per_pixel(method: str, scales: int = 0) -> int:
+    """Binary32 operations per pixel of the definition (products, sums,
+    compares and class tests; the normalisation's reciprocal square root and
+    its three products), counted on the path where every pair passes."""
+    if method == "four_pair":
+        return 35
+    if method == "pair_removal":
+        return 111
+    return 22 * scales + 16   # multiscale: 22 per scale, 16 for the rest
 KERNEL_SOURCES = ["bn_device.h", "bn_tiles.h", "bn_kernels.hip", "bn_batch.hip"]
 ADJOINT_SOURCES = ["bn_device.h", "bn_adjoint.hip", "bn_stack.hip"]
 
@@ -279,6 +293,14 @@ def roofline(px, ms, traffic=None):
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
 
 
+def alu_roofline(px, ms, ops_per_pixel):
+    """The same launch against the vector ALUs: algorithmic operations per
+    second over the unpacked binary32 issue rate."""
+    achieved = ops_per_pixel * px / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
+            "frac": achieved / ALU_PEAK_TOPS, "ops_per_pixel": ops_per_pixel}
+
+
 def roofline_from_rate(mpix_s):
     """HBM roofline of a pixel rate (17 algorithmic bytes per pixel)."""
     achieved = BYTES_PER_PIXEL * mpix_s * 1e6 / 1e9
@@ -394,7 +416,8 @@ def run_plain(args, torch, bn, inputs):
                             "unit": "Mpix/s",
                             "roofline": roofline(px, mms,
                                                  load_traffic(f"{name}_a{alpha}_k{K}_1080", px,
-                                                              variant=dict(bn.variants())[mv]))})
+                                                              variant=dict(bn.variants())[mv])),
+                            "alu_roofline": alu_roofline(px, mms, alu_ops_per_pixel(name, K))})
             log(f"{name}: {methods[-1]['value']:.0f} Mpix/s")
         extra["methods"] = methods
         extra["plain640"] = run_plain640(args, torch, bn, inputs)
@@ -422,6 +445,7 @@ def run_plain(args, torch, bn, inputs):
                    "variant_from": ("autotuner" if tuned else "--variant" if args.variant
                                     else "library default")},
         "roofline": roofline(px, ms_step, traffic),
+        "alu_roofline": alu_roofline(px, ms_step, alu_ops_per_pixel("four_pair")),
         "cpu_baseline": cpu,
     }
     out.update(extra)
@@ -845,8 +869,8 @@ def main():
             ach["batched_frac_of_pattern"] = (out["batched"]["roofline"]["achieved"]
                                               / ach["pattern_GBs"])
         line["achievable"] = ach
-    for k in ("batched", "serving", "differentiation", "methods", "hot_cache", "plain640",
-              "single_launch_us", "cpu_oracle_all_cores"):
+    for k in ("alu_roofline", "batched", "serving", "differentiation", "methods", "hot_cache",
+              "plain640", "single_launch_us", "cpu_oracle_all_cores"):
         if k in out:
             line[k] = out[k]
     import multiprocessing

@@ -31,7 +31,7 @@ constexpr uint32_t kSlots = 32;
 struct WorkArea {
     unsigned long long w[16 * (kSlots + 1)];
 };
-static_assert(sizeof(WorkArea) == 4224, "33 lines of 128 bytes");
+static_assert(sizeof(WorkArea) == 128 * (kSlots + 1), "kSlots + 1 lines of 128 bytes");
 
 // Everything a kernel needs to process one frame.
 struct FrameArgs {

@@ -316,6 +316,53 @@ def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
     print("rings done", flush=True)
 
 
+class _Request:
+    """A device depth frame offered to the server (its outputs live in the
+    server's slots)."""
+
+    def __init__(self, depth, fx, fy, cx, cy):
+        self.depth, self.fx, self.fy, self.cx, self.cy = depth, fx, fy, cx, cy
+
+    def _c(self):
+        import paper_2209_08241_amd as bn
+        H, W = self.depth.shape
+        return bn.Frame(self.depth.data_ptr(), H, W, self.depth.stride(0), self.fx, self.fy,
+                        self.cx, self.cy, 0, 0, 0)
+
+
+def serve_launches(requests: int = 4000, rate_hz: float = 50000.0) -> None:
+    """The benchmark's serving workload under a profiler: the five serving
+    sizes (320x240 to 4096x3072, seeds 3000..3004), 16 depth-scaled device
+    copies of each, offered to a server (16 GiB budget, batches of up to 16
+    requests, 2 in flight) as an open-loop Poisson stream of `requests` at
+    `rate_hz`, then `requests` / 4 at once (a backlog: full batches)."""
+    sys.path.insert(0, ROOT)
+    import concurrent.futures as cf
+    from synth import scenes
+    jobs = [(H, W, 3000 + k, {}) for k, (H, W) in enumerate(scenes.SERVE_SIZES)]
+    with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        frames_h = list(ex.map(scenes._sized_job, jobs))
+    import torch
+    import paper_2209_08241_amd as bn
+    gen = torch.Generator(device="cuda").manual_seed(3000)
+    pool = []
+    for s in frames_h:
+        d = torch.from_numpy(s.depth).cuda()
+        H, W = s.depth.shape
+        for _ in range(16):
+            f = 1.0 + 0.02 * (2.0 * float(torch.rand((), device="cuda", generator=gen)) - 1.0)
+            pool.append(_Request(d * f, s.fx, s.fy, s.cx, s.cy))
+    with bn.Server(16 << 30, max_batch=16, max_batches_in_flight=2) as srv:
+        r = srv.run_poisson(pool, rate_hz, requests, seed=3000)
+        print(f"poisson {requests} requests at {rate_hz:.0f}/s: {r['wall_s'] * 1e3:.1f} ms",
+              flush=True)
+        r = srv.run_poisson(pool, 1e12, requests // 4, seed=3100)
+        print(f"backlog {requests // 4} requests: {r['wall_s'] * 1e3:.1f} ms", flush=True)
+        print(json.dumps(srv.stats()), flush=True)
+    torch.cuda.synchronize()
+    print("serve done", flush=True)
+
+
 # kernel -> (workload, pixels or outputs per dispatch)
 def diff_launches(reps: int = 12, calibration_mib: int = 1024) -> None:
     """The differentiation workload of bench.py under a profiler: a
@@ -437,6 +484,9 @@ def main():
     df = sub.add_parser("diff")
     df.add_argument("--reps", type=int, default=12)
     df.add_argument("--calibration-mib", type=int, default=1024)
+    sv = sub.add_parser("serve")
+    sv.add_argument("--requests", type=int, default=4000)
+    sv.add_argument("--rate", type=float, default=50000.0)
     tg = sub.add_parser("tracegrid")
     tg.add_argument("trace_dir")
     tg.add_argument("out_md")
@@ -454,6 +504,8 @@ def main():
         rings(a.reps, a.calibration_mib)
     elif a.what == "diff":
         diff_launches(a.reps, a.calibration_mib)
+    elif a.what == "serve":
+        serve_launches(a.requests, a.rate)
     elif a.what == "valu":
         print(valu_summary(a.pmc_dir, a.out_md, a.cmd))
     elif a.what == "trace":
