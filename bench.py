@@ -337,8 +337,15 @@ def achievable_rates(torch, bn, reps=5):
     out["pattern_GBs"] = BYTES_PER_PIXEL * px / (ms * 1e-3) / 1e9
     out["what"] = ("GB/s of read + write bytes: torch copy_ and bn_stream_copy of 1 GiB; "
                    "bn_stream_pattern = 4 B in + 13 B out per pixel through the kernels' LDS "
-                   "staging, no arithmetic, 168 Mpixel")
+                   "staging, no arithmetic, 168 Mpixel; valu_tops: bn_alu_probe, unpacked "
+                   "binary32 multiplies per second (8192 workgroups x 256 threads x 8 "
+                   "independent chains x 4096 steps)")
     del depth, normals, mask
+    acc = torch.empty(8192 * 256, dtype=torch.float32, device="cuda")
+    lane_ops = 8192 * 256 * 8 * 4096
+    out["valu_tops"] = lane_ops / (timed(lambda: bn.alu_probe(acc, 4096)) * 1e-3) / 1e12
+    out["valu_peak_tops"] = ALU_PEAK_TOPS
+    del acc
     torch.cuda.empty_cache()
     return out
 

@@ -152,6 +152,8 @@ def _bind_eval(L) -> None:
     L.bn_stream_copy.restype = ctypes.c_int
     L.bn_stream_pattern.argtypes = [vp, vp, vp, u64, vp]
     L.bn_stream_pattern.restype = ctypes.c_int
+    L.bn_alu_probe.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, f32, vp]
+    L.bn_alu_probe.restype = ctypes.c_int
 
 
 def _bind_batch(L) -> None:
@@ -973,3 +975,19 @@ def stream_pattern(depth, normals, mask, stream=None) -> None:
                                  ctypes.c_void_p(_stream_handle(stream)))
     if rc != BN_OK:
         raise BnError(rc, "bn_stream_pattern")
+
+
+def alu_probe(out, iters: int, m: float = 1.0000001, stream=None) -> int:
+    """Independent binary32 multiply chains, 8 per thread, `iters` steps each,
+    over out.numel() / 256 workgroups; writes each thread's sum of chains to
+    `out` and returns the number of multiplies (lane operations) issued."""
+    import torch
+    if (not isinstance(out, torch.Tensor) or out.dtype != torch.float32 or not out.is_cuda
+            or not out.is_contiguous() or out.numel() % 256):
+        raise ValueError("out must be a contiguous float32 device tensor of a multiple of 256")
+    wgs = out.numel() // 256
+    rc = lib().bn_alu_probe(ctypes.c_void_p(out.data_ptr()), wgs, int(iters), float(m),
+                            ctypes.c_void_p(_stream_handle(stream)))
+    if rc != BN_OK:
+        raise BnError(rc, "bn_alu_probe")
+    return wgs * 256 * 8 * int(iters)

@@ -4,7 +4,8 @@
 //   * the estimator's traffic shape without its arithmetic: 16 bytes of
 //     depth in per thread (4 pixels), 48 bytes of "normals" out through the
 //     same LDS staging as the vector tiles (three contiguous KiB per
-//     wavefront) and 4 bytes of "codes" out.
+//     wavefront) and 4 bytes of "codes" out;
+//   * the vector ALUs: independent binary32 multiply chains in registers.
 #include "bn_internal.h"
 #include "bn_probe.h"
 #include "bn_tiles.h"
@@ -39,6 +40,23 @@ __global__ __launch_bounds__(256) void k_stream_pattern(const f4 *__restrict__ d
     __builtin_nontemporal_store(slice[128 + lane], out + 128 + lane);
 }
 
+// Eight independent chains keep every SIMD's issue slot busy at 8 wavefronts
+// per SIMD (a multiply's result is not needed for the next 7 instructions).
+__global__ __launch_bounds__(256) void k_alu_chain(float *__restrict__ out, float m,
+                                                   uint32_t iters) {
+    float x[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[c] = 1.0f + 1e-3f * (float)(threadIdx.x + c);
+    for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) x[c] = x[c] * m;
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s = s + x[c];
+    out[(uint64_t)blockIdx.x * 256u + threadIdx.x] = s;
+}
+
 }  // namespace
 }  // namespace bn
 
@@ -69,6 +87,14 @@ int bn_stream_pattern(const float *depth, float *normals, uint8_t *mask, uint64_
     hipLaunchKernelGGL(k_stream_pattern, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream,
                        reinterpret_cast<const f4 *>(depth), reinterpret_cast<f4 *>(normals),
                        reinterpret_cast<uint32_t *>(mask));
+    return hipGetLastError() == hipSuccess ? BN_OK : BN_ERR_DEVICE;
+}
+
+int bn_alu_probe(float *out, uint32_t workgroups, uint32_t iters, float m, void *stream) {
+    if (workgroups == 0) return BN_OK;
+    if (!out || (uintptr_t)out % 4) return BN_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_alu_chain, dim3(workgroups), dim3(256), 0, (hipStream_t)stream, out, m,
+                       iters);
     return hipGetLastError() == hipSuccess ? BN_OK : BN_ERR_DEVICE;
 }
 

@@ -168,6 +168,9 @@ def test_probe_argument_errors():
     assert L.bn_stream_copy(0x20000, 0x10000, 0, None) == bn.BN_OK
     assert L.bn_stream_pattern(0x10000, 0x20000, 0x30000, 1000, None) == bn.BN_ERR_INVALID_ARG
     assert L.bn_stream_pattern(0x10004, 0x20000, 0x30000, 1024, None) == bn.BN_ERR_INVALID_ARG
+    assert L.bn_alu_probe(None, 0, 16, 1.0, None) == bn.BN_OK
+    assert L.bn_alu_probe(None, 4, 16, 1.0, None) == bn.BN_ERR_INVALID_ARG
+    assert L.bn_alu_probe(0x10002, 4, 16, 1.0, None) == bn.BN_ERR_INVALID_ARG
 
 
 def test_alignment_checked_before_launch():
