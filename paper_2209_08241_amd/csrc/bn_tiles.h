@@ -193,23 +193,41 @@ __device__ __forceinline__ void vec4_eval_ms(const FrameArgs &f, uint32_t tile, 
     const uint32_t i = tile * kBlock + t;
     const bool live = i < f.nitems;
     o.live = live;
-    uint32_t y = 0, x0 = 0;
-    if (live) {
-        y = row_of(i, f.inv_gpr);
-        x0 = (i - y * f.gpr) * 4u;
-    }
+    // Every load is unconditional and in the frame: a lane past the last item
+    // takes the last item's position, a lane whose taps below leave the frame
+    // reads them from rows that are in it, and the right-hand float4s are
+    // clamped into the row.  What such a load brings in only reaches pixels
+    // that are not inside (or not live), whose codes are INVALID whatever it
+    // holds.  (Conditional loads had to zero their registers first, and the
+    // compiler waited for the centre load before issuing the rows below.)
+    const uint32_t il = live ? i : f.nitems - 1u;
+    const uint32_t y = row_of(il, f.inv_gpr);
+    const uint32_t x0 = (il - y * f.gpr) * 4u;
     const int K = f.scales;
     const uint32_t reach = (uint32_t)(K * A);
     const float *rp = f.depth + (int64_t)y * f.stride;
     const bool rows_in = live & (y + reach < (uint32_t)f.H);
-    f4 c = {0.f, 0.f, 0.f, 0.f};
-    if (live) c = *reinterpret_cast<const f4 *>(rp + x0);
+    const f4 c = *reinterpret_cast<const f4 *>(rp + x0);
+    // The rows below: from row y, or, where they would leave the frame, from
+    // the last rows that keep all K in it.  On a frame no taller than the
+    // reach no pixel is inside, and every "row below" is row y itself.
+    const bool fits = reach < (uint32_t)f.H;
+    const int64_t rstep = fits ? (int64_t)A * f.stride : 0;
+    const uint32_t yb = (fits && !rows_in) ? (uint32_t)f.H - 1u - reach : y;
+    const float *bp = f.depth + (int64_t)yb * f.stride + x0;
     f4 dn[KMAX];
 #pragma unroll
     for (int s = 0; s < KMAX; ++s) {
-        dn[s] = f4{0.f, 0.f, 0.f, 0.f};
-        if (s < K && rows_in)
-            dn[s] = *reinterpret_cast<const f4 *>(rp + (int64_t)((s + 1) * A) * f.stride + x0);
+        if (s < K) dn[s] = *reinterpret_cast<const f4 *>(bp + (int64_t)(s + 1) * rstep);
+    }
+    // The row window to the right: float4 k of lane l is lane l+k's centre;
+    // lane 63 loads its own (clamped into the row) before any lane shift, so
+    // that no shift waits for a load issued after the rows below.
+    f4 edge[RR];
+#pragma unroll
+    for (int k = 1; k <= RR; ++k) {
+        if (lane == 63)
+            edge[k - 1] = *reinterpret_cast<const f4 *>(rp + min((int)x0 + 4 * k, f.W - 4));
     }
     float row[4 * (RR + 1)];
     row[0] = c.x;
@@ -220,10 +238,7 @@ __device__ __forceinline__ void vec4_eval_ms(const FrameArgs &f, uint32_t tile, 
 #pragma unroll
     for (int k = 1; k <= RR; ++k) {
         rk = from_right(rk);
-        if (lane == 63) {
-            const int xs = (int)x0 + 4 * k;
-            rk = (live && xs < f.W) ? *reinterpret_cast<const f4 *>(rp + xs) : f4{0.f, 0.f, 0.f, 0.f};
-        }
+        if (lane == 63) rk = edge[k - 1];
         row[4 * k + 0] = rk.x;
         row[4 * k + 1] = rk.y;
         row[4 * k + 2] = rk.z;
