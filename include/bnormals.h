@@ -135,7 +135,7 @@ extern "C" {
 #define BN_SMALL_BATCH 16
 #define BN_MAX_WIDTH 65536
 #define BN_MAX_PIXELS (1LL << 28)
-#define BN_MAX_STREAMS 32 /* streams per device with a count work area */
+#define BN_MAX_STREAMS 64 /* streams per device with a count work area at a time */
 
 typedef struct bn_params {
     int32_t alpha;     /* stencil pixel distance, 1..BN_MAX_ALPHA (Section 3.1) */
@@ -163,12 +163,21 @@ typedef struct bn_params {
  * work area that the library owns (never in this structure): the
  * single-frame and stack calls take the work area of the calling stream -
  * one per (device, stream), from a fixed pool of BN_MAX_STREAMS per device
- * held by the library until the process ends (a call on a further stream
- * returns BN_ERR_UNSUPPORTED) - and a batch plan owns one per frame of its
- * capacity.  Calls on one stream run one after another, so they share its
- * work area safely; a launch captured into a graph keeps the work area of
- * the stream it was captured on, so its replays must not overlap other calls
- * on that stream (or replays of other graphs captured on it). */
+ * held by the library until the process ends - and a batch plan owns one per
+ * frame of its capacity.  Calls on one stream run one after another, so they
+ * share its work area safely.  Streams are told apart by their handle: a
+ * stream destroyed while a counted launch on it is pending must not be
+ * followed, before that launch completes, by a counted launch on a new
+ * stream that takes over its handle value.  When a further stream needs a
+ * work area and all BN_MAX_STREAMS are taken, the call first waits for the whole device
+ * (hipDeviceSynchronize) and then hands the work areas out afresh; during
+ * graph capture it returns BN_ERR_UNSUPPORTED instead, and a host thread
+ * that is between another counted call and its launch at that moment may
+ * race with it (so programs that count on more than BN_MAX_STREAMS streams
+ * from several threads at once should not).  A launch captured into a graph
+ * keeps the work area of the stream it was captured on, so its replays must
+ * not overlap other calls on that stream (or replays of other graphs
+ * captured on it). */
 typedef struct bn_frame_stats {
     uint32_t n_valid;
     uint32_t n_boundary;
@@ -207,7 +216,8 @@ typedef struct bn_frame {
  * BN_ERR_UNSUPPORTED (alpha > BN_MAX_ALPHA, scales > BN_MAX_SCALES, a
  * forced variant that the method or the buffers' layout does not allow:
  * the multi-scale method takes the vector variants only when alpha * scales
- * <= 16; or counts asked on more than BN_MAX_STREAMS streams of the device)
+ * <= 16; or counts asked, during graph capture, on a stream beyond the
+ * BN_MAX_STREAMS that hold work areas)
  * or BN_ERR_DEVICE.
  */
 int bn_estimate_normals(const float *depth, int32_t height, int32_t width,

@@ -7,7 +7,10 @@
 // taken from a pool in device memory that each device holds from the
 // library's first use until the process ends.  Launches on one stream run
 // one after another, so they can share the stream's set; launches on
-// distinct streams get distinct sets.
+// distinct streams get distinct sets.  Streams are told apart by their
+// handle.  When every set of a device is taken, the next new stream waits
+// for the whole device (outside graph capture) and the sets are handed out
+// afresh: every launch that used them has then completed.
 #include <map>
 #include <mutex>
 #include <utility>
@@ -20,7 +23,7 @@ namespace {
 constexpr int kMaxDevices = 64;
 constexpr size_t kSetAreas = BN_MAX_STACK;  // one area per frame of a stack
 
-// BN_MAX_STREAMS sets of kSetAreas work areas (8.6 MB); each set is zeroed
+// BN_MAX_STREAMS sets of kSetAreas work areas (17.3 MB); each set is zeroed
 // on the stream it is given to before that stream's first launch uses it.
 __device__ __align__(256) WorkArea g_pool[BN_MAX_STREAMS * kSetAreas];
 
@@ -54,7 +57,21 @@ int stream_work_areas(hipStream_t stream, WorkArea **out) {
         *out = g_base[dev] + (size_t)it->second * kSetAreas;
         return BN_OK;
     }
-    if (g_sets_used[dev] >= BN_MAX_STREAMS) return BN_ERR_UNSUPPORTED;
+    if (g_sets_used[dev] >= BN_MAX_STREAMS) {
+        // every set is taken: once the device is idle, none is in use
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return BN_ERR_DEVICE;
+        if (cs != hipStreamCaptureStatusNone) return BN_ERR_UNSUPPORTED;
+        if (hipDeviceSynchronize() != hipSuccess) return BN_ERR_DEVICE;
+        for (auto e = g_set_of.begin(); e != g_set_of.end();) {
+            if (e->first.first == dev) {
+                e = g_set_of.erase(e);
+            } else {
+                ++e;
+            }
+        }
+        g_sets_used[dev] = 0;
+    }
     WorkArea *set = g_base[dev] + (size_t)g_sets_used[dev] * kSetAreas;
     // zero the set on its stream, ahead of the launch that will use it (a
     // fill kernel, so that a graph captured from this stream replays it
