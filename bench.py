@@ -41,7 +41,7 @@ def alu_ops_per_pixel(method: str, scales: int = 0) -> int:
     compares and class tests; the normalisation's reciprocal square root and
     its three products), counted on the path where every pair passes."""
     if method == "four_pair":
-        return 35
+        return 34
     if method == "pair_removal":
         return 111
     return 22 * scales + 16   # multiscale: 22 per scale, 16 for the rest
