@@ -47,14 +47,24 @@ def _csv_rows(path_or_dir: str, pattern: str):
 
 
 def trace_summary(stats_csv: str, out_md: str, cmd: str = "") -> str:
+    """The kernel statistics of a rocprofv3 run, with each kernel's median
+    duration from the kernel trace beside them when the trace is there."""
     rows = _csv_rows(stats_csv, "*kernel_stats.csv")
+    base = stats_csv if os.path.isdir(stats_csv) else os.path.dirname(stats_csv)
+    med: dict = {}
+    if glob.glob(os.path.join(base, "*kernel_trace.csv")):
+        for r in _csv_rows(base, "*kernel_trace.csv"):
+            med.setdefault(r["Kernel_Name"], []).append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     lines = ["# rocprofv3 kernel statistics", ""]
     if cmd:
         lines += ["Command:", "", "```", cmd, "```", ""]
-    lines += ["| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    lines += ["| kernel | calls | avg us | median us | min us | max us | share % |",
+              "|---|---|---|---|---|---|---|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
         name = r["Name"] if len(r["Name"]) <= 160 else r["Name"][:100] + " ..."
-        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.3f} | "
+        m = f"{statistics.median(med[r['Name']]):.3f}" if r["Name"] in med else ""
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.3f} | {m} | "
                      f"{float(r['MinNs']) / 1e3:.3f} | {float(r['MaxNs']) / 1e3:.3f} | "
                      f"{float(r['Percentage']):.2f} |")
     text = "\n".join(lines) + "\n"
