@@ -169,15 +169,15 @@ typedef struct bn_params {
  * stream destroyed while a counted launch on it is pending must not be
  * followed, before that launch completes, by a counted launch on a new
  * stream that takes over its handle value.  When a further stream needs a
- * work area and all BN_MAX_STREAMS are taken, the call first waits for the whole device
- * (hipDeviceSynchronize) and then hands the work areas out afresh; during
- * graph capture it returns BN_ERR_UNSUPPORTED instead, and a host thread
- * that is between another counted call and its launch at that moment may
- * race with it (so programs that count on more than BN_MAX_STREAMS streams
- * from several threads at once should not).  A launch captured into a graph
- * keeps the work area of the stream it was captured on, so its replays must
- * not overlap other calls on that stream (or replays of other graphs
- * captured on it). */
+ * work area and all BN_MAX_STREAMS are taken, the call first waits for the
+ * whole device (hipDeviceSynchronize) and then hands the work areas out
+ * afresh; during graph capture it returns BN_ERR_UNSUPPORTED instead, and a
+ * host thread that is between another counted call and its launch at that
+ * moment may race with it (so programs that count on more than
+ * BN_MAX_STREAMS streams from several threads at once should not).  A launch
+ * captured into a graph keeps the work area of the stream it was captured
+ * on, so its replays must not overlap other calls on that stream (or replays
+ * of other graphs captured on it). */
 typedef struct bn_frame_stats {
     uint32_t n_valid;
     uint32_t n_boundary;
