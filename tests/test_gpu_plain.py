@@ -240,3 +240,57 @@ def test_max_pixels_sampled():
         got_n = n[y0:y1].cpu().numpy()
         got_m = m[y0:y1].cpu().numpy()
         assert_parity(ref, got_n, got_m, what=f"rows {y0}:{y1}")
+
+
+def test_max_pixels_counts_and_variants():
+    """The 2^28-pixel frame, a smooth surface with steps and holes: the
+    four-pair counts equal the oracle's exactly (the oracle's row entry band by
+    band over the whole frame), and pair removal and multi-scale (alpha 2, K 2)
+    match the oracle on sampled row bands.  The surface is smooth at the pixel
+    spacing, so the per-scale normals of multi-scale point the same way; where
+    noise dominates instead, their sum can cancel and the binary32 error grows
+    with the cancellation, which the boundary test does not bound."""
+    import torch
+    H, W = 4096, 65536
+    log("max-size frame (counts, variants): generating")
+    x = torch.arange(W, device="cuda", dtype=torch.float64)[None, :]
+    y = torch.arange(H, device="cuda", dtype=torch.float64)[:, None]
+    d = (1.5 + x / W + 0.5 * y / H
+         + 0.1 * torch.sin(2 * np.pi * x / 6000) * torch.sin(2 * np.pi * y / 700)
+         + 0.4 * (torch.div(x, 5000, rounding_mode="floor")
+                  + torch.div(y, 600, rounding_mode="floor")).remainder(2)).float()
+    del x, y
+    holes = torch.rand((H, W), device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    d[holes < 0.02] = 0.0
+    del holes
+    fx, fy, cx, cy = 20000.0, 20000.0, 32767.5, 2047.5
+    normals = torch.empty((H, W, 3), device="cuda")
+    mask = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    st = bn.new_stats(device="cuda")
+    bn.estimate_normals(d, fx, fy, cx, cy, 2, "rel", 4.0, normals=normals, mask=mask, stats=st)
+    torch.cuda.synchronize()
+    got = [int(v) for v in st.cpu()[:3]]
+    want = np.zeros(3, dtype=np.uint64)
+    step = 512
+    for y0 in range(0, H, step):
+        y1 = min(H, y0 + step)
+        r0, r1 = max(0, y0 - 2), min(H, y1 + 2)
+        band = np.ascontiguousarray(d[r0:r1].cpu().numpy())
+        ref = oracle.default().normals_f32_rows(band, fx, fy, cx, cy - r0, 2, "rel", 4.0,
+                                                y0 - r0, y1 - r0)
+        want += ref["counts"]
+    log(f"max-size counts: gpu {got}, oracle {[int(c) for c in want]}")
+    assert got == [int(c) for c in want]
+    assert min(got) > H * W // 20, "the frame should mix all three codes"
+    for method, K, reach in (("pair_removal", 0, 2), ("multiscale", 2, 4)):
+        log(f"max-size {method}")
+        bn.estimate_normals(d, fx, fy, cx, cy, 2, "rel", 4.0, method=method, scales=K,
+                            normals=normals, mask=mask, stats=st)
+        torch.cuda.synchronize()
+        for (y0, y1) in ((0, 6), (2045, 2052), (4088, 4096)):
+            r0, r1 = max(0, y0 - reach), min(H, y1 + reach)
+            band = np.ascontiguousarray(d[r0:r1].cpu().numpy())
+            ref = oracle.variant_f32(band, fx, fy, cx, cy - r0, 2, "rel", 4.0, method=method,
+                                     scales=K, rows=(y0 - r0, y1 - r0))
+            assert_parity(ref, normals[y0:y1].cpu().numpy(), mask[y0:y1].cpu().numpy(),
+                          what=f"{method} rows {y0}:{y1}")
