@@ -290,7 +290,7 @@ __device__ __forceinline__ void vjp4_band(const FrameArgs &f, const float *__res
                           (lane < (uint32_t)(kVjpLead + kVjpGroups)) & (x0 < f.W);
     auto put = [&](int y, f4 v) {
         if (out_lane && y < f.H)
-            __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(gd + (int64_t)y * f.W + x0));
+            out_store(v, out_buf(gd + (int64_t)y * f.W, 4u * (uint32_t)f.W), 4u * (uint32_t)x0);
     };
     // The band's 2a outer rows, dealt round the wavefronts.
     for (int k = (int)w; k < 2 * A; k += NW) {

@@ -443,6 +443,46 @@ __device__ __forceinline__ PixelOut eval_pixel_multiscale(bool inside, const flo
 }
 
 // ---------------------------------------------------------------------------
+// Output stores.  Normals and codes are written once and read by no later
+// work item of the launch, so they are stored streaming (nt) at device scope
+// (sc1): written through the XCD's L2 rather than left dirty in it (the
+// cache-policy bits 2 and 16 of the gfx9 buffer-store builtins).  Each
+// wavefront stores through a buffer resource that covers exactly its own
+// share of the output, whose size the hardware checks every lane's offset
+// against (raw buffer, stride 0): a lane whose store would start at or past
+// the end stores nothing.  The base is wavefront-uniform, so the resource
+// lives in scalar registers.
+// ---------------------------------------------------------------------------
+constexpr int kOutPolicy = 2 | 16;          // nt | sc1
+constexpr int kRsrcFormat = 0x00020000;     // word 3: 32-bit data format, no swizzle
+
+struct OutBuf {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+// The wavefront's index in its workgroup, as a scalar.
+__device__ __forceinline__ uint32_t wave_id() {
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// base: wavefront-uniform; bytes: the size of the share, < 2^31.
+__device__ __forceinline__ OutBuf out_buf(void *base, uint32_t bytes) {
+    return OutBuf{__builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, kRsrcFormat)};
+}
+__device__ __forceinline__ void out_store(f4 v, const OutBuf &b, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, b.r, off, 0, kOutPolicy);
+}
+__device__ __forceinline__ void out_store(uint32_t v, const OutBuf &b, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, b.r, off, 0, kOutPolicy);
+}
+__device__ __forceinline__ void out_store(float v, const OutBuf &b, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), b.r, off, 0, kOutPolicy);
+}
+__device__ __forceinline__ void out_store_byte(uint8_t v, const OutBuf &b, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b8(v, b.r, off, 0, kOutPolicy);
+}
+
+// ---------------------------------------------------------------------------
 // Wavefront lane shifts (DPP wave_shr:1 / wave_shl:1).  Lane i receives the
 // value of lane i-1 (from_left) or i+1 (from_right); the lane without a
 // source receives 0.  Every lane of the wave must execute these.

@@ -1,6 +1,7 @@
 // Bandwidth probes: the HBM rates this GPU reaches for plain streaming
 // traffic, as the achievable reference next to the 8 TB/s peak.
-//   * a copy with 16-byte non-temporal loads and stores;
+//   * a copy with 16-byte non-temporal loads and streaming device-scope
+//     stores (the stores of the estimator's outputs);
 //   * the estimator's traffic shape without its arithmetic: 16 bytes of
 //     depth in per thread (4 pixels), 48 bytes of "normals" out through the
 //     same LDS staging as the vector tiles (three contiguous KiB per
@@ -16,28 +17,32 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_stream_copy(const f4 *__restrict__ src,
                                                      f4 *__restrict__ dst, uint64_t n16) {
-    const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    const uint64_t b0 = (uint64_t)blockIdx.x * 256u;
+    const uint64_t i = b0 + threadIdx.x;
+    const uint32_t nb = n16 - b0 < 256u ? (uint32_t)(n16 - b0) : 256u;
+    if (i < n16) out_store(__builtin_nontemporal_load(src + i), out_buf(dst + b0, 16u * nb),
+                           16u * threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_stream_pattern(const f4 *__restrict__ depth,
                                                         f4 *__restrict__ normals,
                                                         uint32_t *__restrict__ mask) {
     __shared__ TileLds lds;
-    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = wave_id();
     const uint64_t i = (uint64_t)blockIdx.x * 256u + t;
     const f4 c = depth[i];
-    __builtin_nontemporal_store(__float_as_uint(c.x) & 0x01010101u, mask + i);
+    out_store(__float_as_uint(c.x) & 0x01010101u,
+              out_buf(mask + (uint64_t)blockIdx.x * 256u + 64u * w, 256u), 4u * lane);
     f4 *slice = lds.v + 192 * w;
     wave_lds_sync();
     slice[3 * lane + 0] = c;
     slice[3 * lane + 1] = c * 2.0f;
     slice[3 * lane + 2] = c * 3.0f;
     wave_lds_sync();
-    f4 *out = normals + 3 * ((uint64_t)blockIdx.x * 256u + 64u * w);
-    __builtin_nontemporal_store(slice[lane], out + lane);
-    __builtin_nontemporal_store(slice[64 + lane], out + 64 + lane);
-    __builtin_nontemporal_store(slice[128 + lane], out + 128 + lane);
+    const OutBuf nb = out_buf(normals + 3 * ((uint64_t)blockIdx.x * 256u + 64u * w), 3072u);
+    out_store(slice[lane], nb, 16u * lane);
+    out_store(slice[64 + lane], nb, 16u * lane + 1024u);
+    out_store(slice[128 + lane], nb, 16u * lane + 2048u);
 }
 
 // Eight independent chains keep every SIMD's issue slot busy at 8 wavefronts

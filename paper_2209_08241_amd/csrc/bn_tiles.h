@@ -287,16 +287,22 @@ __device__ __forceinline__ void vec4_eval_method(const FrameArgs &f, uint32_t ti
 // Vector tile, second half: the four codes with one 32-bit store, the 12
 // normal floats through the wavefront's LDS slice with contiguous 16-byte
 // stores (lane l holds groups 3l..3l+2 of the slice; store k writes
-// float4s 64k .. 64k+63 of it, one contiguous KiB).
+// float4s 64k .. 64k+63 of it, one contiguous KiB).  The stores stream at
+// device scope (out_store); the wavefront's share of the frame bounds them,
+// so the lanes past the frame's last work item store nothing.
 template <int M, int TB = kBlock>
 __device__ __forceinline__ void vec4_write(const FrameArgs &f, uint32_t tile, TileLdsT<TB> &lds,
                                            const Vec4Out &o) {
     const uint32_t t = threadIdx.x;
     const uint32_t lane = t & 63u;
-    const uint32_t i = tile * TB + t;
     const float *nv = o.nv;
-    if (o.live) __builtin_nontemporal_store(o.codes, reinterpret_cast<uint32_t *>(f.mask) + i);
-    const uint32_t w = t >> 6;
+    const uint32_t w = wave_id();
+    const uint32_t g0 = tile * TB + 64 * w;  // first work item of this wavefront
+    const uint32_t ng = g0 < f.nitems ? min(64u, f.nitems - g0) : 0u;
+    if (ng) {
+        const OutBuf mb = out_buf(reinterpret_cast<uint32_t *>(f.mask) + g0, 4 * ng);
+        out_store(o.codes, mb, 4 * lane);
+    }
     f4 *slice = lds.v + 192 * w;
     if (!kEarlyStage<M>) {
         wave_lds_sync();
@@ -305,15 +311,10 @@ __device__ __forceinline__ void vec4_write(const FrameArgs &f, uint32_t tile, Ti
         slice[3 * lane + 2] = f4{nv[8], nv[9], nv[10], nv[11]};
     }
     wave_lds_sync();
-    const uint32_t g0 = tile * TB + 64 * w;  // first group of this wavefront
-    if (g0 < f.nitems) {
-        const uint32_t n = 3 * min(64u, f.nitems - g0);
-        f4 *out = reinterpret_cast<f4 *>(f.normals) + 3 * (int64_t)g0;
+    if (ng) {
+        const OutBuf nb = out_buf(reinterpret_cast<f4 *>(f.normals) + 3 * (int64_t)g0, 48 * ng);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const uint32_t j = 64 * k + lane;
-            if (j < n) __builtin_nontemporal_store(slice[j], out + j);
-        }
+        for (int k = 0; k < 3; ++k) out_store(slice[64 * k + lane], nb, 16 * lane + 1024 * k);
     }
 }
 
@@ -388,27 +389,23 @@ __device__ __forceinline__ void scalar_eval(const FrameArgs &f, uint32_t tile, S
 __device__ __forceinline__ void scalar_write(const FrameArgs &f, uint32_t tile, TileLds &lds,
                                              const ScalarOut &r) {
     float *s = reinterpret_cast<float *>(lds.v);
-    const uint32_t i = tile * kBlock + threadIdx.x;
-    if (r.live) f.mask[i] = (uint8_t)r.code;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t w = wave_id();
+    const uint32_t p0 = tile * kBlock + 64 * w;  // first pixel of this wavefront
+    const uint32_t np = p0 < f.nitems ? min(64u, f.nitems - p0) : 0u;
+    if (np) out_store_byte((uint8_t)r.code, out_buf(f.mask + p0, np), lane);
     const float nx = r.nx, ny = r.ny, nz = r.nz;
     // wavefront-local transpose through this wavefront's LDS slice
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t w = threadIdx.x >> 6;
     float *slice = s + 192 * w;
     wave_lds_sync();
     slice[3 * lane + 0] = nx;
     slice[3 * lane + 1] = ny;
     slice[3 * lane + 2] = nz;
     wave_lds_sync();
-    const uint32_t p0 = tile * kBlock + 64 * w;  // first pixel of this wavefront
-    if (p0 < f.nitems) {
-        const uint32_t n = 3 * min(64u, f.nitems - p0);
-        float *out = f.normals + 3 * (int64_t)p0;
+    if (np) {
+        const OutBuf nb = out_buf(f.normals + 3 * (int64_t)p0, 12 * np);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const uint32_t j = 64 * k + lane;
-            if (j < n) out[j] = slice[j];
-        }
+        for (int k = 0; k < 3; ++k) out_store(slice[64 * k + lane], nb, 4 * lane + 256 * k);
     }
 }
 
