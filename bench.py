@@ -356,9 +356,15 @@ def run_plain640(args, torch, bn, inputs):
     shape."""
     scs640 = inputs["plain640"]
     r640 = Ring(torch, bn, scs640, 256)
-    v640 = (bn.autotune_plain(480, 640, args.alpha, args.mode, args.tau)[0]
-            if not args.no_autotune else bn.default_variant(480, 640, "four_pair", args.alpha, 0))
-    kw640 = dict(alpha=args.alpha, mode=args.mode, tau=args.tau)
+    if args.variant:
+        v640, from640 = args.variant, "--variant"
+    elif args.no_autotune:
+        v640, from640 = bn.default_variant(480, 640, "four_pair", args.alpha, 0), "library default"
+    else:
+        v640 = bn.autotune_plain(480, 640, args.alpha, args.mode, args.tau)[0]
+        from640 = "autotuner"
+    # variant 0 takes the autotuner's entry for this size when there is one
+    kw640 = dict(alpha=args.alpha, mode=args.mode, tau=args.tau, variant=args.variant)
     parity_check(r640, kw640, args.alpha, args.mode, args.tau)
     ms640, steps640, warm640, _ = r640.time(kw640, 2560, 256)
     px640 = 640 * 480
@@ -370,7 +376,7 @@ def run_plain640(args, torch, bn, inputs):
             "value": px640 / (ms640 * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_step": ms640,
             "us_per_frame": ms640 * 1e3, "steps": steps640, "warmup": warm640,
             "variant": name640,
-            "variant_from": "library default" if args.no_autotune else "autotuner",
+            "variant_from": from640,
             "roofline": roofline(px640, ms640, load_traffic("plain640", px640,
                                                             variant=name640))}
 

@@ -295,9 +295,9 @@ def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
     names = dict(bn.variants())
     runs = [("four_pair", 2, 0, 0), ("pair_removal", 2, 0, 0), ("multiscale", 1, 3, 0),
             ("multiscale", 3, 3, 0)]
-    runs += [("four_pair", 2, 0, v) for v in range(3, 8)]
-    runs += [("pair_removal", 2, 0, v) for v in range(3, 8)]
-    runs += [("multiscale", a, 3, v) for a in (1, 3) for v in (3, 4)]
+    runs += [("four_pair", 2, 0, v) for v in (1, 3, 4, 5, 6, 7)]
+    runs += [("pair_removal", 2, 0, v) for v in (1, 3, 4, 5, 6, 7)]
+    runs += [("multiscale", a, 3, v) for a in (1, 3) for v in (1, 3, 4)]
     d, nm, mk, st = ring_of(f1080, 32)
     s0 = f1080[0]
     for method, alpha, K, v in runs:
@@ -309,7 +309,7 @@ def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
         torch.cuda.synchronize()
     del d, nm, mk, st
     d, nm, mk, st = ring_of(f640, 256)
-    for v in (0, 3, 4, 5, 6, 7):
+    for v in (0, 1, 3, 4, 5, 6, 7):
         print(f"640x480 four_pair alpha 2 {names.get(v, 'default')}", flush=True)
         for r in range(max(reps, 256)):
             j = r % 256
