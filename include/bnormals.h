@@ -141,7 +141,11 @@ typedef struct bn_params {
     int32_t alpha;     /* stencil pixel distance, 1..BN_MAX_ALPHA (Section 3.1) */
     int32_t mask_mode; /* BN_MASK_REL, BN_MASK_ABS or BN_MASK_NONE (Section 3.2) */
     float tau;         /* threshold, finite and > 0 (ignored by BN_MASK_NONE) */
-    uint32_t variant;  /* 0 = library's choice; else a kernel variant id
+    uint32_t variant;  /* 0 = library's choice (the autotuner's entry for
+                          the frame's size class, else vector tiles where the
+                          method and layout allow them, except four-pair
+                          frames of at most 2^19 pixels, which take the
+                          scalar tiles); else a kernel variant id
                           (bn_variant_count / bn_variant_name), for tests and
                           tuning: every variant writes identical output */
     int32_t method;    /* BN_METHOD_*; 0 = the paper's four-pair estimator */

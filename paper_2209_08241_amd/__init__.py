@@ -203,10 +203,12 @@ def default_variant(height: int, width: int, method="four_pair", alpha: int = 2,
                     scales: int = 0) -> int:
     """The variant the library takes with no autotuning entry, for dense
     frames of this size (vector tiles when the method and the layout allow
-    them)."""
+    them, except four-pair frames of at most 2^19 pixels: scalar tiles)."""
     me = METHODS[method] if isinstance(method, str) else int(method)
     vec_method = me != METHODS["multiscale"] or alpha * max(scales, 1) <= 16
-    return 2 if (vec_method and width % 4 == 0) else 1
+    if not (vec_method and width % 4 == 0):
+        return 1
+    return 1 if (me == METHODS["four_pair"] and height * width <= (1 << 19)) else 2
 
 
 def variants() -> Sequence[Tuple[int, str]]:

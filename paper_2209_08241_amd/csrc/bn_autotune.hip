@@ -230,9 +230,8 @@ int bn_autotune_plain(int32_t height, int32_t width, const bn_params *params, in
     // more than kMargin (choices within run-to-run noise would otherwise flip
     // between runs).
     constexpr float kMargin = 0.97f;
-    const int dflt = (method_has_vec4(params) && vec4_layout(d[0], width, width, n[0], m[0]))
-                         ? (int)VAR_VEC4
-                         : (int)VAR_SCALAR;
+    const int dflt =
+        default_plain_variant(params, px, vec4_layout(d[0], width, width, n[0], m[0]));
     int best = 0;
     float best_t = 1e30f, dflt_t = 1e30f;
     const int reps = ring * ((px < (1u << 20)) ? 8 : 3);

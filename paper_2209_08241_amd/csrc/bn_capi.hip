@@ -43,6 +43,18 @@ bool method_has_vec4(const bn_params *p) {
     return p->method != BN_METHOD_MULTISCALE || p->alpha * p->scales <= kMsVecReach;
 }
 
+// A small frame has few tiles: at 1024 pixels a tile, a 640x480 frame is
+// 1200 wavefronts, about one per SIMD, and its launch is one chain of
+// latencies; at one pixel a thread it is 4800 wavefronts whose latencies
+// overlap.  Four-pair, graph-replayed: 320x240 3.19 against 3.60-3.81 us,
+// 640x480 3.77 against 4.25-4.37 us for the vector shapes; 1280x720 the
+// same within 1.5%; 1920x1080 9.2 against 7.5 us.
+int default_plain_variant(const bn_params *p, uint64_t pixels, bool vec_layout) {
+    if (!vec_layout || !method_has_vec4(p)) return VAR_SCALAR;
+    if (p->method == BN_METHOD_FOUR_PAIR && pixels <= kSmallFrame) return VAR_SCALAR;
+    return VAR_VEC4;
+}
+
 int check_frame_args(const float *depth, int32_t H, int32_t W, int64_t stride, float fx,
                      float fy, float cx, float cy, const float *normals, const uint8_t *mask) {
     if (H < 0 || W < 0) return BN_ERR_INVALID_ARG;
@@ -122,8 +134,8 @@ static int pick_variant(const float *depth, int32_t H, int32_t W, int64_t stride
                         const float *normals, const uint8_t *mask, const bn_params *p) {
     const int tuned = tuned_plain_variant(p->method, p->alpha, (uint64_t)H * (uint64_t)W);
     if (tuned > 0 && method_variant_ok(p, tuned, depth, W, stride, normals, mask)) return tuned;
-    if (method_has_vec4(p) && vec4_layout(depth, W, stride, normals, mask)) return VAR_VEC4;
-    return VAR_SCALAR;
+    return default_plain_variant(p, (uint64_t)H * (uint64_t)W,
+                                 vec4_layout(depth, W, stride, normals, mask));
 }
 
 void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t stride,

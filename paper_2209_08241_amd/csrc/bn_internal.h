@@ -45,6 +45,11 @@ bool vec4_layout(const float *depth, int32_t W, int64_t stride, const float *nor
 // True when the method can take vector tiles (multi-scale: alpha * scales
 // <= kMsVecReach).
 bool method_has_vec4(const bn_params *p);
+// The plain entry point's tile shape when nothing is tuned for the frame:
+// vector tiles where the method and the layout allow them, except four-pair
+// frames of at most kSmallFrame pixels, which take the scalar tiles.
+constexpr uint64_t kSmallFrame = 1u << 19;
+int default_plain_variant(const bn_params *p, uint64_t pixels, bool vec_layout);
 // Per-frame kernel arguments (derived constants included); work = NULL (the
 // caller sets the count work area when stats is given).
 void fill_frame_args(FrameArgs &f, const float *depth, int32_t H, int32_t W, int64_t stride,
