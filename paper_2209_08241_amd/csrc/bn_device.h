@@ -24,9 +24,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kBlock = 256;  // 4 wave64 per workgroup
 
 // The in-launch reduction's device words for one frame (library-owned; zero
-// between launches): line 0 holds the level-2 word, lines 1..kSlots the
-// level-1 slot words, one 128-byte line each so that the slots' atomics
-// proceed in parallel.
+// between launches): line 0 holds the root word, lines 1..kSlots the slot
+// words, one 128-byte line each so that the slots' atomics proceed in
+// parallel.
 constexpr uint32_t kSlots = 32;
 struct WorkArea {
     unsigned long long w[16 * (kSlots + 1)];
@@ -509,40 +509,49 @@ __device__ __forceinline__ uint32_t wave_count(bool pred) {
 // ---------------------------------------------------------------------------
 // Per-frame counts, reduced inside the launch.
 //
-// A frame's pixels are split into `nparts` parts (workgroups or tiles).  Each
-// part contributes its VALID and BOUNDARY counts with ONE relaxed 64-bit
-// atomic add on the word of slot (part % kSlots) of the frame's WorkArea,
-// each slot on its own 128-byte line so that the adds of different slots
-// proceed in parallel.  The word packs the counts and an arrival ticket, so
-// the value the atomic returns holds every earlier contribution: the last
-// arrival of a slot (ticket = parts in the slot - 1) knows the slot total
-// without any fence or reload.  It clears the slot and forwards the total
-// the same way to the level-2 word; the last of those stores (or adds) the
-// frame totals in the destination's counters (INVALID = pixels - VALID -
-// BOUNDARY) and clears the level-2 word.  The work area is therefore zero
-// again after every launch.
+// A frame's pixels are split into `nparts` parts (workgroups or tiles),
+// numbered in about the order the hardware dispatches them.  The last
+// kDirect parts contribute their VALID and BOUNDARY counts with ONE relaxed
+// 64-bit atomic add on the root word of the frame's WorkArea; every other
+// part adds to the word of slot (part % kSlots), each slot on its own
+// 128-byte line so that the adds of different slots proceed in parallel.
+// A word packs the counts and an arrival ticket, so the value the atomic
+// returns holds every earlier contribution: the last arrival of a slot
+// (ticket = parts in the slot - 1) knows the slot total without any fence
+// or reload, clears the slot and forwards the total to the root the same
+// way; the last arrival at the root (a slot's forward or a direct part)
+// stores (or adds) the frame totals in the destination's counters (INVALID
+// = pixels - VALID - BOUNDARY) and clears the root.  The work area is
+// therefore zero again after every launch.  The parts dispatched last
+// usually finish last, and a direct part that finishes last waits for one
+// return before it stores the totals where a slot's part waits for two
+// (1080p four-pair launch: 7.23-7.31 against 7.31-7.40 us).
 //
-// Level 1 word: VALID [0,24) | BOUNDARY [24,48) | ticket [48,64)
+// Slot word: VALID [0,24) | BOUNDARY [24,48) | ticket [48,64)
 //   (a slot holds fewer than 2^24 pixels and 2^16 parts for frames of at
 //    most 2^28 pixels and parts of at most 2^12 pixels).
-// Level 2 word: VALID [0,29) | BOUNDARY [29,58) | ticket [58,64)
-//   (at most 2^28 pixels, at most kSlots = 32 arrivals).
+// Root word: VALID [0,29) | BOUNDARY [29,58) | ticket [58,64)
+//   (at most 2^28 pixels, at most kSlots + kDirect = 63 arrivals).
 // ---------------------------------------------------------------------------
+constexpr uint32_t kDirect = 31;
+static_assert(kSlots + kDirect <= 63, "root arrivals fit the 6-bit ticket");
+
 __device__ __forceinline__ unsigned long long *stats_word(WorkArea *wa, uint32_t slot) {
-    // slot 0..kSlots-1: level 1 (lines 1..kSlots); kSlots: level 2 (line 0)
+    // slot 0..kSlots-1: the slots (lines 1..kSlots); kSlots: the root (line 0)
     return &wa->w[slot < kSlots ? 16 * (slot + 1) : 0];
 }
 
-// First half: the level-1 atomic.  Its result is used only in the second
-// half, so the caller can place other work (the output stores) in between
-// and hide the atomic's round trip behind it.
+// First half: the part's atomic (on its slot or the root).  Its result is
+// used only in the second half, so the caller can place other work (the
+// output stores) in between and hide the atomic's round trip behind it.
 struct CountTicket {
     WorkArea *work;
     bn_frame_stats *out;
     unsigned long long *w1;
     unsigned long long mine1;
     unsigned long long old1;
-    uint32_t ns, nparts, npix, overwrite;
+    uint32_t ns, npix, overwrite, nroot;
+    bool direct;
 };
 
 __device__ __forceinline__ CountTicket count_issue(WorkArea *work, bn_frame_stats *out,
@@ -551,14 +560,22 @@ __device__ __forceinline__ CountTicket count_issue(WorkArea *work, bn_frame_stat
                                                    uint32_t npix, uint32_t overwrite) {
     CountTicket k;
     k.overwrite = overwrite;
-    const uint32_t s = part % kSlots;
     k.work = work;
     k.out = out;
-    k.ns = nparts / kSlots + (s < nparts % kSlots ? 1u : 0u);
-    k.nparts = nparts;
     k.npix = npix;
-    k.w1 = stats_word(work, s);
-    k.mine1 = (unsigned long long)nvalid | ((unsigned long long)nboundary << 24) | (1ull << 48);
+    const uint32_t nslotted = nparts > kDirect ? nparts - kDirect : 0u;
+    k.direct = part >= nslotted;
+    k.nroot = (nslotted < kSlots ? nslotted : kSlots) + (nparts - nslotted);
+    if (k.direct) {
+        k.ns = 0;
+        k.w1 = stats_word(work, kSlots);
+        k.mine1 = (unsigned long long)nvalid | ((unsigned long long)nboundary << 29) | (1ull << 58);
+    } else {
+        const uint32_t s = part % kSlots;
+        k.ns = nslotted / kSlots + (s < nslotted % kSlots ? 1u : 0u);
+        k.w1 = stats_word(work, s);
+        k.mine1 = (unsigned long long)nvalid | ((unsigned long long)nboundary << 24) | (1ull << 48);
+    }
     k.old1 = atomicAdd(k.w1, k.mine1);
     return k;
 }
@@ -578,23 +595,30 @@ __device__ __forceinline__ void put_counts(bn_frame_stats *st, uint32_t vt, uint
     }
 }
 
+// An arrival at the root: the last one stores the frame totals.
+__device__ __forceinline__ void root_arrival(const CountTicket &k, unsigned long long old2,
+                                             unsigned long long mine2) {
+    if ((uint32_t)(old2 >> 58) != k.nroot - 1u) return;
+    const unsigned long long tot2 = old2 + mine2;
+    atomicExch(stats_word(k.work, kSlots), 0ull);
+    const uint32_t vt = (uint32_t)(tot2 & ((1ull << 29) - 1));
+    const uint32_t bt = (uint32_t)((tot2 >> 29) & ((1ull << 29) - 1));
+    put_counts(k.out, vt, bt, k.npix, k.overwrite);
+}
+
 __device__ __forceinline__ void count_finish(const CountTicket &k) {
+    if (k.direct) {
+        root_arrival(k, k.old1, k.mine1);
+        return;
+    }
     if ((uint32_t)(k.old1 >> 48) != k.ns - 1u) return;
     const unsigned long long tot1 = k.old1 + k.mine1;
     atomicExch(k.w1, 0ull);
     const uint32_t vs = (uint32_t)(tot1 & 0xffffffull);
     const uint32_t bs = (uint32_t)((tot1 >> 24) & 0xffffffull);
-    const uint32_t nactive = k.nparts < kSlots ? k.nparts : kSlots;
-    unsigned long long *w2 = stats_word(k.work, kSlots);
     const unsigned long long mine2 =
         (unsigned long long)vs | ((unsigned long long)bs << 29) | (1ull << 58);
-    const unsigned long long old2 = atomicAdd(w2, mine2);
-    if ((uint32_t)(old2 >> 58) != nactive - 1u) return;
-    const unsigned long long tot2 = old2 + mine2;
-    atomicExch(w2, 0ull);
-    const uint32_t vt = (uint32_t)(tot2 & ((1ull << 29) - 1));
-    const uint32_t bt = (uint32_t)((tot2 >> 29) & ((1ull << 29) - 1));
-    put_counts(k.out, vt, bt, k.npix, k.overwrite);
+    root_arrival(k, atomicAdd(stats_word(k.work, kSlots), mine2), mine2);
 }
 
 __device__ __forceinline__ void reduce_counts(WorkArea *work, bn_frame_stats *out,

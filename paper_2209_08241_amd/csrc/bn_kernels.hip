@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kBlock) void k_scalar(FrameArgs f) {
     const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
     uint32_t cv = 0, cb = 0;
     run_tile<A, M>(f, false, blk, lds, cv, cb);
-    if (f.stats) block_counts(f, blk, gridDim.x, cv, cb);
+    if (f.stats) block_counts(f, blockIdx.x, gridDim.x, cv, cb);
 }
 
 // Vector kernel: four consecutive pixels of a row per thread, G tiles of
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
     const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
     uint32_t cv = 0, cb = 0;
     if (G == 1) {
-        vec4_tile_counted<A, M>(f, blk, blk, gridDim.x, lds);
+        vec4_tile_counted<A, M>(f, blk, blockIdx.x, gridDim.x, lds);
         return;
     }
 #pragma unroll
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_vec4(FrameArgs f) {
         if (tile * kBlock >= f.nitems) break;  // uniform over the workgroup
         run_tile<A, M>(f, true, tile, lds, cv, cb);
     }
-    if (f.stats) block_counts(f, blk, gridDim.x, cv, cb);
+    if (f.stats) block_counts(f, blockIdx.x, gridDim.x, cv, cb);
 }
 
 // Vector kernel, two tiles per workgroup, software-pipelined (the second
@@ -61,7 +61,7 @@ template <int A, int M>
 __global__ __launch_bounds__(kBlock) void k_vec4p(FrameArgs f) {
     __shared__ TileLds lds;
     const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
-    vec4_tile_pair_counted<A, M>(f, 2 * blk, 2 * blk + 1, blk, gridDim.x, lds);
+    vec4_tile_pair_counted<A, M>(f, 2 * blk, 2 * blk + 1, blockIdx.x, gridDim.x, lds);
 }
 
 // Vector kernel with workgroups of TB = 64 or 128 threads (tiles of 256 or
@@ -71,7 +71,7 @@ template <int A, int M, int TB>
 __global__ __launch_bounds__(TB) void k_vec4w(FrameArgs f) {
     __shared__ TileLdsT<TB> lds;
     const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
-    vec4_tile_counted<A, M, TB>(f, blk, blk, gridDim.x, lds);
+    vec4_tile_counted<A, M, TB>(f, blk, blockIdx.x, gridDim.x, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -309,7 +309,7 @@ def rings(reps: int = 64, calibration_mib: int = 1024) -> None:
         torch.cuda.synchronize()
     del d, nm, mk, st
     d, nm, mk, st = ring_of(f640, 256)
-    for v in (0, 1, 3, 4, 5, 6, 7):
+    for v in (0, 2, 3, 4, 5, 6, 7):
         print(f"640x480 four_pair alpha 2 {names.get(v, 'default')}", flush=True)
         for r in range(max(reps, 256)):
             j = r % 256
