@@ -57,6 +57,24 @@ def test_every_alpha(f640, alpha):
     check_frame(s.depth, *s.intrinsics, alpha, "rel", 3.0, 0, what=f"alpha={alpha}")
 
 
+
+def test_count_parts_around_the_direct_root():
+    """The count reduction sends the last 31 parts of a frame (in dispatch
+    order) straight to the root word and the others through 32 slot words:
+    frames whose part counts sit on either side of those boundaries (1, 31,
+    32, 33, 62, 63, 64 and 95 tiles of 1024 pixels, and so 4 times as many
+    scalar parts) give the oracle's counts in every tile shape."""
+    rng = np.random.default_rng(11)
+    for H in (1, 31, 32, 33, 62, 63, 64, 95):
+        W = 1024
+        d = (1.0 + 0.01 * np.arange(W, dtype=np.float32)[None, :]
+             + 0.05 * rng.standard_normal((H, W)).astype(np.float32)).astype(np.float32)
+        d[rng.random((H, W)) < 0.03] = 0.0
+        for variant in [0] + ALL_VARIANTS:
+            log(f"count parts: {H}x{W} v={variant}")
+            check_frame(d, 800.0, 800.0, 511.5, H / 2.0, 1, "rel", 2.0, variant,
+                        what=f"parts {H}x{W} v={variant}")
+
 @pytest.mark.parametrize("W", [1, 2, 3, 4, 5, 7, 8, 9, 12, 13, 17, 31, 33, 64, 65, 127, 129,
                                255, 257, 1023, 1025, 1028])
 @pytest.mark.parametrize("H", [1, 2, 3, 5, 17, 33])
