@@ -4,10 +4,11 @@
 // its probe test call them through the library's exported symbols.  Device
 // pointers, asynchronous on `stream`, nothing allocated.
 //   bn_stream_copy: bytes (a multiple of 16, 16-byte aligned buffers) from
-//     src to dst with 16-byte non-temporal loads and stores.
+//     src to dst with 16-byte non-temporal loads and the estimator's
+//     streaming device-scope stores.
 //   bn_stream_pattern: the estimator's traffic without its arithmetic: reads
 //     4 B of depth and writes 12 B of normals and 1 B of code per pixel
-//     through the same LDS staging; pixels a multiple of 1024, depth and
+//     through the same LDS staging and stores; pixels a multiple of 1024, depth and
 //     normals 16-byte and mask 4-byte aligned.  Output values are
 //     meaningless.
 //   bn_alu_probe: the vector ALUs' issue rate for unpacked binary32
