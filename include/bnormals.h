@@ -61,12 +61,14 @@
  * Pair removal, per pair p in Eq. 7's order (h, v) = (2,3), (4,3), (4,5),
  * (2,5), with directions (sh, sv) = (+,+), (-,+), (-,-), (+,-):
  *     eh=dh-d1  ev=dv-d1  A=eh*dv  B=dh*ev  (negated where sh, sv is -)
- *     C=dh*dv   then mx, my, t3, w, mz, q as above with a=A, b=B, c=C
- *   (m_p = -(fx fy / alpha) n_p).  Any pair's q not a finite number >=
- *   FLT_MIN: INVALID.  REL fires for the pair iff q > (tau*tau)*(w*w); ABS
- *   iff q > (float)(((fx*fy)*tau)/alpha)^2 (double), i.e. |n_p| > tau.  The
+ *     C=dh*dv   mx=fx*A  my=fy*B  w=alpha*C
+ *     mz=fma(xc, A, fma(yc, B, w))   q=fma(mx, mx, fma(my, my, mz*mz))
+ *   (m_p = -(fx fy / alpha) n_p; each fma is one IEEE fused multiply-add,
+ *   rounded once).  Any pair's q not a finite number >= FLT_MIN: INVALID.
+ *   REL fires for the pair iff q > (tau*tau)*(w*w); ABS iff
+ *   q > (float)(((fx*fy)*tau)/alpha)^2 (double), i.e. |n_p| > tau.  The
  *   passing pairs' mx, my, mz are summed in pair order from +0 (sx, sy,
- *   sz); Q=((sx*sx)+(sy*sy))+(sz*sz) not a finite number >= FLT_MIN:
+ *   sz); Q=fma(sx, sx, fma(sy, sy, sz*sz)) not a finite number >= FLT_MIN:
  *   INVALID.  Normal (sx, sy, -sz)/sqrt(Q).  When all four pairs pass, the
  *   sum is the four-pair m (Eq. 7) and is taken in its closed form instead:
  *   (sx, sy, sz, Q) = (mx, my, mz, q) of the four-pair sequence, in which

@@ -544,7 +544,10 @@ int bno_normals_vjp_f64(const double *depth, int H, int W, int64_t stride,
  *   for the others follows from the same expansion of the cross product.
  *   m_jk . ray = -alpha C, so REL compares |m_jk|^2 with tau^2 (alpha C)^2,
  *   and ABS compares it with (fx fy tau / alpha)^2.  The four m_jk sum to
- *   the m of method 0.
+ *   the m of method 0.  Method 1 takes the third component and each squared
+ *   length with fused multiply-adds, every step rounded once (fp32_pair_fma
+ *   below); method 2 keeps the separately rounded products and sums of
+ *   fp32_pair.
  *   MULTISCALE sums alpha_i m(alpha_i), which is -K fx fy times the average
  *   of Eqs. 4-6; REL compares with tau^2 (sum alpha_i^2 C_i)^2 and ABS with
  *   (K fx fy tau)^2.
@@ -619,6 +622,32 @@ static void fp32_pair(float dh, float dv, float d1, int sh, int sv, float fx, fl
     *q = (x2 + y2) + z2;
 }
 
+/* Method 1's binary32 scaled vector of one pair: the products A, B, C, mx,
+ * my and w as in fp32_pair, then
+ *   mz = fma(xc, A, fma(yc, B, w)),   q = fma(mx, mx, fma(my, my, mz * mz)),
+ * each fma rounded once (C99 fmaf). */
+static void fp32_pair_fma(float dh, float dv, float d1, int sh, int sv, float fx, float fy,
+                          float xc, float yc, float af, float *mx, float *my, float *mz,
+                          float *w, float *q)
+{
+    float eh = dh - d1;
+    float ev = dv - d1;
+    float A = eh * dv;
+    float B = dh * ev;
+    if (sh < 0) A = -A;
+    if (sv < 0) B = -B;
+    float C = dh * dv;
+    float x = fx * A;
+    float y = fy * B;
+    float ww = af * C;
+    float z = fmaf(xc, A, fmaf(yc, B, ww));
+    *mx = x;
+    *my = y;
+    *mz = z;
+    *w = ww;
+    *q = fmaf(x, x, fmaf(y, y, z * z));
+}
+
 static int q_degenerate(float q)
 {
     return !isfinite(q) || q < FLT_MIN;
@@ -650,7 +679,8 @@ static float multiscale_abs_threshold_f32(float fx, float fy, float tau, int sca
  * (4, 3), (4, 5), (2, 5).  A pair whose |m|^2 is not a finite number >=
  * FLT_MIN makes the pixel INVALID; *keep gets bit p for each pair p that
  * passes the test; the passing pairs' scaled vectors are summed in pair
- * order, and a sum whose |.|^2 is degenerate is INVALID too. */
+ * order, and a sum whose |.|^2 (fused as for one pair) is degenerate is
+ * INVALID too. */
 static int fp32_pairs_code(const float d[6], int x, int y, float fx, float fy, float cx,
                            float cy, int alpha, int mode, float tau, float kpair, int *keep)
 {
@@ -664,7 +694,7 @@ static int fp32_pairs_code(const float d[6], int x, int y, float fx, float fy, f
     float mx[4], my[4], mz[4], w[4], q[4];
     *keep = 0;
     for (int p = 0; p < 4; ++p) {
-        fp32_pair(d[th[p]], d[tv[p]], d[1], sh[p], sv[p], fx, fy, xc, yc, af,
+        fp32_pair_fma(d[th[p]], d[tv[p]], d[1], sh[p], sv[p], fx, fy, xc, yc, af,
                   &mx[p], &my[p], &mz[p], &w[p], &q[p]);
         if (q_degenerate(q[p]))
             return ORC_INVALID;
@@ -707,10 +737,7 @@ static int fp32_pairs_code(const float d[6], int x, int y, float fx, float fy, f
             sz = sz + mz[p];
         }
     }
-    float sx2 = sx * sx;
-    float sy2 = sy * sy;
-    float sz2 = sz * sz;
-    float Q = (sx2 + sy2) + sz2;
+    float Q = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
     return q_degenerate(Q) ? ORC_INVALID : ORC_VALID;
 }
 

@@ -146,17 +146,28 @@ __host__ __device__ constexpr int kernel_method(int method, int alpha, int scale
     return method == kMultiScale && alpha * scales > kMsShortReach ? kMultiScaleLong : method;
 }
 
+// A constant placed in a scalar register.  The class tests below take their
+// class mask as a second operand that cannot be a literal in this encoding;
+// left to itself the compiler rebuilds the mask in a vector register before
+// each pixel's tests (one VALU move each), where a scalar register serves
+// them all.
+__device__ __forceinline__ uint32_t sconst(uint32_t v) {
+    uint32_t r;
+    asm("s_mov_b32 %0, %1" : "=s"(r) : "i"(v));
+    return r;
+}
+
 // A finite depth > 0: bit patterns 0x00000001 .. 0x7f7fffff, that is the
 // classes positive subnormal and positive normal (one class test: it reads
 // the bit pattern, whatever the denormal mode).
 __device__ __forceinline__ uint32_t tap_ok(float d) {
-    return __builtin_amdgcn_classf(d, 0x180) ? 1u : 0u;  // +subnormal | +normal
+    return __builtin_amdgcn_classf(d, sconst(0x180)) ? 1u : 0u;  // +subnormal | +normal
 }
 
 // q is a finite number >= FLT_MIN: bit patterns 0x00800000 .. 0x7f7fffff,
 // the class positive normal.
 __device__ __forceinline__ uint32_t q_ok(float q) {
-    return __builtin_amdgcn_classf(q, 0x100) ? 1u : 0u;  // +normal
+    return __builtin_amdgcn_classf(q, sconst(0x100)) ? 1u : 0u;  // +normal
 }
 
 // Row of a flat work item: floor(i / gpr) exactly, for i < 2^28 and
@@ -235,13 +246,17 @@ __device__ __forceinline__ PixelOut eval_pixel(bool inside, float d1, float d2, 
 // with, for horizontal tap h, vertical tap v and their directions sh, sv:
 //   A = sh (d_h - d1) d_v,  B = sv d_h (d_v - d1),  C = d_h d_v
 // (Eqs. 1-3 scaled for the pair (2, 3)).  Each pair is tested like the
-// four-pair vector, with w_p = alpha C; the passing pairs are summed in pair
+// four-pair vector, with w_p = alpha C, its third component and squared
+// length taken with fused multiply-adds; the passing pairs are summed in pair
 // order, each sum starting from +0 (adding +0 for a failing pair changes no
 // bit of the squared length).  When all four pass, the sum is the
 // four-pair m, taken in its closed form (d1 cancels exactly there, while the
 // rounded sum of the pairs can lose it to cancellation).
 // ---------------------------------------------------------------------------
-// The binary32 vector of one pair and its test, in the order written above.
+// The binary32 vector of one pair and its test:
+//   mx = fx A, my = fy B, w = alpha C,
+//   mz = fma(xc, A, fma(yc, B, w)),  q = fma(mx, mx, fma(my, my, mz mz)),
+// each fused multiply-add rounded once.
 // keep: the pair passes; ok: its q is a finite number >= FLT_MIN.
 struct PairT {
     float mx, my, mz;
@@ -253,20 +268,14 @@ __device__ __forceinline__ PairT pair_t(float A, float B, float C, float xc, flo
     PairT r;
     r.mx = f.fx * A;
     r.my = f.fy * B;
-    const float xa = xc * A;
-    const float yb = yc * B;
-    const float t3 = xa + yb;
     const float w = f.af * C;
-    r.mz = t3 + w;
-    const float mx2 = r.mx * r.mx;
-    const float my2 = r.my * r.my;
-    const float mz2 = r.mz * r.mz;
-    const float q = (mx2 + my2) + mz2;
+    r.mz = __builtin_fmaf(xc, A, __builtin_fmaf(yc, B, w));
+    const float q = __builtin_fmaf(r.mx, r.mx, __builtin_fmaf(r.my, r.my, r.mz * r.mz));
     const float ww = w * w;
     const float hrel = f.tt * ww;
     const float h = f.rel ? hrel : f.hconst;
     r.keep = !(q > h);
-    r.ok = __builtin_amdgcn_classf(q, 0x100);
+    r.ok = __builtin_amdgcn_classf(q, sconst(0x100));
     return r;
 }
 
@@ -307,7 +316,7 @@ __device__ __forceinline__ ClosedM closed_m(float d2, float d3, float d4, float 
 // one it adds a zero, which leaves every t of the sum unchanged (t is never
 // -0: it starts as k m_0 + (+0)).  A failing pair whose vector is not finite
 // has a q that is not finite either, and then the pixel is INVALID whatever
-// the sum holds.
+// the sum holds.  The sum's squared length is fused as a pair's.
 __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, float d2, float d3,
                                                      float d4, float d5, float xc, float yc,
                                                      const FrameArgs &f) {
@@ -325,7 +334,7 @@ __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, floa
     // all four pass: the four-pair closed form, in which d1 cancels exactly
     const ClosedM c = closed_m(d2, d3, d4, d5, xc, yc, f);
     float sx = c.mx, sy = c.my, sz = c.mz, Q = c.q;
-    if (__any(!all)) {
+    if (__builtin_amdgcn_ballot_w64(!all) != 0) {
         const float k0 = p0.keep ? 1.0f : 0.0f;
         const float k1 = p1.keep ? 1.0f : 0.0f;
         const float k2 = p2.keep ? 1.0f : 0.0f;
@@ -342,10 +351,7 @@ __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, floa
         tx = __builtin_fmaf(k3, p3.mx, tx);
         ty = __builtin_fmaf(k3, p3.my, ty);
         tz = __builtin_fmaf(k3, p3.mz, tz);
-        const float tx2 = tx * tx;
-        const float ty2 = ty * ty;
-        const float tz2 = tz * tz;
-        const float Qs = (tx2 + ty2) + tz2;
+        const float Qs = __builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, tz * tz));
         sx = all ? sx : tx;
         sy = all ? sy : ty;
         sz = all ? sz : tz;
