@@ -70,13 +70,15 @@
  *   passing pairs' mx, my, mz are summed in pair order from +0 (sx, sy,
  *   sz); Q=fma(sx, sx, fma(sy, sy, sz*sz)) not a finite number >= FLT_MIN:
  *   INVALID.  Normal (sx, sy, -sz)/sqrt(Q).  When all four pairs pass, the
- *   sum is the four-pair m (Eq. 7) and is taken in its closed form instead:
- *   (sx, sy, sz, Q) = (mx, my, mz, q) of the four-pair sequence, in which
- *   d1 cancels exactly rather than through rounded sums.
+ *   sum is the four-pair m (Eq. 7) and is taken in its closed form instead,
+ *   in which d1 cancels exactly rather than through rounded sums: (sx, sy)
+ *   = (mx, my) of the four-pair sequence, sz = fma(xc, a, fma(yc, b, w))
+ *   with its a, b, w, and Q as above.
  * Multi-scale: for i = 1..K, a=(float)(i*alpha), taps d2 = (x+i*alpha, y),
  *   d3 = (x, y+i*alpha): e2=d2-d1 e3=d3-d1 A=e2*d3 B=d2*e3 C=d2*d3, then
- *   mx, my, t3, mz as above with w=a*C; Mx+=a*mx  My+=a*my  Mz+=a*mz
- *   Wt+=a*w (from +0, in scale order); q=((Mx*Mx)+(My*My))+(Mz*Mz).  REL
+ *   mx, my, w=a*C and mz as for one pair of pair removal; Mx=fma(a, mx, Mx)
+ *   and likewise My, Mz, Wt with my, mz, w (from +0, in scale order);
+ *   q=fma(Mx, Mx, fma(My, My, Mz*Mz)).  REL
  *   fires iff q > (tau*tau)*(Wt*Wt); ABS iff q > (float)((((K*fx)*fy)*tau)^2)
  *   (double), i.e. |average of Eqs. 4-6| > tau.  Normal (Mx, My, -Mz)/sqrt(q).
  *

@@ -544,10 +544,10 @@ int bno_normals_vjp_f64(const double *depth, int H, int W, int64_t stride,
  *   for the others follows from the same expansion of the cross product.
  *   m_jk . ray = -alpha C, so REL compares |m_jk|^2 with tau^2 (alpha C)^2,
  *   and ABS compares it with (fx fy tau / alpha)^2.  The four m_jk sum to
- *   the m of method 0.  Method 1 takes the third component and each squared
- *   length with fused multiply-adds, every step rounded once (fp32_pair_fma
- *   below); method 2 keeps the separately rounded products and sums of
- *   fp32_pair.
+ *   the m of method 0.  Methods 1 and 2 take the third component, the
+ *   weighted sums and each squared length with fused multiply-adds, every
+ *   step rounded once (fp32_pair_fma below); method 0 keeps the separately
+ *   rounded products and sums of its pinned sequence.
  *   MULTISCALE sums alpha_i m(alpha_i), which is -K fx fy times the average
  *   of Eqs. 4-6; REL compares with tau^2 (sum alpha_i^2 C_i)^2 and ABS with
  *   (K fx fy tau)^2.
@@ -592,40 +592,11 @@ static void single_pair_closed_form(double d1, double d2, double d3, double u1, 
            + a * a / (fx * fy) * d2 * d3;                               /* Eq. 3 */
 }
 
-/* Binary32 scaled vector of one pair, in a fixed operation order; mz holds
- * the negated third component, w = alpha C. */
-static void fp32_pair(float dh, float dv, float d1, int sh, int sv, float fx, float fy,
-                      float xc, float yc, float af, float *mx, float *my, float *mz,
-                      float *w, float *q)
-{
-    float eh = dh - d1;
-    float ev = dv - d1;
-    float A = eh * dv;
-    float B = dh * ev;
-    if (sh < 0) A = -A;
-    if (sv < 0) B = -B;
-    float C = dh * dv;
-    float x = fx * A;
-    float y = fy * B;
-    float xa = xc * A;
-    float yb = yc * B;
-    float t3 = xa + yb;
-    float ww = af * C;
-    float z = t3 + ww;
-    float x2 = x * x;
-    float y2 = y * y;
-    float z2 = z * z;
-    *mx = x;
-    *my = y;
-    *mz = z;
-    *w = ww;
-    *q = (x2 + y2) + z2;
-}
-
-/* Method 1's binary32 scaled vector of one pair: the products A, B, C, mx,
- * my and w as in fp32_pair, then
- *   mz = fma(xc, A, fma(yc, B, w)),   q = fma(mx, mx, fma(my, my, mz * mz)),
- * each fma rounded once (C99 fmaf). */
+/* Binary32 scaled vector of one pair (methods 1 and 2): the products
+ *   A = sh (dh - d1) dv,  B = sv dh (dv - d1),  C = dh dv,
+ *   mx = fx A,  my = fy B,  w = alpha C,
+ * then mz = fma(xc, A, fma(yc, B, w)) (the negated third component) and
+ * q = fma(mx, mx, fma(my, my, mz * mz)), each fma rounded once (C99 fmaf). */
 static void fp32_pair_fma(float dh, float dv, float d1, int sh, int sv, float fx, float fy,
                           float xc, float yc, float af, float *mx, float *my, float *mz,
                           float *w, float *q)
@@ -716,11 +687,23 @@ static int fp32_pairs_code(const float d[6], int x, int y, float fx, float fy, f
     if (!k)
         return ORC_BOUNDARY;
     /* All four pass: their average is Eq. 7's n, taken in its closed form
-     * (Eqs. 10-12, the four-pair sequence above), in which d1 cancels
-     * exactly instead of through rounded sums. */
-    if (k == 15)
-        return fp32_code(d[2], d[3], d[4], d[5], x, y, fx, fy, cx, cy, alpha, ORC_NONE, tau,
-                         0.0f);
+     * (Eqs. 10-12), in which d1 cancels exactly instead of through rounded
+     * sums; its third component and squared length fused as for one pair. */
+    if (k == 15) {
+        float P = d[2] - d[4];
+        float S = d[2] + d[4];
+        float Qv = d[3] - d[5];
+        float T = d[3] + d[5];
+        float a = T * P;
+        float b = S * Qv;
+        float c = S * T;
+        float cx_ = fx * a;
+        float cy_ = fy * b;
+        float cw = af * c;
+        float cz = fmaf(xc, a, fmaf(yc, b, cw));
+        float Qc = fmaf(cx_, cx_, fmaf(cy_, cy_, cz * cz));
+        return q_degenerate(Qc) ? ORC_INVALID : ORC_VALID;
+    }
     int first = 1;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     for (int p = 0; p < 4; ++p) {
@@ -742,7 +725,8 @@ static int fp32_pairs_code(const float d[6], int x, int y, float fx, float fy, f
 }
 
 /* Method 2 binary32 decision: scales i = 1..K at offset a = i*alpha, the
- * pair (2, 3) vector of each weighted by a and summed in scale order. */
+ * pair (2, 3) vector of each (fp32_pair_fma) weighted by a and summed in
+ * scale order with fused multiply-adds; |M|^2 fused as for one pair. */
 static int fp32_multiscale_code(float d1, const float *d2s, const float *d3s, int scales, int x,
                                 int y, float fx, float fy, float cx, float cy, int alpha, int mode,
                                 float tau, float kms)
@@ -753,27 +737,21 @@ static int fp32_multiscale_code(float d1, const float *d2s, const float *d3s, in
     for (int i = 1; i <= scales; ++i) {
         float a = (float)(i * alpha);
         float mx, my, mz, w, q;
-        fp32_pair(d2s[i - 1], d3s[i - 1], d1, 1, 1, fx, fy, xc, yc, a, &mx, &my, &mz, &w, &q);
-        float ax = a * mx;
-        float ay = a * my;
-        float az = a * mz;
-        float aw = a * w;
+        fp32_pair_fma(d2s[i - 1], d3s[i - 1], d1, 1, 1, fx, fy, xc, yc, a, &mx, &my, &mz, &w,
+                      &q);
         if (i == 1) {
-            Mx = ax;
-            My = ay;
-            Mz = az;
-            Wt = aw;
+            Mx = a * mx;
+            My = a * my;
+            Mz = a * mz;
+            Wt = a * w;
         } else {
-            Mx = Mx + ax;
-            My = My + ay;
-            Mz = Mz + az;
-            Wt = Wt + aw;
+            Mx = fmaf(a, mx, Mx);
+            My = fmaf(a, my, My);
+            Mz = fmaf(a, mz, Mz);
+            Wt = fmaf(a, w, Wt);
         }
     }
-    float x2 = Mx * Mx;
-    float y2 = My * My;
-    float z2 = Mz * Mz;
-    float q = (x2 + y2) + z2;
+    float q = fmaf(Mx, Mx, fmaf(My, My, Mz * Mz));
     if (q_degenerate(q))
         return ORC_INVALID;
     if (mode == ORC_NONE)

@@ -279,9 +279,11 @@ __device__ __forceinline__ PairT pair_t(float A, float B, float C, float xc, flo
     return r;
 }
 
-// The four-pair closed form m and q (the sequence of eval_terms, no test).
+// The four-pair closed form m (Eqs. 10-12) as pair removal takes it when all
+// four pairs pass: the products of eval_terms, the third component fused as
+// for one pair.
 struct ClosedM {
-    float mx, my, mz, q;
+    float mx, my, mz;
 };
 
 __device__ __forceinline__ ClosedM closed_m(float d2, float d3, float d4, float d5, float xc,
@@ -296,15 +298,8 @@ __device__ __forceinline__ ClosedM closed_m(float d2, float d3, float d4, float 
     ClosedM r;
     r.mx = f.fx * a;
     r.my = f.fy * b;
-    const float xa = xc * a;
-    const float yb = yc * b;
-    const float t3 = xa + yb;
     const float w = f.af * c;
-    r.mz = t3 + w;
-    const float mx2 = r.mx * r.mx;
-    const float my2 = r.my * r.my;
-    const float mz2 = r.mz * r.mz;
-    r.q = (mx2 + my2) + mz2;
+    r.mz = __builtin_fmaf(xc, a, __builtin_fmaf(yc, b, w));
     return r;
 }
 
@@ -316,7 +311,8 @@ __device__ __forceinline__ ClosedM closed_m(float d2, float d3, float d4, float 
 // one it adds a zero, which leaves every t of the sum unchanged (t is never
 // -0: it starts as k m_0 + (+0)).  A failing pair whose vector is not finite
 // has a q that is not finite either, and then the pixel is INVALID whatever
-// the sum holds.  The sum's squared length is fused as a pair's.
+// the sum holds.  The squared length of the closed form or of the sum,
+// whichever the pixel takes, is fused as a pair's.
 __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, float d2, float d3,
                                                      float d4, float d5, float xc, float yc,
                                                      const FrameArgs &f) {
@@ -333,7 +329,7 @@ __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, floa
     const bool any = p0.keep || p1.keep || p2.keep || p3.keep;
     // all four pass: the four-pair closed form, in which d1 cancels exactly
     const ClosedM c = closed_m(d2, d3, d4, d5, xc, yc, f);
-    float sx = c.mx, sy = c.my, sz = c.mz, Q = c.q;
+    float sx = c.mx, sy = c.my, sz = c.mz;
     if (__builtin_amdgcn_ballot_w64(!all) != 0) {
         const float k0 = p0.keep ? 1.0f : 0.0f;
         const float k1 = p1.keep ? 1.0f : 0.0f;
@@ -351,12 +347,11 @@ __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, floa
         tx = __builtin_fmaf(k3, p3.mx, tx);
         ty = __builtin_fmaf(k3, p3.my, ty);
         tz = __builtin_fmaf(k3, p3.mz, tz);
-        const float Qs = __builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, tz * tz));
         sx = all ? sx : tx;
         sy = all ? sy : ty;
         sz = all ? sz : tz;
-        Q = all ? Q : Qs;
     }
+    const float Q = __builtin_fmaf(sx, sx, __builtin_fmaf(sy, sy, sz * sz));
     const bool ok = inside && (tap_ok(d1) & tap_ok(d2) & tap_ok(d3) & tap_ok(d4) & tap_ok(d5)) &&
                     p0.ok && p1.ok && p2.ok && p3.ok;
     PixelOut o;
@@ -389,7 +384,8 @@ __device__ __forceinline__ PixelOut eval_method(bool inside, float d1, float d2,
 // read: inside means x + K alpha < W and y + K alpha < H.
 // ---------------------------------------------------------------------------
 // One scale: the pair (2, 3) vector at offset a (taps d2 = (x+a, y),
-// d3 = (x, y+a)), weighted by a and added to the running sums.
+// d3 = (x, y+a)), its third component fused as in pair removal, weighted by
+// a and added to the running sums with fused multiply-adds.
 __device__ __forceinline__ void ms_accumulate(float d1, float d2, float d3, float a, float xc,
                                               float yc, const FrameArgs &f, float &Mx, float &My,
                                               float &Mz, float &Wt) {
@@ -400,23 +396,17 @@ __device__ __forceinline__ void ms_accumulate(float d1, float d2, float d3, floa
     const float C = d2 * d3;
     const float mx = f.fx * A;
     const float my = f.fy * B;
-    const float xa = xc * A;
-    const float yb = yc * B;
-    const float t3 = xa + yb;
     const float w = a * C;
-    const float mz = t3 + w;
-    Mx = Mx + a * mx;
-    My = My + a * my;
-    Mz = Mz + a * mz;
-    Wt = Wt + a * w;
+    const float mz = __builtin_fmaf(xc, A, __builtin_fmaf(yc, B, w));
+    Mx = __builtin_fmaf(a, mx, Mx);
+    My = __builtin_fmaf(a, my, My);
+    Mz = __builtin_fmaf(a, mz, Mz);
+    Wt = __builtin_fmaf(a, w, Wt);
 }
 
 __device__ __forceinline__ PixelOut ms_finish(uint32_t ok, float Mx, float My, float Mz, float Wt,
                                               const FrameArgs &f) {
-    const float x2 = Mx * Mx;
-    const float y2 = My * My;
-    const float z2 = Mz * Mz;
-    const float q = (x2 + y2) + z2;
+    const float q = __builtin_fmaf(Mx, Mx, __builtin_fmaf(My, My, Mz * Mz));
     const float ww = Wt * Wt;
     const float hrel = f.tt * ww;
     const float h = f.rel ? hrel : f.hconst;

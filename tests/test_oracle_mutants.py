@@ -53,10 +53,12 @@ MUTANTS = {
                                      "static const int PAIR_K[4] = {3, 2, 5, 4};")],
     # multi-scale
     "ms_same_offset_every_scale": [("float a = (float)(i * alpha);", "float a = (float)alpha;")],
-    "ms_unweighted_scales": [("float ax = a * mx;", "float ax = mx;"),
-                             ("float ay = a * my;", "float ay = my;"),
-                             ("float az = a * mz;", "float az = mz;"),
-                             ("float aw = a * w;", "float aw = w;")],
+    "ms_unweighted_scales": [("Mx = a * mx;", "Mx = mx;"), ("My = a * my;", "My = my;"),
+                             ("Mz = a * mz;", "Mz = mz;"), ("Wt = a * w;", "Wt = w;"),
+                             ("Mx = fmaf(a, mx, Mx);", "Mx = Mx + mx;"),
+                             ("My = fmaf(a, my, My);", "My = My + my;"),
+                             ("Mz = fmaf(a, mz, Mz);", "Mz = Mz + mz;"),
+                             ("Wt = fmaf(a, w, Wt);", "Wt = Wt + w;")],
     "ms_abs_without_K": [("    double k = (double)scales;\n    k = k * (double)fx;",
                           "    double k = 1.0;\n    k = k * (double)fx;")],
     "ms_border_both_sides": [("int inside = (x + reach <= W - 1) && (y + reach <= H - 1);",
