@@ -44,7 +44,11 @@
 
 namespace bn {
 
-// Tap gradients of one pixel (meaningful when its code is VALID).
+// Tap gradients of one pixel (meaningful when its code is VALID).  The
+// gradient is not part of the pinned mask sequence (the code comes from
+// eval_terms, unfused), so its products and sums are fused where a product
+// feeds a sum; every kernel here calls this one function, so all of them
+// still give the same bits.
 struct TapGrads {
     float g2, g3, g4, g5;
 };
@@ -53,17 +57,17 @@ __device__ __forceinline__ TapGrads tap_grads(const PixelTerms &t, float gx, flo
                                               float xc, float yc, const FrameArgs &f) {
     const float inv = __builtin_amdgcn_rsqf(t.q);
     const float nx = t.mx * inv, ny = t.my * inv, nz = -(t.mz * inv);
-    const float dot = (nx * gx + ny * gy) + nz * gz;
-    const float ox = (gx - dot * nx) * inv;
-    const float oy = (gy - dot * ny) * inv;
-    const float oz = (gz - dot * nz) * inv;
-    const float u = f.fx * ox - xc * oz;
-    const float v = f.fy * oy - yc * oz;
+    const float dot = __builtin_fmaf(nz, gz, __builtin_fmaf(ny, gy, nx * gx));
+    const float ox = __builtin_fmaf(-dot, nx, gx) * inv;
+    const float oy = __builtin_fmaf(-dot, ny, gy) * inv;
+    const float oz = __builtin_fmaf(-dot, nz, gz) * inv;
+    const float u = __builtin_fmaf(f.fx, ox, -(xc * oz));
+    const float v = __builtin_fmaf(f.fy, oy, -(yc * oz));
     const float z = f.af * oz;
     const float dP = t.T * u;
     const float dQ = t.S * v;
-    const float dS = t.Q * v - t.T * z;
-    const float dT = t.P * u - t.S * z;
+    const float dS = __builtin_fmaf(t.Q, v, -(t.T * z));
+    const float dT = __builtin_fmaf(t.P, u, -(t.S * z));
     return TapGrads{dP + dS, dQ + dT, dS - dP, dT - dQ};
 }
 
