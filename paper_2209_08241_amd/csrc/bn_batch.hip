@@ -185,9 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_small(const SmallBatch s) {
         vec4_tile_counted<A, M>(f, tile, tile, nparts, lds);
         return;
     }
-    uint32_t cv = 0, cb = 0;
-    run_tile<A, M>(f, false, tile, lds, cv, cb);
-    if (f.stats) block_counts(f, tile, nparts, cv, cb);
+    scalar_tile_counted<A, M>(f, tile, tile, nparts, lds);
 }
 
 typedef void (*BatchKernelFn)(const BatchFrame *, const uint32_t *, uint32_t *, uint32_t,

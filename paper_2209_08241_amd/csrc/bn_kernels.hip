@@ -28,9 +28,7 @@ template <int A, int M>
 __global__ __launch_bounds__(kBlock) void k_scalar(FrameArgs f) {
     __shared__ TileLds lds;
     const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
-    uint32_t cv = 0, cb = 0;
-    run_tile<A, M>(f, false, blk, lds, cv, cb);
-    if (f.stats) block_counts(f, blockIdx.x, gridDim.x, cv, cb);
+    scalar_tile_counted<A, M>(f, blk, blockIdx.x, gridDim.x, lds);
 }
 
 // Vector kernel: four consecutive pixels of a row per thread, G tiles of

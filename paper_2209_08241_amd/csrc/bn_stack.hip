@@ -29,9 +29,7 @@ __global__ __launch_bounds__(kBlock) void k_stack(const StackArgs s) {
         vec4_tile_counted<A, M>(f, tile, tile, s.tiles_per_frame, lds);
         return;
     }
-    uint32_t cv = 0, cb = 0;
-    run_tile<A, M>(f, false, tile, lds, cv, cb);
-    if (f.stats) block_counts(f, tile, s.tiles_per_frame, cv, cb);
+    scalar_tile_counted<A, M>(f, tile, tile, s.tiles_per_frame, lds);
 }
 
 typedef void (*StackFn)(const StackArgs);

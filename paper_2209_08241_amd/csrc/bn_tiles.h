@@ -298,8 +298,13 @@ __device__ __forceinline__ void vec4_write(const FrameArgs &f, uint32_t tile, Ti
     const float *nv = o.nv;
     const uint32_t w = wave_id();
     const uint32_t g0 = tile * TB + 64 * w;  // first work item of this wavefront
+    // A wavefront past the frame's end has a resource of size 0, which
+    // drops every store.  The stores are unconditional, so a count ticket
+    // issued before them is waited for by its own position in the counter
+    // (loads, stores and atomics complete in issue order), not by a wait for
+    // all of them.
     const uint32_t ng = g0 < f.nitems ? min(64u, f.nitems - g0) : 0u;
-    if (ng) {
+    {
         const OutBuf mb = out_buf(reinterpret_cast<uint32_t *>(f.mask) + g0, 4 * ng);
         out_store(o.codes, mb, 4 * lane);
     }
@@ -311,7 +316,7 @@ __device__ __forceinline__ void vec4_write(const FrameArgs &f, uint32_t tile, Ti
         slice[3 * lane + 2] = f4{nv[8], nv[9], nv[10], nv[11]};
     }
     wave_lds_sync();
-    if (ng) {
+    {
         const OutBuf nb = out_buf(reinterpret_cast<f4 *>(f.normals) + 3 * (int64_t)g0, 48 * ng);
 #pragma unroll
         for (int k = 0; k < 3; ++k) out_store(slice[64 * k + lane], nb, 16 * lane + 1024 * k);
@@ -392,8 +397,9 @@ __device__ __forceinline__ void scalar_write(const FrameArgs &f, uint32_t tile, 
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = wave_id();
     const uint32_t p0 = tile * kBlock + 64 * w;  // first pixel of this wavefront
+    // unconditional stores, as in vec4_write (size 0 past the frame's end)
     const uint32_t np = p0 < f.nitems ? min(64u, f.nitems - p0) : 0u;
-    if (np) out_store_byte((uint8_t)r.code, out_buf(f.mask + p0, np), lane);
+    out_store_byte((uint8_t)r.code, out_buf(f.mask + p0, np), lane);
     const float nx = r.nx, ny = r.ny, nz = r.nz;
     // wavefront-local transpose through this wavefront's LDS slice
     float *slice = s + 192 * w;
@@ -402,11 +408,9 @@ __device__ __forceinline__ void scalar_write(const FrameArgs &f, uint32_t tile, 
     slice[3 * lane + 1] = ny;
     slice[3 * lane + 2] = nz;
     wave_lds_sync();
-    if (np) {
-        const OutBuf nb = out_buf(f.normals + 3 * (int64_t)p0, 12 * np);
+    const OutBuf nb = out_buf(f.normals + 3 * (int64_t)p0, 12 * np);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) out_store(slice[64 * k + lane], nb, 4 * lane + 256 * k);
-    }
+    for (int k = 0; k < 3; ++k) out_store(slice[64 * k + lane], nb, 4 * lane + 256 * k);
 }
 
 __device__ __forceinline__ void scalar_count(const ScalarOut &r, uint32_t &cv, uint32_t &cb) {
@@ -460,6 +464,29 @@ __device__ __forceinline__ void vec4_tile_counted(const FrameArgs &f, uint32_t t
         }
     }
     vec4_write<M, TB>(f, tile, lds, o);
+    if (have) count_finish(tk);
+}
+
+// One scalar tile with its counts, as part `part` of `nparts` of the frame:
+// as in vec4_tile_counted, the count atomic goes out before the stores.
+template <int A, int M>
+__device__ __forceinline__ void scalar_tile_counted(const FrameArgs &f, uint32_t tile,
+                                                    uint32_t part, uint32_t nparts,
+                                                    TileLds &lds) {
+    ScalarOut r;
+    scalar_eval<A, M>(f, tile, r);
+    CountTicket tk;
+    bool have = false;
+    if (f.stats) {
+        uint32_t cv = 0, cb = 0, v, b;
+        scalar_count(r, cv, cb);
+        block_sum(cv, cb, v, b);
+        if (threadIdx.x == 0) {
+            tk = count_issue(f.work, f.stats, part, nparts, v, b, f.npix, f.overwrite);
+            have = true;
+        }
+    }
+    scalar_write(f, tile, lds, r);
     if (have) count_finish(tk);
 }
 
