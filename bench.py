@@ -46,7 +46,7 @@ def alu_ops_per_pixel(method: str, scales: int = 0) -> int:
         return 34
     if method == "pair_removal":
         return 95
-    return 22 * scales + 16   # multiscale: 22 per scale, 16 for the rest
+    return 16 * scales + 14   # multiscale: 16 per scale, 14 for the rest
 KERNEL_SOURCES = ["bn_device.h", "bn_tiles.h", "bn_kernels.hip", "bn_batch.hip"]
 ADJOINT_SOURCES = ["bn_device.h", "bn_adjoint.hip", "bn_stack.hip"]
 
