@@ -61,11 +61,11 @@
  * Pair removal, per pair p in Eq. 7's order (h, v) = (2,3), (4,3), (4,5),
  * (2,5), with directions (sh, sv) = (+,+), (-,+), (-,-), (+,-):
  *     eh=dh-d1  ev=dv-d1  A=eh*dv  B=dh*ev  (negated where sh, sv is -)
- *     C=dh*dv   mx=fx*A  my=fy*B  w=alpha*C
+ *     w=((float)alpha*dh)*dv   mx=fx*A  my=fy*B
  *     mz=fma(xc, A, fma(yc, B, w))   q=fma(mx, mx, fma(my, my, mz*mz))
  *   (m_p = -(fx fy / alpha) n_p; each fma is one IEEE fused multiply-add,
  *   rounded once).  Any pair's q not a finite number >= FLT_MIN: INVALID.
- *   REL fires for the pair iff q > (tau*tau)*(w*w); ABS iff
+ *   REL fires for the pair iff q > ((tau*tau)*w)*w; ABS iff
  *   q > (float)(((fx*fy)*tau)/alpha)^2 (double), i.e. |n_p| > tau.  The
  *   passing pairs' mx, my, mz are summed in pair order from +0 (sx, sy,
  *   sz); Q=fma(sx, sx, fma(sy, sy, sz*sz)) not a finite number >= FLT_MIN:

@@ -592,14 +592,15 @@ static void single_pair_closed_form(double d1, double d2, double d3, double u1, 
            + a * a / (fx * fy) * d2 * d3;                               /* Eq. 3 */
 }
 
-/* Binary32 scaled vector of one pair (methods 1 and 2): the products
- *   A = sh (dh - d1) dv,  B = sv dh (dv - d1),  C = dh dv,
- *   mx = fx A,  my = fy B,  w = alpha C,
+/* Binary32 scaled vector of one pair (methods 1 and 2), given its
+ * w = alpha dh dv (each method rounds that product in its own order): the
+ * products
+ *   A = sh (dh - d1) dv,  B = sv dh (dv - d1),  mx = fx A,  my = fy B,
  * then mz = fma(xc, A, fma(yc, B, w)) (the negated third component) and
  * q = fma(mx, mx, fma(my, my, mz * mz)), each fma rounded once (C99 fmaf). */
 static void fp32_pair_fma(float dh, float dv, float d1, int sh, int sv, float fx, float fy,
-                          float xc, float yc, float af, float *mx, float *my, float *mz,
-                          float *w, float *q)
+                          float xc, float yc, float w, float *mx, float *my, float *mz,
+                          float *q)
 {
     float eh = dh - d1;
     float ev = dv - d1;
@@ -607,15 +608,12 @@ static void fp32_pair_fma(float dh, float dv, float d1, int sh, int sv, float fx
     float B = dh * ev;
     if (sh < 0) A = -A;
     if (sv < 0) B = -B;
-    float C = dh * dv;
     float x = fx * A;
     float y = fy * B;
-    float ww = af * C;
-    float z = fmaf(xc, A, fmaf(yc, B, ww));
+    float z = fmaf(xc, A, fmaf(yc, B, w));
     *mx = x;
     *my = y;
     *mz = z;
-    *w = ww;
     *q = fmaf(x, x, fmaf(y, y, z * z));
 }
 
@@ -649,9 +647,9 @@ static float multiscale_abs_threshold_f32(float fx, float fy, float tau, int sca
 /* Method 1 binary32 decision.  Pairs in Eq. 7's order: (h, v) = (2, 3),
  * (4, 3), (4, 5), (2, 5).  A pair whose |m|^2 is not a finite number >=
  * FLT_MIN makes the pixel INVALID; *keep gets bit p for each pair p that
- * passes the test; the passing pairs' scaled vectors are summed in pair
- * order, and a sum whose |.|^2 (fused as for one pair) is degenerate is
- * INVALID too. */
+ * passes the test (REL: q > (tau^2 w) w, each product rounded); the passing
+ * pairs' scaled vectors are summed in pair order, and a sum whose |.|^2
+ * (fused as for one pair) is degenerate is INVALID too. */
 static int fp32_pairs_code(const float d[6], int x, int y, float fx, float fy, float cx,
                            float cy, int alpha, int mode, float tau, float kpair, int *keep)
 {
@@ -665,8 +663,10 @@ static int fp32_pairs_code(const float d[6], int x, int y, float fx, float fy, f
     float mx[4], my[4], mz[4], w[4], q[4];
     *keep = 0;
     for (int p = 0; p < 4; ++p) {
-        fp32_pair_fma(d[th[p]], d[tv[p]], d[1], sh[p], sv[p], fx, fy, xc, yc, af,
-                  &mx[p], &my[p], &mz[p], &w[p], &q[p]);
+        /* w = (alpha dh) dv: alpha times the horizontal tap first */
+        w[p] = (af * d[th[p]]) * d[tv[p]];
+        fp32_pair_fma(d[th[p]], d[tv[p]], d[1], sh[p], sv[p], fx, fy, xc, yc, w[p],
+                      &mx[p], &my[p], &mz[p], &q[p]);
         if (q_degenerate(q[p]))
             return ORC_INVALID;
     }
@@ -675,8 +675,8 @@ static int fp32_pairs_code(const float d[6], int x, int y, float fx, float fy, f
         int fire = 0;
         if (mode == ORC_REL) {
             float tt = tau * tau;
-            float ww = w[p] * w[p];
-            float h = tt * ww;
+            float tw = tt * w[p];
+            float h = tw * w[p];
             fire = q[p] > h;
         } else if (mode == ORC_ABS) {
             fire = q[p] > kpair;
@@ -736,9 +736,9 @@ static int fp32_multiscale_code(float d1, const float *d2s, const float *d3s, in
     float Mx = 0.0f, My = 0.0f, Mz = 0.0f, Wt = 0.0f;
     for (int i = 1; i <= scales; ++i) {
         float a = (float)(i * alpha);
-        float mx, my, mz, w, q;
-        fp32_pair_fma(d2s[i - 1], d3s[i - 1], d1, 1, 1, fx, fy, xc, yc, a, &mx, &my, &mz, &w,
-                      &q);
+        float mx, my, mz, q;
+        float w = a * (d2s[i - 1] * d3s[i - 1]);
+        fp32_pair_fma(d2s[i - 1], d3s[i - 1], d1, 1, 1, fx, fy, xc, yc, w, &mx, &my, &mz, &q);
         if (i == 1) {
             Mx = a * mx;
             My = a * my;

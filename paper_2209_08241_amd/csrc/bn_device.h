@@ -253,27 +253,29 @@ __device__ __forceinline__ PixelOut eval_pixel(bool inside, float d1, float d2, 
 // four-pair m, taken in its closed form (d1 cancels exactly there, while the
 // rounded sum of the pairs can lose it to cancellation).
 // ---------------------------------------------------------------------------
-// The binary32 vector of one pair and its test:
-//   mx = fx A, my = fy B, w = alpha C,
+// The binary32 vector of one pair and its test, given w = (alpha d_h) d_v:
+//   mx = fx A, my = fy B,
 //   mz = fma(xc, A, fma(yc, B, w)),  q = fma(mx, mx, fma(my, my, mz mz)),
-// each fused multiply-add rounded once.
+// each fused multiply-add rounded once; the pair fails iff
+// q > fma(k1 w, w, k0) with (k1, k0) = (tau^2, 0) for REL, that is
+// q > (tau^2 w) w with both products rounded, and (0, K) otherwise (0 w is
+// a signed zero for every finite w, so the threshold is K; a w that is not
+// finite comes from a tap product that overflowed, whose q is not finite
+// either, and the pixel is INVALID whatever the test says).
 // keep: the pair passes; ok: its q is a finite number >= FLT_MIN.
 struct PairT {
     float mx, my, mz;
     bool keep, ok;
 };
 
-__device__ __forceinline__ PairT pair_t(float A, float B, float C, float xc, float yc,
-                                        const FrameArgs &f) {
+__device__ __forceinline__ PairT pair_t(float A, float B, float w, float xc, float yc, float k1,
+                                        float k0, const FrameArgs &f) {
     PairT r;
     r.mx = f.fx * A;
     r.my = f.fy * B;
-    const float w = f.af * C;
     r.mz = __builtin_fmaf(xc, A, __builtin_fmaf(yc, B, w));
     const float q = __builtin_fmaf(r.mx, r.mx, __builtin_fmaf(r.my, r.my, r.mz * r.mz));
-    const float ww = w * w;
-    const float hrel = f.tt * ww;
-    const float h = f.rel ? hrel : f.hconst;
+    const float h = __builtin_fmaf(k1 * w, w, k0);
     r.keep = !(q > h);
     r.ok = __builtin_amdgcn_classf(q, sconst(0x100));
     return r;
@@ -320,11 +322,15 @@ __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, floa
     const float e3 = d3 - d1;
     const float e4 = d4 - d1;
     const float e5 = d5 - d1;
+    const float k1 = f.rel ? f.tt : 0.0f;
+    const float k0 = f.rel ? 0.0f : f.hconst;
+    const float a2 = f.af * d2;
+    const float a4 = f.af * d4;
     // (h, v) = (2, 3), (4, 3), (4, 5), (2, 5); sh, sv = ++, -+, --, +-
-    const PairT p0 = pair_t(e2 * d3, d2 * e3, d2 * d3, xc, yc, f);
-    const PairT p1 = pair_t(-(e4 * d3), d4 * e3, d4 * d3, xc, yc, f);
-    const PairT p2 = pair_t(-(e4 * d5), -(d4 * e5), d4 * d5, xc, yc, f);
-    const PairT p3 = pair_t(e2 * d5, -(d2 * e5), d2 * d5, xc, yc, f);
+    const PairT p0 = pair_t(e2 * d3, d2 * e3, a2 * d3, xc, yc, k1, k0, f);
+    const PairT p1 = pair_t(-(e4 * d3), d4 * e3, a4 * d3, xc, yc, k1, k0, f);
+    const PairT p2 = pair_t(-(e4 * d5), -(d4 * e5), a4 * d5, xc, yc, k1, k0, f);
+    const PairT p3 = pair_t(e2 * d5, -(d2 * e5), a2 * d5, xc, yc, k1, k0, f);
     const bool all = p0.keep && p1.keep && p2.keep && p3.keep;
     const bool any = p0.keep || p1.keep || p2.keep || p3.keep;
     // all four pass: the four-pair closed form, in which d1 cancels exactly
