@@ -162,6 +162,109 @@ def pin_pairs_step_keeps_own_plane(o):
         assert (want_keep[inn] == 15).sum() > 0 and (want_keep[inn] == 0).sum() > 0
 
 
+def pin_pairs_rel_split_matches_fp64(o):
+    """The binary32 pair decisions agree with the FP64 decisions of the
+    definition wherever the FP64 decision is clear of the threshold.  On a
+    sphere each pair's rho = |n_p| / (n_p . ray) varies over the frame and
+    among the four pairs of a pixel; tau is put at the median four-pair rho,
+    so that many pairs fail and many pass, and a pair is clear when its FP64
+    decision is the same at tau (1 - 1e-4) and tau (1 + 1e-4) (binary32
+    rounding moves a rho by a few 1e-7).  Both sides see the same binary32
+    depths."""
+    H, W, a = 40, 48, 2
+    fx, fy, cx, cy = 70.0, 64.0, 22.5, 19.0
+    depth, _ = scenes.sphere_depth(H, W, fx, fy, cx, cy, (0.05, -0.04, 1.2), 0.55)
+    d32 = depth.astype(np.float32)
+    d64 = d32.astype(np.float64)
+    assert np.all(np.isfinite(d64))
+    inn = interior(H, W, a)
+    rho = o.variant_f64(d64, fx, fy, cx, cy, a, "rel", 1e6, method="four_pair",
+                        want_rho=True)["rho"]
+    tau = float(np.median(rho[inn]))
+
+    def keep64(t):
+        return o.variant_f64(d64, fx, fy, cx, cy, a, "rel", t, method=PR, want_keep=True)["keep"]
+
+    k64, lo, hi = keep64(tau), keep64(tau * (1 - 1e-4)), keep64(tau * (1 + 1e-4))
+    k32 = o.variant_f32(d32, fx, fy, cx, cy, a, "rel", tau, method=PR, want_keep=True)["keep"]
+    kept = failed = unclear = 0
+    for p in range(4):
+        b64, b32 = (k64[inn] >> p) & 1, (k32[inn] >> p) & 1
+        clear = ((lo[inn] >> p) & 1) == ((hi[inn] >> p) & 1)
+        assert np.array_equal(b32[clear], b64[clear]), f"pair {p}"
+        kept += int((b64[clear] == 1).sum())
+        failed += int((b64[clear] == 0).sum())
+        unclear += int((~clear).sum())
+    assert kept > 300 and failed > 300 and unclear < 20, (kept, failed, unclear)
+
+
+def _pair_normals_bruteforce(d, x, y, a, fx, fy, cx, cy):
+    """FP64 pair normals n_jk = (X_j - X_1) x (X_k - X_1) of Eq. 7 at pixel
+    (x, y), each X back-projected with its own pixel offset (Eqs. 8-9)."""
+    X = {}
+    for t, (dx, dy) in TAP_D.items():
+        xx, yy = x + a * dx, y + a * dy
+        z = float(d[yy, xx])
+        X[t] = np.array([(xx - cx) / fx * z, (yy - cy) / fy * z, z])
+    return [np.cross(X[j] - X[1], X[k] - X[1]) for j, k in PAIRS]
+
+
+def pin_pairs_overflow_of_kept_vector(o):
+    """Binary32 degeneracy (R10) on the vectors pair removal keeps: a pixel
+    is INVALID when a pair's |m_p|^2 or the |.|^2 of the kept vector (the
+    closed form when all four pass, else the sum of the passing pairs)
+    exceeds FLT_MAX, with m_p = -(fx fy / alpha) n_p.  A sphere scaled so
+    that these squared lengths straddle FLT_MAX, decided by brute force in
+    FP64 from the definition on the same binary32 depths: all pairs passing
+    (REL tau = 1e6), and about half failing (tau at the median pair rho, on
+    a larger scale); pixels whose decision sits within 1e-3 of the overflow
+    or 1e-4 of tau are skipped."""
+    H, W, a = 18, 22, 1
+    fx, fy, cx, cy = 40.0, 36.0, 10.5, 8.0
+    depth, _ = scenes.sphere_depth(H, W, fx, fy, cx, cy, (0.03, -0.02, 1.2), 0.55)
+    k = fx * fy / a
+    fmax = float(np.finfo(np.float32).max)
+    pix = [(x, y) for y in range(a, H - a) for x in range(a, W - a)]
+
+    def pairs(d, x, y):
+        ray = np.array([(x - cx) / fx, (y - cy) / fy, 1.0])
+        ns = _pair_normals_bruteforce(d, x, y, a, fx, fy, cx, cy)
+        return ns, [np.linalg.norm(n) / float(n @ ray) for n in ns]
+
+    rho_med = float(np.median([r for x, y in pix for r in pairs(depth, x, y)[1]]))
+    seen = {}
+    for tau in (1e6, rho_med):
+        # scale: the median |.|^2 of the kept vectors (of the sums of fewer than
+        # four pairs in the second pass) at FLT_MAX; it grows as depth^4
+        qk = []
+        for x, y in pix:
+            ns, rho = pairs(depth, x, y)
+            kept = [n for n, r in zip(ns, rho) if r <= tau]
+            if kept and (tau > 1e5 or len(kept) < 4):  # the second pass scales to the sums
+                qk.append((k * np.linalg.norm(np.sum(kept, axis=0))) ** 2)
+        d32 = (depth * (fmax / float(np.median(qk))) ** 0.25).astype(np.float32)
+        d64 = d32.astype(np.float64)
+        got = o.variant_f32(d32, fx, fy, cx, cy, a, "rel", tau, method=PR)["mask"]
+        for x, y in pix:
+            ns, rho = pairs(d64, x, y)
+            if min(abs(r / tau - 1.0) for r in rho) < 1e-4:
+                continue
+            kept = [n for n, r in zip(ns, rho) if r <= tau]
+            if not kept:
+                continue
+            vals = [(k * np.linalg.norm(n)) ** 2 for n in ns]
+            vals.append((k * np.linalg.norm(np.sum(kept, axis=0))) ** 2)
+            if min(abs(v / fmax - 1.0) for v in vals) < 1e-3:
+                continue
+            want = INVALID if max(vals) > fmax else VALID
+            assert got[y, x] == want, (tau, x, y, len(kept), [v / fmax for v in vals])
+            key = ("closed" if len(kept) == 4 else "sum", want)
+            seen[key] = seen.get(key, 0) + 1
+    for key, least in ((("closed", VALID), 40), (("closed", INVALID), 40), (("sum", VALID), 10),
+                       (("sum", INVALID), 10)):
+        assert seen.get(key, 0) >= least, seen
+
+
 def pin_pairs_fronto_thresholds(o):
     """Fronto plane at depth D: every pair vector is (0, 0, -alpha C) with
     C = D^2, so |m|^2 = (alpha C)^2 exactly and REL passes iff tau >= 1.
@@ -371,6 +474,8 @@ def pin_ms_symmetries(o):
 
 
 VARIANT_PINS = [
+    pin_pairs_rel_split_matches_fp64,
+    pin_pairs_overflow_of_kept_vector,
     pin_pairs_all_kept_is_eq7,
     pin_pairs_plane_exact_f64,
     pin_pairs_ray_component,

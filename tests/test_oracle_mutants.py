@@ -51,6 +51,18 @@ MUTANTS = {
                                 "    k = k * k;\n    return (float)k;\n}\n\nstatic float multiscale_abs")],
     "pair_definition_wrong_order": [("static const int PAIR_K[4] = {3, 4, 5, 2};",
                                      "static const int PAIR_K[4] = {3, 2, 5, 4};")],
+    # the fused binary32 pair sequence (methods 1 and 2)
+    "pair_mz_offsets_swapped": [("float z = fmaf(xc, A, fmaf(yc, B, w));",
+                                 "float z = fmaf(xc, B, fmaf(yc, A, w));")],
+    "pair_q_missing_my": [("*q = fmaf(x, x, fmaf(y, y, z * z));", "*q = fmaf(x, x, z * z);")],
+    "pair_w_wrong_tap": [("w[p] = (af * d[th[p]]) * d[tv[p]];", "w[p] = (af * d[th[p]]) * d[th[p]];")],
+    "pair_rel_threshold_not_squared": [("float h = tw * w[p];", "float h = tw;")],
+    "pair_sum_q_missing_z": [("float Q = fmaf(sx, sx, fmaf(sy, sy, sz * sz));",
+                              "float Q = fmaf(sx, sx, sy * sy);")],
+    "pair_closed_form_mz_sign": [("float cz = fmaf(xc, a, fmaf(yc, b, cw));",
+                                  "float cz = fmaf(xc, a, fmaf(yc, b, -cw));")],
+    "ms_q_missing_mz": [("float q = fmaf(Mx, Mx, fmaf(My, My, Mz * Mz));",
+                         "float q = fmaf(Mx, Mx, My * My);")],
     # multi-scale
     "ms_same_offset_every_scale": [("float a = (float)(i * alpha);", "float a = (float)alpha;")],
     "ms_unweighted_scales": [("Mx = a * mx;", "Mx = mx;"), ("My = a * my;", "My = my;"),
