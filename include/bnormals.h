@@ -42,8 +42,8 @@
  *               for all four pairs);
  *   BN_VALID    otherwise.
  *
- * The threshold test is decided in IEEE binary32, with this exact order of
- * operations (no fused multiply-add), on m = -(4 fx fy / alpha) n:
+ * The four-pair threshold test is decided in IEEE binary32, with this exact
+ * order of operations (no fused multiply-add), on m = -(4 fx fy / alpha) n:
  *     P=d2-d4  S=d2+d4  Q=d3-d5  T=d3+d5   a=T*P  b=S*Q  c=S*T
  *     mx=fx*a  my=fy*b  xc=(float)x-cx  yc=(float)y-cy
  *     t3=(xc*a)+(yc*b)  w=(float)alpha*c  mz=t3+w

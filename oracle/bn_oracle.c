@@ -10,7 +10,8 @@
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
  * (no FMA contraction and no reassociation, so every float expression below
- * rounds exactly once per written operation, in the written order).
+ * rounds exactly once per written operation, in the written order; the
+ * fused multiply-adds that methods 1 and 2 name are written as C99 fmaf).
  *
  * What it computes, per pixel p = (x, y) of an organized depth map d, x the
  * column and y the row:

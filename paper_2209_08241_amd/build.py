@@ -3,8 +3,9 @@
     python -m paper_2209_08241_amd.build
 
 Every kernel translation unit is compiled with contraction off (the
-boundary mask is specified as unfused binary32 operations) and with packed
-FP32 instructions disabled.
+boundary masks are specified as binary32 sequences: the four-pair one
+unfused, the fused multiply-adds of the other methods written out as such)
+and with packed FP32 instructions disabled.
 """
 from __future__ import annotations
 
