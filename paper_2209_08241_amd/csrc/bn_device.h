@@ -246,10 +246,10 @@ __device__ __forceinline__ PixelOut eval_pixel(bool inside, float d1, float d2, 
 // with, for horizontal tap h, vertical tap v and their directions sh, sv:
 //   A = sh (d_h - d1) d_v,  B = sv d_h (d_v - d1),  C = d_h d_v
 // (Eqs. 1-3 scaled for the pair (2, 3)).  Each pair is tested like the
-// four-pair vector, with w_p = alpha C, its third component and squared
-// length taken with fused multiply-adds; the passing pairs are summed in pair
-// order, each sum starting from +0 (adding +0 for a failing pair changes no
-// bit of the squared length).  When all four pass, the sum is the
+// four-pair vector, with w_p = (alpha d_h) d_v (alpha C), its third component
+// and squared length taken with fused multiply-adds; the passing pairs are
+// summed in pair order, each sum starting from +0 (adding +0 for a failing
+// pair changes no bit of the squared length).  When all four pass, the sum is the
 // four-pair m, taken in its closed form (d1 cancels exactly there, while the
 // rounded sum of the pairs can lose it to cancellation).
 // ---------------------------------------------------------------------------
@@ -257,8 +257,8 @@ __device__ __forceinline__ PixelOut eval_pixel(bool inside, float d1, float d2, 
 //   mx = fx A, my = fy B,
 //   mz = fma(xc, A, fma(yc, B, w)),  q = fma(mx, mx, fma(my, my, mz mz)),
 // each fused multiply-add rounded once; the pair fails iff
-// q > fma(k1 w, w, k0) with (k1, k0) = (tau^2, 0) for REL, that is
-// q > (tau^2 w) w with both products rounded, and (0, K) otherwise (0 w is
+// q > fma(rel_k w, w, abs_k) with (rel_k, abs_k) = (tau^2, 0) for REL, that
+// is q > (tau^2 w) w with both products rounded, and (0, K) otherwise (0 w is
 // a signed zero for every finite w, so the threshold is K; a w that is not
 // finite comes from a tap product that overflowed, whose q is not finite
 // either, and the pixel is INVALID whatever the test says).
@@ -268,14 +268,14 @@ struct PairT {
     bool keep, ok;
 };
 
-__device__ __forceinline__ PairT pair_t(float A, float B, float w, float xc, float yc, float k1,
-                                        float k0, const FrameArgs &f) {
+__device__ __forceinline__ PairT pair_t(float A, float B, float w, float xc, float yc,
+                                        float rel_k, float abs_k, const FrameArgs &f) {
     PairT r;
     r.mx = f.fx * A;
     r.my = f.fy * B;
     r.mz = __builtin_fmaf(xc, A, __builtin_fmaf(yc, B, w));
     const float q = __builtin_fmaf(r.mx, r.mx, __builtin_fmaf(r.my, r.my, r.mz * r.mz));
-    const float h = __builtin_fmaf(k1 * w, w, k0);
+    const float h = __builtin_fmaf(rel_k * w, w, abs_k);
     r.keep = !(q > h);
     r.ok = __builtin_amdgcn_classf(q, sconst(0x100));
     return r;
@@ -322,15 +322,15 @@ __device__ __forceinline__ PixelOut eval_pixel_pairs(bool inside, float d1, floa
     const float e3 = d3 - d1;
     const float e4 = d4 - d1;
     const float e5 = d5 - d1;
-    const float k1 = f.rel ? f.tt : 0.0f;
-    const float k0 = f.rel ? 0.0f : f.hconst;
+    const float rel_k = f.rel ? f.tt : 0.0f;
+    const float abs_k = f.rel ? 0.0f : f.hconst;
     const float a2 = f.af * d2;
     const float a4 = f.af * d4;
     // (h, v) = (2, 3), (4, 3), (4, 5), (2, 5); sh, sv = ++, -+, --, +-
-    const PairT p0 = pair_t(e2 * d3, d2 * e3, a2 * d3, xc, yc, k1, k0, f);
-    const PairT p1 = pair_t(-(e4 * d3), d4 * e3, a4 * d3, xc, yc, k1, k0, f);
-    const PairT p2 = pair_t(-(e4 * d5), -(d4 * e5), a4 * d5, xc, yc, k1, k0, f);
-    const PairT p3 = pair_t(e2 * d5, -(d2 * e5), a2 * d5, xc, yc, k1, k0, f);
+    const PairT p0 = pair_t(e2 * d3, d2 * e3, a2 * d3, xc, yc, rel_k, abs_k, f);
+    const PairT p1 = pair_t(-(e4 * d3), d4 * e3, a4 * d3, xc, yc, rel_k, abs_k, f);
+    const PairT p2 = pair_t(-(e4 * d5), -(d4 * e5), a4 * d5, xc, yc, rel_k, abs_k, f);
+    const PairT p3 = pair_t(e2 * d5, -(d2 * e5), a2 * d5, xc, yc, rel_k, abs_k, f);
     const bool all = p0.keep && p1.keep && p2.keep && p3.keep;
     const bool any = p0.keep || p1.keep || p2.keep || p3.keep;
     // all four pass: the four-pair closed form, in which d1 cancels exactly
