@@ -352,6 +352,58 @@ def achievable_rates(torch, bn, reps=5):
     return out
 
 
+def graph_ring_ms(torch, launch, n, passes=10):
+    """ms per call of launch(i, stream), i = 0..n-1, captured in one graph and
+    replayed `passes` times after one untimed replay."""
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for i in range(n):
+            launch(i, stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        for i in range(n):
+            launch(i, torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        graph.replay()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        for _ in range(passes):
+            graph.replay()
+        end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / (passes * n)
+
+
+def launch_breakdown(torch, bn, ring, kw):
+    """Per-launch times on the same graph-replayed ring: the launch floor (a
+    16-byte device copy), the estimator's traffic shape without arithmetic
+    or counts, and the estimator without its counts."""
+    dev = ring.depth[0].device
+    n = ring.ring
+    a16 = [torch.empty(4, device=dev) for _ in range(n)]
+    b16 = [torch.zeros(4, device=dev) for _ in range(n)]
+    s0 = ring.scs[0]
+    return {
+        "launch_floor_us": 1e3 * graph_ring_ms(
+            torch, lambda i, st: bn.stream_copy(a16[i], b16[i], stream=st), n),
+        "traffic_pattern_us": 1e3 * graph_ring_ms(
+            torch, lambda i, st: bn.stream_pattern(ring.depth[i], ring.normals[i], ring.masks[i],
+                                                   stream=st), n),
+        "without_counts_us": 1e3 * graph_ring_ms(
+            torch, lambda i, st: bn.estimate_normals(ring.depth[i], s0.fx, s0.fy, s0.cx, s0.cy,
+                                                     normals=ring.normals[i], mask=ring.masks[i],
+                                                     want_stats=False, stream=st, **kw), n),
+        "what": ("per launch, graph-replayed over the same ring: a 16-byte bn_stream_copy (the "
+                 "launch floor), bn_stream_pattern on the frame buffers (4 B in, 13 B out per "
+                 "pixel through the same LDS staging and stores, no arithmetic, no counts), the "
+                 "estimator without its counts; us_per_frame is the estimator with them"),
+    }
+
+
 def run_plain640(args, torch, bn, inputs):
     """The small plain configuration: 640x480, a ring of 256 buffers (1.6 GB,
     beyond the last-level cache), one launch per frame, the autotuner's tile
@@ -371,6 +423,9 @@ def run_plain640(args, torch, bn, inputs):
     ms640, steps640, warm640, _ = r640.time(kw640, 2560, 256)
     px640 = 640 * 480
     log(f"plain 640x480: {ms640 * 1e3:.2f} us per frame")
+    brk = launch_breakdown(torch, bn, r640, kw640)
+    log(f"plain 640x480 breakdown: floor {brk['launch_floor_us']:.2f} us, traffic pattern "
+        f"{brk['traffic_pattern_us']:.2f} us, without counts {brk['without_counts_us']:.2f} us")
     del r640
     name640 = dict(bn.variants())[v640]
     return {"workload": "plain 640x480, one launch per frame, ring of 256 buffers (8 distinct "
@@ -379,6 +434,7 @@ def run_plain640(args, torch, bn, inputs):
             "us_per_frame": ms640 * 1e3, "steps": steps640, "warmup": warm640,
             "variant": name640,
             "variant_from": from640,
+            "launch_breakdown": brk,
             "roofline": roofline(px640, ms640, load_traffic("plain640", px640,
                                                             variant=name640))}
 
@@ -835,7 +891,8 @@ def main():
                "config": {"workload": p["workload"], "frame": "640x480", "fx": 525.0,
                           "alpha": args.alpha, "mask": args.mode, "tau": args.tau,
                           "variant": p["variant"], "variant_from": p["variant_from"]},
-               "roofline": p["roofline"], "cpu_baseline": None}
+               "roofline": p["roofline"], "launch_breakdown": p["launch_breakdown"],
+               "cpu_baseline": None}
     elif args.workload == "batch":
         b = run_batch(args, torch, bn, inputs)
         out = {"metric": "normals Mpix/s (batched launch)", "value": b["value"],
