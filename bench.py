@@ -472,6 +472,11 @@ def run_plain(args, torch, bn, inputs):
                               "note": "one frame buffer relaunched: the 256 MB last-level "
                                       "cache holds it, not an HBM figure"}
         extra["single_launch_us"] = ring.single_launch_us(kw)
+        extra["launch_breakdown"] = launch_breakdown(torch, bn, ring, kw)
+        log("plain {}x{} breakdown: floor {:.2f} us, traffic pattern {:.2f} us, without counts "
+            "{:.2f} us".format(W, H, *(extra["launch_breakdown"][k] for k in
+                                       ("launch_floor_us", "traffic_pattern_us",
+                                        "without_counts_us"))))
         methods = []
         for name, alpha, K in (("pair_removal", args.alpha, 0), ("multiscale", 1, 3),
                                ("multiscale", 3, 3)):
@@ -941,8 +946,8 @@ def main():
             ach["batched_frac_of_pattern"] = (out["batched"]["roofline"]["achieved"]
                                               / ach["pattern_GBs"])
         line["achievable"] = ach
-    for k in ("alu_roofline", "batched", "serving", "differentiation", "methods", "hot_cache",
-              "plain640", "single_launch_us", "cpu_oracle_all_cores"):
+    for k in ("alu_roofline", "launch_breakdown", "batched", "serving", "differentiation",
+              "methods", "hot_cache", "plain640", "single_launch_us", "cpu_oracle_all_cores"):
         if k in out:
             line[k] = out[k]
     import multiprocessing
