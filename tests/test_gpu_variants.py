@@ -204,3 +204,48 @@ def test_counts_store_and_accumulate_flag(f640, method, K):
             plan.run()
         torch.cuda.synchronize()
         assert fr.stats[:3].cpu().tolist() == want
+
+
+def _median_rho_sphere(H, W, fx, fy, cx, cy, scale=1.0):
+    """A sphere filling the frame (binary32 depth, scaled), and the median
+    four-pair rho of its interior pixels: at that tau many pair and
+    multi-scale decisions sit near the threshold."""
+    depth, _ = scenes.sphere_depth(H, W, fx, fy, cx, cy, (0.05, -0.04, 1.2), 0.7)
+    assert np.all(np.isfinite(depth))
+    d32 = (depth * scale).astype(np.float32)
+    rho = oracle.variant_f64(d32.astype(np.float64), fx, fy, cx, cy, 2, "rel", 1e6,
+                             method="four_pair", want_rho=True)["rho"]
+    return d32, float(np.median(rho[2:H - 2, 2:W - 2]))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 5])
+@pytest.mark.parametrize("method,alpha,K", [(PR, 1, 0), (PR, 2, 0), (MS, 1, 3), (MS, 2, 2)])
+def test_fused_sequences_near_threshold(method, alpha, K, variant):
+    """The fused binary32 sequences of pair removal and multi-scale decide
+    exactly as the oracle's where many decisions sit near tau (a sphere with
+    tau at its median rho, and tau 1e-3 either side of it)."""
+    H, W, fx, fy, cx, cy = 96, 128, 140.0, 128.0, 63.5, 47.0
+    d, tau = _median_rho_sphere(H, W, fx, fy, cx, cy)
+    for t in (tau, tau * (1 - 1e-3), tau * (1 + 1e-3)):
+        log(f"near threshold {method} alpha={alpha} K={K} variant={variant} tau={t:.6g}")
+        v = variant if (method == PR or variant in (0, 1, 2)) else 0
+        check(d, fx, fy, cx, cy, alpha, "rel", t, method, K, v, what="near threshold")
+
+
+@pytest.mark.parametrize("method,alpha,K,scales", [(PR, 1, 0, (3e9, 4e9, 4.5e9, 7e9)),
+                                                   (MS, 1, 2, (3e9, 3.5e9))])
+def test_fused_sequences_at_overflow(method, alpha, K, scales):
+    """Depths scaled (|m|^2 grows as depth^4) so that the squared lengths of
+    the pairs and of the kept vectors straddle FLT_MAX: the INVALID pixels
+    (binary32 overflow) and the decisions beside them are the oracle's."""
+    H, W, fx, fy, cx, cy = 64, 80, 90.0, 84.0, 39.5, 31.0
+    d, tau = _median_rho_sphere(H, W, fx, fy, cx, cy)
+    for scale in scales:
+        ds = (d.astype(np.float64) * scale).astype(np.float32)
+        ref = oracle.variant_f32(ds, fx, fy, cx, cy, alpha, "rel", tau, method=method,
+                                 scales=K)
+        log(f"overflow {method} alpha={alpha} scale={scale:g} "
+            f"invalid={int((ref['mask'] == 2).sum())}")
+        n, m, st = run(ds, fx, fy, cx, cy, alpha, "rel", tau, method, K)
+        assert np.array_equal(m, ref["mask"]), f"masks differ at scale {scale:g}"
+        assert st[:3].tolist() == [int(c) for c in ref["counts"]]
